@@ -1,0 +1,164 @@
+"""Python view of the CPU oracle (test infrastructure only).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``libtsdf_oracle.so`` (plain C, see
+``tsdf_oracle.h``) with numpy arrays; it shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtsdf_oracle.so")
+_lib = None
+
+WEIGHTINGS = {"constant": 0, "linear_dropoff": 1}
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = C.CDLL(_LIB_PATH)
+    f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+    f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+    i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+    lib.ora_create.restype = C.c_void_p
+    lib.ora_create.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int]
+    lib.ora_destroy.argtypes = [C.c_void_p]
+    lib.ora_integrate_depth.restype = C.c_longlong
+    lib.ora_integrate_depth.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
+    lib.ora_num_blocks.restype = C.c_longlong
+    lib.ora_num_blocks.argtypes = [C.c_void_p]
+    lib.ora_blocks.argtypes = [C.c_void_p, i32p]
+    lib.ora_voxels.argtypes = [C.c_void_p, f64p, f64p]
+    lib.ora_find_block.restype = C.c_longlong
+    lib.ora_find_block.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.ora_touched.restype = C.c_longlong
+    lib.ora_touched.argtypes = [C.c_void_p, C.c_void_p]
+    lib.ora_last_scan.argtypes = [C.c_void_p, i32p, i32p]
+    lib.ora_camera_from_world.argtypes = [C.c_int, f32p, f64p, f64p]
+    lib.ora_dense_integrate.restype = C.c_longlong
+    lib.ora_dense_integrate.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
+                                        f32p, C.c_int, C.c_int, f32p, f32p, i32p, i32p, f64p, f64p]
+    _lib = lib
+    return lib
+
+
+def _f32(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if n is not None:
+        a = a.reshape(n)
+    return a
+
+
+class OracleMap:
+    """Sparse TSDF map integrated on the CPU in binary32 (``precision=32``,
+    the parity oracle) or binary64 (``precision=64``, the error oracle)."""
+
+    def __init__(self, voxel_size: float, truncation_vox: float, *, precision: int = 32,
+                 max_weight: float = 100.0, max_range: float = 5.0, weighting: str = "constant"):
+        lib = _load()
+        self.precision = precision
+        self.voxel_size = voxel_size
+        self._h = lib.ora_create(precision, voxel_size, truncation_vox, max_weight, max_range,
+                                 WEIGHTINGS[weighting])
+        if not self._h:
+            raise ValueError("invalid oracle map parameters")
+
+    @classmethod
+    def from_params(cls, params, precision: int = 32) -> "OracleMap":
+        return cls(params.voxel_size, params.truncation_vox, precision=precision,
+                   max_weight=params.max_weight, max_range=params.max_range,
+                   weighting=params.weighting)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.ora_destroy(h)
+            self._h = None
+
+    def integrate(self, depth: np.ndarray, K, T_world_cam) -> int:
+        depth = _f32(depth)
+        H, W = depth.shape
+        n = _lib.ora_integrate_depth(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16))
+        if n < 0:
+            raise ValueError("oracle rejected the frame")
+        return int(n)
+
+    def num_blocks(self) -> int:
+        return int(_lib.ora_num_blocks(self._h))
+
+    def blocks(self) -> np.ndarray:
+        out = np.empty((self.num_blocks(), 3), np.int32)
+        if out.size:
+            _lib.ora_blocks(self._h, out)
+        return out
+
+    def voxels(self) -> Tuple[np.ndarray, np.ndarray]:
+        n = self.num_blocks()
+        d = np.zeros((n, 512), np.float64)
+        w = np.zeros((n, 512), np.float64)
+        if n:
+            _lib.ora_voxels(self._h, d, w)
+        return d, w
+
+    def find(self, x: int, y: int, z: int) -> int:
+        return int(_lib.ora_find_block(self._h, x, y, z))
+
+    def touched(self) -> np.ndarray:
+        n = int(_lib.ora_touched(self._h, None))
+        out = np.empty((n, 3), np.int32)
+        if n:
+            _lib.ora_touched(self._h, out.ctypes.data_as(C.c_void_p))
+        return out
+
+    def last_scan(self) -> Tuple[np.ndarray, np.ndarray]:
+        lo = np.empty(3, np.int32)
+        hi = np.empty(3, np.int32)
+        _lib.ora_last_scan(self._h, lo, hi)
+        return lo, hi
+
+    def sorted_state(self):
+        """(blocks, dist, weight) sorted by block index (x, y, z)."""
+        b = self.blocks()
+        d, w = self.voxels()
+        order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
+        return b[order], d[order], w[order]
+
+
+def camera_from_world(T_world_cam, precision: int = 32):
+    lib = _load()
+    R = np.empty(9, np.float64)
+    t = np.empty(3, np.float64)
+    lib.ora_camera_from_world(precision, _f32(T_world_cam, 16), R, t)
+    return R.reshape(3, 3), t
+
+
+def dense_integrate(params, frames, K, poses, gmin, gdim, precision: int = 32):
+    """Brute force over a dense voxel box (no blocks, hash or candidates).
+    Returns (dist, weight) arrays shaped (gdim[2], gdim[1], gdim[0])."""
+    lib = _load()
+    gmin = np.ascontiguousarray(np.asarray(gmin, np.int32))
+    gdim = np.ascontiguousarray(np.asarray(gdim, np.int32))
+    n = int(np.prod(gdim.astype(np.int64)))
+    dist = np.zeros(n, np.float64)
+    weight = np.zeros(n, np.float64)
+    for depth, T in zip(frames, poses):
+        depth = _f32(depth)
+        H, W = depth.shape
+        r = lib.ora_dense_integrate(precision, params.voxel_size, params.truncation_vox,
+                                    params.max_weight, params.max_range,
+                                    WEIGHTINGS[params.weighting], depth, W, H, _f32(K, 4),
+                                    _f32(T, 16), gmin, gdim, dist, weight)
+        if r < 0:
+            raise ValueError("oracle rejected the frame")
+    shape = (int(gdim[2]), int(gdim[1]), int(gdim[0]))
+    return dist.reshape(shape), weight.reshape(shape)

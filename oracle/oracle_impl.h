@@ -1,0 +1,263 @@
+/*
+ * oracle_impl.h -- precision-generic body of the CPU oracle.
+ *
+ * TEST INFRASTRUCTURE ONLY (see tsdf_oracle.h).
+ *
+ * Included by tsdf_oracle.c once with REAL = float (suffix _f32) and once with
+ * REAL = double (suffix _f64).  Every arithmetic statement below is a single
+ * IEEE-754 operation in REAL, evaluated left to right as written; the file is
+ * compiled without contraction or fast-math so the binary32 instance performs
+ * exactly these roundings.
+ */
+
+#define FN_(a, b) a##b
+#define FN2(a, b) FN_(a, b)
+#define FN(name) FN2(name, SFX)
+
+/* Per-frame constants in REAL.  Paper §IV-B: T_CL is the inverse of the sensor
+ * pose T_LC (§III); epsilon is the truncation distance. */
+typedef struct {
+    REAL R[9];          /* camera-from-world rotation, row-major */
+    REAL t[3];          /* camera-from-world translation */
+    REAL fx, fy, cx, cy;
+    REAL width_r, height_r;
+    int width, height;
+    REAL vs;            /* voxel edge */
+    REAL eps;           /* truncation distance epsilon */
+    REAL delta;         /* start of the linear weight dropoff behind the surface */
+    REAL span_inv;      /* 1 / (epsilon - delta) */
+    REAL w_max, d_max;
+    int weighting;
+    const float *depth;
+} FN(frame);
+
+/* Frame set-up.  The inverse of a rigid pose is (R^T, -R^T t).  R^T is exact;
+ * each component of -R^T t is accumulated in binary64 from the binary32 pose,
+ * in the order ((R0i t0 + R1i t1) + R2i t2), and rounded once to REAL. */
+static void FN(frame_setup)(FN(frame) *f, const ora_params *p, const float *depth,
+                            int width, int height, const float K[4], const float T[16])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            f->R[3 * i + j] = (REAL)T[4 * j + i];
+    for (int i = 0; i < 3; ++i) {
+        double acc = ((double)T[0 * 4 + i] * (double)T[3] + (double)T[1 * 4 + i] * (double)T[7])
+                     + (double)T[2 * 4 + i] * (double)T[11];
+        f->t[i] = (REAL)(-acc);
+    }
+    f->fx = (REAL)K[0];
+    f->fy = (REAL)K[1];
+    f->cx = (REAL)K[2];
+    f->cy = (REAL)K[3];
+    f->width = width;
+    f->height = height;
+    f->width_r = (REAL)width;
+    f->height_r = (REAL)height;
+    f->vs = (REAL)p->voxel_size;
+    f->eps = (REAL)p->truncation_vox * f->vs;
+    /* Linear dropoff (the paper only says the weight may follow a sensor
+     * model): weight 1 down to one voxel behind the surface, then falling
+     * linearly to 0 at -epsilon. */
+    f->delta = f->vs;
+    f->span_inv = f->eps > f->delta ? (REAL)1 / (f->eps - f->delta) : (REAL)0;
+    f->w_max = (REAL)p->max_weight;
+    f->d_max = (REAL)p->max_range;
+    f->weighting = p->weighting;
+    f->depth = depth;
+}
+
+/* One voxel against one frame (§IV-B, Eq. (1)-(2) and the TSDF functor).
+ * g = global voxel index.  Returns 1 and the truncated distance *x and the
+ * measurement weight *wm when the voxel is updated; 0 when it is not. */
+static int FN(voxel_measure)(const FN(frame) *f, int32_t gx, int32_t gy, int32_t gz,
+                             REAL *x, REAL *wm)
+{
+    const REAL half = (REAL)0.5;
+    /* voxel centre p_L */
+    REAL px = ((REAL)gx + half) * f->vs;
+    REAL py = ((REAL)gy + half) * f->vs;
+    REAL pz = ((REAL)gz + half) * f->vs;
+    /* Eq. (1): p_C = T_CL p_L */
+    REAL xc = ((f->R[0] * px + f->R[1] * py) + f->R[2] * pz) + f->t[0];
+    REAL yc = ((f->R[3] * px + f->R[4] * py) + f->R[5] * pz) + f->t[1];
+    REAL zc = ((f->R[6] * px + f->R[7] * py) + f->R[8] * pz) + f->t[2];
+    if (!(zc > 0))
+        return 0;
+    /* Eq. (2), pinhole: u = fu x/z + cu, v = fv y/z + cv */
+    REAL r = (REAL)1 / zc;
+    REAL u = f->fx * (xc * r) + f->cx;
+    REAL v = f->fy * (yc * r) + f->cy;
+    /* nearest-neighbour sample: pixel (i, j) covers [i, i+1) x [j, j+1) */
+    if (!(u >= 0 && u < f->width_r && v >= 0 && v < f->height_r))
+        return 0;
+    int32_t i = (int32_t)u;
+    int32_t j = (int32_t)v;
+    REAL d = (REAL)f->depth[(size_t)j * (size_t)f->width + (size_t)i];
+    /* a measurement is valid iff 0 < d <= max range (NaN, Inf, <= 0 fail) */
+    if (!(d > 0 && d <= f->d_max))
+        return 0;
+    /* projective distance; voxel depth d_v is the camera-frame z for a depth image */
+    REAL dp = d - zc;
+    /* voxels more than epsilon behind the surface are skipped, not clamped */
+    if (!(dp >= -f->eps))
+        return 0;
+    REAL w = (REAL)1;
+    if (f->weighting == ORA_WEIGHT_LINEAR_DROPOFF && dp < -f->delta)
+        w = (f->eps + dp) * f->span_inv;
+    if (!(w > 0))
+        return 0;
+    *x = dp < f->eps ? dp : f->eps;
+    *wm = w;
+    return 1;
+}
+
+/* Weighted average with capped weight sum (§IV-B): the running distance is
+ * averaged with the uncapped weight sum; only the stored weight is capped. */
+static void FN(voxel_fuse)(REAL *D, REAL *W, REAL x, REAL wm, REAL w_max)
+{
+    REAL n = *D * *W + x * wm;
+    REAL s = *W + wm;
+    *D = n / s;
+    *W = s < w_max ? s : w_max;
+}
+
+/* Inclusive block box containing every voxel that can be updated by the
+ * frame: such a voxel has 0 < z_c <= d + epsilon <= zfar and projects inside
+ * the image, so it lies in the pyramid spanned by the camera centre and the
+ * four image corners at depth zfar.  The box of that pyramid is widened by one
+ * voxel on every side.  Returns 0 if the frame has no valid pixel. */
+static int FN(scan_box)(const FN(frame) *f, const float K[4], const float T[16],
+                        int32_t bmin[3], int32_t bmax[3])
+{
+    double zmax = -1.0;
+    for (size_t k = 0; k < (size_t)f->width * (size_t)f->height; ++k) {
+        float d = f->depth[k];
+        if (d > 0 && d <= (float)f->d_max && (double)d > zmax)
+            zmax = (double)d;
+    }
+    if (zmax <= 0)
+        return 0;
+    double zfar = zmax + (double)f->eps;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a)
+        lo[a] = hi[a] = (double)T[4 * a + 3];   /* camera centre */
+    for (int c = 0; c < 4; ++c) {
+        double u = (c & 1) ? (double)f->width : 0.0;
+        double v = (c & 2) ? (double)f->height : 0.0;
+        double pc[3] = {(u - K[2]) / K[0] * zfar, (v - K[3]) / K[1] * zfar, zfar};
+        for (int a = 0; a < 3; ++a) {
+            double w = (double)T[4 * a + 3];
+            for (int b = 0; b < 3; ++b)
+                w += (double)T[4 * a + b] * pc[b];
+            if (w < lo[a]) lo[a] = w;
+            if (w > hi[a]) hi[a] = w;
+        }
+    }
+    double edge = 8.0 * (double)f->vs;
+    for (int a = 0; a < 3; ++a) {
+        bmin[a] = (int32_t)floor((lo[a] - (double)f->vs) / edge);
+        bmax[a] = (int32_t)floor((hi[a] + (double)f->vs) / edge);
+    }
+    return 1;
+}
+
+static REAL *FN(dist_ptr)(ora_map *m) { return (REAL *)m->dist; }
+static REAL *FN(weight_ptr)(ora_map *m) { return (REAL *)m->weight; }
+
+/* One frame into the sparse map.  Every block of the scan box is evaluated
+ * voxel by voxel; a block that has at least one updated voxel is looked up or
+ * inserted in the block hash (§IV-A) and its updated voxels are fused. */
+static long long FN(integrate)(ora_map *m, const float *depth, int width, int height,
+                               const float K[4], const float T[16])
+{
+    FN(frame) f;
+    FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    m->n_touched = 0;
+    int32_t bmin[3], bmax[3];
+    if (!FN(scan_box)(&f, K, T, bmin, bmax)) {
+        for (int a = 0; a < 3; ++a) { m->scan_min[a] = 0; m->scan_max[a] = -1; }
+        return 0;
+    }
+    for (int a = 0; a < 3; ++a) { m->scan_min[a] = bmin[a]; m->scan_max[a] = bmax[a]; }
+    long long updates = 0;
+    REAL xs[512], ws[512];
+    unsigned char hit[512];
+    for (int32_t bz = bmin[2]; bz <= bmax[2]; ++bz)
+        for (int32_t by = bmin[1]; by <= bmax[1]; ++by)
+            for (int32_t bx = bmin[0]; bx <= bmax[0]; ++bx) {
+                int any = 0;
+                for (int lz = 0; lz < 8; ++lz)
+                    for (int ly = 0; ly < 8; ++ly)
+                        for (int lx = 0; lx < 8; ++lx) {
+                            int k = lx + 8 * ly + 64 * lz;
+                            hit[k] = (unsigned char)FN(voxel_measure)(
+                                &f, 8 * bx + lx, 8 * by + ly, 8 * bz + lz, &xs[k], &ws[k]);
+                            any |= hit[k];
+                        }
+                if (!any)
+                    continue;
+                long long b = map_find_or_insert(m, bx, by, bz);
+                if (b < 0)
+                    return -1;
+                if (touched_push(m, b) != 0)
+                    return -1;
+                REAL *D = FN(dist_ptr)(m) + 512 * b;
+                REAL *W = FN(weight_ptr)(m) + 512 * b;
+                for (int k = 0; k < 512; ++k)
+                    if (hit[k]) {
+                        FN(voxel_fuse)(&D[k], &W[k], xs[k], ws[k], f.w_max);
+                        ++updates;
+                    }
+            }
+    return updates;
+}
+
+static void FN(export_voxels)(const ora_map *m, double *dist, double *weight)
+{
+    const REAL *D = (const REAL *)m->dist;
+    const REAL *W = (const REAL *)m->weight;
+    for (long long k = 0; k < 512 * m->n_blocks; ++k) {
+        dist[k] = (double)D[k];
+        weight[k] = (double)W[k];
+    }
+}
+
+static long long FN(dense)(const ora_params *p, const float *depth, int width, int height,
+                           const float K[4], const float T[16],
+                           const int32_t gmin[3], const int32_t gdim[3],
+                           double *dist, double *weight)
+{
+    FN(frame) f;
+    FN(frame_setup)(&f, p, depth, width, height, K, T);
+    long long updates = 0;
+    size_t k = 0;
+    for (int32_t z = 0; z < gdim[2]; ++z)
+        for (int32_t y = 0; y < gdim[1]; ++y)
+            for (int32_t x = 0; x < gdim[0]; ++x, ++k) {
+                REAL xv, wv;
+                if (!FN(voxel_measure)(&f, gmin[0] + x, gmin[1] + y, gmin[2] + z, &xv, &wv))
+                    continue;
+                REAL D = (REAL)dist[k], W = (REAL)weight[k];
+                FN(voxel_fuse)(&D, &W, xv, wv, f.w_max);
+                dist[k] = (double)D;
+                weight[k] = (double)W;
+                ++updates;
+            }
+    return updates;
+}
+
+static void FN(camera_from_world)(const float T[16], double R[9], double t[3])
+{
+    ora_params p = {0};
+    p.voxel_size = 1.0f;
+    p.truncation_vox = 1.0f;
+    FN(frame) f;
+    float K[4] = {1, 1, 0, 0};
+    FN(frame_setup)(&f, &p, 0, 1, 1, K, T);
+    for (int k = 0; k < 9; ++k) R[k] = (double)f.R[k];
+    for (int k = 0; k < 3; ++k) t[k] = (double)f.t[k];
+}
+
+#undef FN
+#undef FN2
+#undef FN_

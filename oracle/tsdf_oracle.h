@@ -1,0 +1,87 @@
+/*
+ * tsdf_oracle.h -- CPU oracle for projective TSDF integration.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow reference that
+ * the test-suite, the smoke check and the benchmark's CPU-baseline leg compare
+ * the HIP library against.  The product library never includes, links or
+ * calls anything in this directory, and this directory includes nothing from
+ * the product.
+ *
+ * What it computes (nvblox paper, §IV-B "Frame Integration", Eq. (1)-(2) and
+ * the TSDF update functor that follows them):
+ *   for each depth frame (pose T_LC, pinhole intrinsics), every voxel centre
+ *   p_L is moved into the camera frame with T_CL = T_LC^{-1}, projected with
+ *   the pinhole model, the depth image is sampled at the nearest pixel, the
+ *   projective distance d_p = d - z is truncated, weighted, and folded into the
+ *   voxel by a weighted average whose weight sum is capped.
+ *   Blocks of 8x8x8 voxels are kept in a hash map (§IV-A) and a block exists
+ *   once any of its voxels has been updated.
+ *
+ * Every routine is compiled twice: in binary32 (the parity oracle: the same
+ * operations, in the same order, as the GPU library is required to perform)
+ * and in binary64 (the error oracle).  Selected by `precision` = 32 or 64.
+ *
+ * Readings of points the paper leaves open (pixel convention, which voxels are
+ * skipped behind the surface, the dropoff weight, the range limit, operation
+ * order) are listed in the repository's design notes and restated next to the
+ * code that implements them.
+ */
+#ifndef TSDF_ORACLE_H
+#define TSDF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_WEIGHT_CONSTANT = 0, ORA_WEIGHT_LINEAR_DROPOFF = 1 };
+
+typedef struct ora_map ora_map;
+
+/* A new empty map.  voxel_size in metres, truncation in voxels
+ * (epsilon = truncation_vox * voxel_size), max_weight caps the stored weight,
+ * max_range bounds valid measurements (0 < d <= max_range).
+ * Returns NULL on bad arguments or out of memory. */
+ora_map *ora_create(int precision, float voxel_size, float truncation_vox,
+                    float max_weight, float max_range, int weighting);
+void ora_destroy(ora_map *m);
+
+/* Integrates one depth frame (row-major float32, width x height, metres) seen
+ * from T_world_cam (row-major 4x4 float32) with K = {fx, fy, cx, cy}.
+ * Returns the number of voxel updates, or -1 on bad arguments / no memory. */
+long long ora_integrate_depth(ora_map *m, const float *depth, int width, int height,
+                              const float K[4], const float T_world_cam[16]);
+
+long long ora_num_blocks(const ora_map *m);
+/* Block indices (x, y, z), 3 int32 per block, in insertion order. */
+void ora_blocks(const ora_map *m, int32_t *xyz);
+/* Voxel distance and weight, 512 per block in insertion order, voxel
+ * (lx, ly, lz) at lx + 8 ly + 64 lz.  binary32 values widen exactly. */
+void ora_voxels(const ora_map *m, double *dist, double *weight);
+/* Insertion index of block (x, y, z), or -1. */
+long long ora_find_block(const ora_map *m, int32_t x, int32_t y, int32_t z);
+/* Blocks updated by the last integrated frame; returns their count and, if
+ * xyz is non-NULL, writes them (3 int32 each). */
+long long ora_touched(const ora_map *m, int32_t *xyz);
+/* Inclusive block-index box that the last frame scanned (its candidates). */
+void ora_last_scan(const ora_map *m, int32_t bmin[3], int32_t bmax[3]);
+
+/* Camera-from-world transform the oracle uses for Eq. (1), as doubles
+ * (binary32 values when precision == 32). */
+void ora_camera_from_world(int precision, const float T_world_cam[16], double R[9], double t[3]);
+
+/* Dense brute force over the voxel box [gmin, gmin + gdim): no blocks, no hash,
+ * no candidate set.  dist/weight (gdim[0]*gdim[1]*gdim[2] each, x fastest)
+ * carry the state in and out.  Returns the number of voxel updates. */
+long long ora_dense_integrate(int precision, float voxel_size, float truncation_vox,
+                              float max_weight, float max_range, int weighting,
+                              const float *depth, int width, int height,
+                              const float K[4], const float T_world_cam[16],
+                              const int32_t gmin[3], const int32_t gdim[3],
+                              double *dist, double *weight);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,488 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+* closed-form signed distances (fronto-parallel plane, sphere, box room),
+* invariants (weight = number of observing frames, bounds, monotone block set),
+* a dense brute force with no blocks, hash or candidate set,
+* a hand-derived worked example (tests/golden),
+* binary32 against binary64 within the rounding bound,
+* the rigid-pose inverse.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2311_00626_amd import synth
+from tests import geometry as geo
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def lookup(state, g, voxel_size=None):
+    """(dist, weight) of global voxel indices g (N, 3) in a sorted oracle state;
+    voxels of absent blocks read (0, 0).  Also returns a presence mask."""
+    blocks, dist, weight = state
+    b = np.floor_divide(g, 8)
+    l = g - 8 * b
+    li = l[:, 0] + 8 * l[:, 1] + 64 * l[:, 2]
+    key = lambda a: (a[:, 0].astype(np.int64) + (1 << 20)) * (1 << 42) + \
+        (a[:, 1].astype(np.int64) + (1 << 20)) * (1 << 21) + (a[:, 2].astype(np.int64) + (1 << 20))
+    bk = key(blocks)
+    order = np.argsort(bk)
+    bk_sorted = bk[order]
+    q = key(b)
+    pos = np.searchsorted(bk_sorted, q)
+    pos = np.minimum(pos, max(len(bk_sorted) - 1, 0))
+    present = (len(bk_sorted) > 0) & (bk_sorted[pos] == q) if len(bk_sorted) else np.zeros(len(q), bool)
+    idx = order[pos] if len(bk_sorted) else np.zeros(len(q), np.int64)
+    d = np.where(present, dist[idx, li] if len(bk_sorted) else 0.0, 0.0)
+    w = np.where(present, weight[idx, li] if len(bk_sorted) else 0.0, 0.0)
+    return d, w, present
+
+
+def box_voxels(lo, hi, vs):
+    """Global indices and centres of all voxels whose centres lie in [lo, hi]."""
+    glo = np.floor(np.asarray(lo) / vs).astype(np.int64) - 1
+    ghi = np.ceil(np.asarray(hi) / vs).astype(np.int64) + 1
+    ax = [np.arange(glo[a], ghi[a] + 1) for a in range(3)]
+    g = np.stack(np.meshgrid(*ax, indexing="ij"), axis=-1).reshape(-1, 3)
+    return g, (g.astype(np.float64) + 0.5) * float(np.float32(vs))
+
+
+def frustum_box(cam, T, zfar):
+    T = np.asarray(T, np.float64)
+    pts = [T[:3, 3]]
+    for u in (0.0, cam.width):
+        for v in (0.0, cam.height):
+            pc = np.array([(u - cam.cx) / cam.fx * zfar, (v - cam.cy) / cam.fy * zfar, zfar])
+            pts.append(T[:3, :3] @ pc + T[:3, 3])
+    pts = np.array(pts)
+    return pts.min(0), pts.max(0)
+
+
+CAM_ODD = synth.PinholeCamera(160, 120, 140.0, 150.0, 75.0, 62.0)   # fx != fy, off-centre
+
+
+def plane_pose(normal, pos, seed):
+    rng = np.random.default_rng(seed)
+    n = np.asarray(normal, np.float64)
+    n = n / np.linalg.norm(n)
+    h = rng.standard_normal(3)
+    return synth.pose_look_along(pos, n, h)
+
+
+# --------------------------------------------------------------------------
+# Fronto-parallel plane: projective distance equals the Euclidean distance
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_plane_single_frame_closed_form(oracle_mod, seed):
+    rng = np.random.default_rng(100 + seed)
+    normal = rng.standard_normal(3)
+    pos = rng.uniform(-3, 3, 3)
+    T = plane_pose(normal, pos, seed)
+    n = T[:3, 2].astype(np.float64)
+    n /= np.linalg.norm(n)
+    Z0 = 2.0
+    c = float(n @ T[:3, 3].astype(np.float64) + Z0)
+    scene = synth.Scene(planes=[(tuple(n), c)])
+    depth = synth.render_depth(scene, CAM_ODD, T)
+    assert np.all(np.abs(depth - Z0) < 1e-5)
+    params = synth.MapParams(0.05, 4.0, "constant")
+    eps = 4 * 0.05
+    m = oracle_mod.OracleMap.from_params(params)
+    m.integrate(depth, CAM_ODD.K, T)
+    state = m.sorted_state()
+
+    # every stored voxel: D = min(s, eps) with s the distance to the plane, W = 1
+    cen = geo.voxel_centres(state[0], 0.05)
+    s = geo.plane_sdf(cen, n, c)
+    upd = state[2] > 0
+    assert upd.sum() > 10000
+    assert np.all(state[2][upd] == 1.0)
+    err = np.abs(state[1][upd] - np.minimum(s[upd], eps))
+    assert err.max() < 2e-6, err.max()
+    assert np.all(state[1][~upd] == 0.0) and np.all(state[2][~upd] == 0.0)
+
+    # coverage: every voxel clearly inside the view and not beyond -eps is updated,
+    # every voxel clearly outside is not
+    lo, hi = frustum_box(CAM_ODD, T, Z0 + eps + 0.2)
+    g, p = box_voxels(lo, hi, 0.05)
+    pc = geo.world_to_camera(T, p)
+    marg = geo.frustum_margin(CAM_ODD, pc)
+    sd = geo.plane_sdf(p, n, c)
+    must = (marg > 1e-3) & (pc[:, 2] > 1e-3) & (sd > -eps + 1e-5)
+    must_not = (marg < -1e-3) | (sd < -eps - 1e-5)
+    _, w, _ = lookup(state, g)
+    assert must.sum() > 10000
+    assert np.all(w[must] == 1.0)
+    assert np.all(w[must_not] == 0.0)
+
+
+def test_plane_translated_frames_weight_counts(oracle_mod):
+    """Frames translated parallel to the plane leave D unchanged; W counts the
+    frames whose view contains the voxel (capped at max weight)."""
+    T0 = plane_pose([0.3, -0.2, 1.0], [0.1, 0.2, 0.3], 7)
+    n = T0[:3, 2].astype(np.float64)
+    n /= np.linalg.norm(n)
+    Z0 = 1.5
+    c = float(n @ T0[:3, 3].astype(np.float64) + Z0)
+    scene = synth.Scene(planes=[(tuple(n), c)])
+    params = synth.MapParams(0.04, 4.0, "constant")
+    eps = 4 * 0.04
+    m = oracle_mod.OracleMap.from_params(params)
+    poses = []
+    for k, (a, b) in enumerate([(0, 0), (0.3, 0), (0.3, 0.25), (-0.2, 0.1), (0.05, -0.3)]):
+        T = T0.copy()
+        T[:3, 3] = (T0[:3, 3].astype(np.float64) + a * T0[:3, 0] + b * T0[:3, 1]).astype(np.float32)
+        poses.append(T)
+        m.integrate(synth.render_depth(scene, CAM_ODD, T), CAM_ODD.K, T)
+    state = m.sorted_state()
+    lo, hi = frustum_box(CAM_ODD, poses[0], Z0 + eps + 0.5)
+    lo -= 0.6
+    hi += 0.6
+    g, p = box_voxels(lo, hi, 0.04)
+    sd = geo.plane_sdf(p, n, c)
+    count = np.zeros(len(g), np.int64)
+    ambiguous = np.abs(sd + eps) < 1e-5
+    for T in poses:
+        pc = geo.world_to_camera(T, p)
+        marg = geo.frustum_margin(CAM_ODD, pc)
+        ambiguous |= np.abs(marg) < 1e-3
+        count += (marg > 0) & (sd >= -eps)
+    d, w, _ = lookup(state, g)
+    ok = ~ambiguous
+    assert (count[ok] >= 2).sum() > 5000
+    assert np.array_equal(w[ok], np.minimum(count[ok], 100).astype(np.float64))
+    seen = ok & (count > 0)
+    assert np.abs(d[seen] - np.minimum(sd[seen], eps)).max() < 1e-5
+
+
+def test_weight_equals_frame_count_capped(oracle_mod):
+    """150 identical frames under constant weighting: every updated voxel ends
+    at the max weight 100 and keeps its single-frame distance."""
+    w = synth.box_room_single(0)
+    depth = w.frames()[0]
+    one = oracle_mod.OracleMap.from_params(w.params)
+    one.integrate(depth, w.camera.K, w.poses[0])
+    many = oracle_mod.OracleMap.from_params(w.params)
+    for _ in range(150):
+        many.integrate(depth, w.camera.K, w.poses[0])
+    b1, d1, w1 = one.sorted_state()
+    b2, d2, w2 = many.sorted_state()
+    assert np.array_equal(b1, b2)
+    assert np.array_equal(w2[w1 > 0], np.full((w1 > 0).sum(), 100.0))
+    assert np.all(w2[w1 == 0] == 0)
+    assert np.abs(d2 - d1).max() < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Sphere: near the surface the projective distance follows the Euclidean SDF
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("offset", [(0.0, 0.0), (0.35, -0.25), (-0.4, 0.3)])
+def test_sphere_surface_distance(oracle_mod, offset):
+    T = synth.pose_from_forward([0.2, -0.1, 1.3], math.radians(25), math.radians(-8), math.radians(12))
+    Tf = T.astype(np.float64)
+    r = 0.5
+    centre = Tf[:3, 3] + 2.2 * Tf[:3, 2] + offset[0] * Tf[:3, 0] + offset[1] * Tf[:3, 1]
+    scene = synth.Scene(spheres=[(tuple(centre), r)])
+    depth = synth.render_depth(scene, CAM_ODD, T)
+    vs = 0.02
+    params = synth.MapParams(vs, 4.0, "constant")
+    m = oracle_mod.OracleMap.from_params(params)
+    m.integrate(depth, CAM_ODD.K, T)
+    blocks, dist, weight = m.sorted_state()
+    cen = geo.voxel_centres(blocks, vs).reshape(-1, 3)
+    D = dist.reshape(-1)
+    W = weight.reshape(-1)
+    s = geo.sphere_sdf(cen, centre, r)
+    pc = geo.world_to_camera(T, cen)
+    o = Tf[:3, 3]
+    ray = cen - o
+    ray_n = ray / np.linalg.norm(ray, axis=1, keepdims=True)
+    cos_a = ray_n @ Tf[:3, 2]
+    nrm = (cen - centre) / np.linalg.norm(cen - centre, axis=1, keepdims=True)
+    cos_t = np.abs(np.sum(ray_n * nrm, axis=1))
+    marg = geo.frustum_margin(CAM_ODD, pc)
+    sel = (W > 0) & (np.abs(s) <= vs) & (cos_t > 0.5) & (marg > 2)
+    assert sel.sum() > 200
+    f = min(CAM_ODD.fx, CAM_ODD.fy)
+    tan_t = np.sqrt(np.maximum(1 - cos_t ** 2, 0)) / cos_t
+    along = np.abs(s) / cos_t
+    bound = (np.abs(s) * np.abs(cos_a / cos_t - 1)
+             + pc[:, 2] * (math.sqrt(2) / 2) / f * tan_t * 1.5
+             + along ** 2 * (1 - cos_t ** 2) / (2 * r)
+             + pc[:, 2] * (math.sqrt(2) / 2) / f * along / r)
+    err = np.abs(D - s)
+    assert np.all(err[sel] <= 2 * bound[sel] + 1e-5), (err[sel] / (2 * bound[sel] + 1e-5)).max()
+    # straight through the centre of the sphere's image the error is tiny
+    to_c = (centre - o) / np.linalg.norm(centre - o)
+    axis = sel & (np.linalg.norm(np.cross(ray_n, to_c), axis=1) < vs / np.linalg.norm(centre - o))
+    assert axis.sum() >= 1
+    assert err[axis].max() < 2e-3
+
+
+def test_box_room_walls(oracle_mod):
+    """Config-1 box room: away from edges, voxels near a wall carry the wall distance."""
+    w = synth.box_room_single(0)
+    depth = w.frames()[0]
+    m = oracle_mod.OracleMap.from_params(w.params)
+    m.integrate(depth, w.camera.K, w.poses[0])
+    blocks, dist, weight = m.sorted_state()
+    vs = w.params.voxel_size
+    cen = geo.voxel_centres(blocks, vs).reshape(-1, 3)
+    D, W = dist.reshape(-1), weight.reshape(-1)
+    s, wall, gap = geo.room_sdf(cen, w.scene.room)
+    T = w.poses[0].astype(np.float64)
+    ray = cen - T[:3, 3]
+    ray_n = ray / np.linalg.norm(ray, axis=1, keepdims=True)
+    cos_a = ray_n @ T[:3, 2]
+    cos_t = np.abs(np.sum(ray_n * geo.ROOM_NORMALS[wall], axis=1))
+    pc = geo.world_to_camera(T, cen)
+    marg = geo.frustum_margin(w.camera, pc)
+    sel = (W > 0) & (np.abs(s) <= vs) & (cos_t > 0.5) & (gap > 0.5) & (marg > 2)
+    assert sel.sum() > 200
+    f = w.camera.fx
+    tan_t = np.sqrt(np.maximum(1 - cos_t ** 2, 0)) / cos_t
+    bound = np.abs(s) * np.abs(cos_a / cos_t - 1) + pc[:, 2] * (math.sqrt(2) / 2) / f * tan_t * 1.5
+    err = np.abs(D - s)
+    assert np.all(err[sel] <= 2 * bound[sel] + 1e-5)
+    # all voxels well inside the room and in front of every wall by > eps are free space: D = eps
+    eps = 4 * vs
+    free = (W > 0) & (s > eps * 3) & (marg > 2)
+    assert free.sum() > 1000
+    assert np.all(D[free] == np.float32(eps))
+
+
+# --------------------------------------------------------------------------
+# Pixel convention: pixel (i, j) covers [i, i+1) x [j, j+1)
+# --------------------------------------------------------------------------
+def test_pixel_convention_step_image(oracle_mod):
+    """A depth image that steps from 1.0 m to 2.0 m at column k: a voxel whose
+    projection lies in [k-1, k) samples the near side."""
+    cam = synth.PinholeCamera(64, 48, 60.0, 60.0, 32.0, 24.0)
+    k = 40
+    depth = np.full((48, 64), 2.0, np.float32)
+    depth[:, :k] = 1.0
+    T = np.eye(4, dtype=np.float32)
+    params = synth.MapParams(0.01, 4.0, "constant")
+    m = oracle_mod.OracleMap.from_params(params)
+    m.integrate(depth, cam.K, T)
+    blocks, dist, weight = m.sorted_state()
+    cen = geo.voxel_centres(blocks, 0.01).reshape(-1, 3)
+    D, W = dist.reshape(-1), weight.reshape(-1)
+    u = cam.fx * cen[:, 0] / cen[:, 2] + cam.cx
+    v = cam.fy * cen[:, 1] / cen[:, 2] + cam.cy
+    inside_v = (v > 0.01) & (v < cam.height - 0.01)
+    near_side = inside_v & (u > k - 0.49) & (u < k - 0.01) & (cen[:, 2] < 0.95)
+    far_side = inside_v & (u > k + 0.01) & (u < k + 0.49) & (cen[:, 2] < 0.95)
+    assert near_side.sum() > 50 and far_side.sum() > 50
+    eps = 0.04
+    assert np.all(W[near_side] == 1)
+    assert np.abs(D[near_side] - np.minimum(1.0 - cen[near_side, 2], eps)).max() < 1e-6
+    assert np.abs(D[far_side] - np.minimum(2.0 - cen[far_side, 2], eps)).max() < 1e-6
+
+
+# --------------------------------------------------------------------------
+# Dense brute force: sparse blocks + hash + candidate box change nothing
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("weighting,noise", [("constant", False), ("linear_dropoff", True)])
+def test_sparse_equals_dense_bruteforce(oracle_mod, weighting, noise):
+    room = (4.0, 3.0, 2.5)
+    cam = synth.PinholeCamera(32, 24, 28.0, 28.0, 16.0, 12.0)
+    poses = synth.spline_trajectory(room, 8, np.random.default_rng(5), margin=0.6, speed=20.0)
+    scene = synth.Scene(room=room, spheres=[((2.0, 1.5, 1.0), 0.4)])
+    rng = np.random.default_rng(9)
+    frames = []
+    for T in poses:
+        d = synth.render_depth(scene, cam, T)
+        if noise:
+            d = synth.add_depth_noise(d, rng, dropout=0.1)
+        frames.append(d)
+    params = synth.MapParams(0.25, 3.0, weighting, max_weight=4.0, max_range=3.5)
+    m = oracle_mod.OracleMap.from_params(params)
+    for d, T in zip(frames, poses):
+        m.integrate(d, cam.K, T)
+    gmin = np.array([-28, -28, -28])
+    gdim = np.array([72, 68, 64])
+    Dd, Wd = oracle_mod.dense_integrate(params, frames, cam.K, poses, gmin, gdim)
+    zz, yy, xx = np.nonzero(Wd > 0)
+    assert len(xx) > 400
+    # nothing reaches the border of the dense box, so the box holds every update
+    assert xx.min() > 0 and yy.min() > 0 and zz.min() > 0
+    assert xx.max() < gdim[0] - 1 and yy.max() < gdim[1] - 1 and zz.max() < gdim[2] - 1
+    g = np.stack([xx, yy, zz], 1) + gmin
+    state = m.sorted_state()
+    d, w, present = lookup(state, g)
+    assert present.all()
+    assert np.array_equal(d, Dd[zz, yy, xx]) and np.array_equal(w, Wd[zz, yy, xx])
+    # every allocated block holds at least one updated voxel and nothing else is set
+    blocks, dist, weight = state
+    assert np.all((weight > 0).any(axis=1))
+    assert int((weight > 0).sum()) == len(xx)
+    assert np.all(dist[weight == 0] == 0)
+
+
+def test_touched_and_scan_box(oracle_mod):
+    """The touched list is exactly the set of blocks whose voxels changed in the
+    frame, and lies inside the scanned box."""
+    w = synth.box_room_sequence(0.05, n_frames=4)
+    frames = w.frames()
+    m = oracle_mod.OracleMap.from_params(w.params)
+    prev = None
+    for d, T in zip(frames, w.poses):
+        m.integrate(d, w.camera.K, T)
+        b, dist, weight = m.sorted_state()
+        touched = m.touched()
+        lo, hi = m.last_scan()
+        assert np.all(touched >= lo) and np.all(touched <= hi)
+        if prev is not None:
+            pb, pd, pw = prev
+            # blocks are never removed and weights never decrease
+            keys_prev = {tuple(x) for x in pb}
+            assert keys_prev <= {tuple(x) for x in b}
+            idx = {tuple(x): i for i, x in enumerate(b)}
+            sel = np.array([idx[tuple(x)] for x in pb])
+            changed = np.any((weight[sel] != pw) | (dist[sel] != pd), axis=1)
+            assert np.all(weight[sel] >= pw)
+            changed_set = {tuple(x) for x in pb[changed]}
+            new_set = {tuple(x) for x in b} - keys_prev
+            assert {tuple(x) for x in touched} >= changed_set | new_set
+        prev = (b, dist, weight)
+
+
+# --------------------------------------------------------------------------
+# Bounds
+# --------------------------------------------------------------------------
+def test_bounds_sequence(oracle_mod):
+    w = synth.box_room_sequence(0.05, n_frames=12)
+    frames = w.frames()
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff", max_weight=5.0)
+    m = oracle_mod.OracleMap.from_params(params)
+    for d, T in zip(frames, w.poses):
+        m.integrate(d, w.camera.K, T)
+    b, dist, weight = m.sorted_state()
+    eps = np.float32(4) * np.float32(0.05)
+    pos = weight > 0
+    assert np.all(dist[pos] >= -eps) and np.all(dist[pos] <= eps)
+    assert np.all(weight >= 0) and np.all(weight <= 5.0)
+    assert np.all(dist[~pos] == 0)
+
+
+# --------------------------------------------------------------------------
+# Hand-derived worked example
+# --------------------------------------------------------------------------
+def test_golden_dropoff_two_frames(oracle_mod):
+    with open(os.path.join(GOLDEN, "dropoff_two_frames.json")) as f:
+        spec = json.load(f)
+    params = synth.MapParams(spec["voxel_size"], spec["truncation_vox"], spec["weighting"])
+    T = np.eye(4, dtype=np.float32)
+    for case in spec["cases"]:
+        for prec in (32, 64):
+            m = oracle_mod.OracleMap.from_params(params, precision=prec)
+            for dval in case["frame_depths"]:
+                depth = np.full((spec["height"], spec["width"]), dval, np.float32)
+                m.integrate(depth, np.array(spec["K"], np.float32), T)
+            state = m.sorted_state()
+            for vx in case["voxels"]:
+                d, w, present = lookup(state, np.array([vx["g"]]))
+                assert present[0]
+                assert abs(d[0] - vx["dist_num"] / vx["dist_den"]) < 1e-6, (vx, d)
+                assert abs(w[0] - vx["weight_num"] / vx["weight_den"]) < 1e-6, (vx, w)
+
+
+# --------------------------------------------------------------------------
+# binary32 against binary64
+# --------------------------------------------------------------------------
+def test_fp32_matches_fp64_within_rounding(oracle_mod):
+    """binary32 and binary64 agree to 1e-5 m except where a pixel or band
+    decision flips, which happens only for voxels whose projection lies within
+    a hair of a pixel edge (or whose d_p lies at the truncation edge)."""
+    w = synth.box_room_sequence(0.05, n_frames=10)
+    frames = w.frames()
+    m32 = oracle_mod.OracleMap.from_params(w.params, precision=32)
+    m64 = oracle_mod.OracleMap.from_params(w.params, precision=64)
+    for d, T in zip(frames, w.poses):
+        m32.integrate(d, w.camera.K, T)
+        m64.integrate(d, w.camera.K, T)
+    b32, d32, w32 = m32.sorted_state()
+    b64, d64, w64 = m64.sorted_state()
+    k32 = {tuple(x): i for i, x in enumerate(b32)}
+    common = [(k32[tuple(x)], j) for j, x in enumerate(b64) if tuple(x) in k32]
+    assert len(common) >= 0.99 * max(len(b32), len(b64))
+    i32 = np.array([a for a, _ in common])
+    i64 = np.array([b for _, b in common])
+    D32, D64 = d32[i32].reshape(-1), d64[i64].reshape(-1)
+    W32, W64 = w32[i32].reshape(-1), w64[i64].reshape(-1)
+    both = (W32 > 0) | (W64 > 0)
+    bad = both & ((np.abs(D32 - D64) > 1e-5) | (np.abs(W32 - W64) > 1e-6))
+    assert bad.sum() <= 1e-3 * both.sum(), (bad.sum(), both.sum())
+    cen = geo.voxel_centres(b64[i64], 0.05).reshape(-1, 3)[bad]
+    eps = 0.2
+    explained = np.zeros(len(cen), bool)
+    for d, T in zip(frames, w.poses):
+        pc = geo.world_to_camera(T, cen)
+        u = w.camera.fx * pc[:, 0] / pc[:, 2] + w.camera.cx
+        v = w.camera.fy * pc[:, 1] / pc[:, 2] + w.camera.cy
+        edge = np.minimum(np.abs(u - np.round(u)), np.abs(v - np.round(v)))
+        explained |= edge < 1e-3
+        ok = (u >= 0) & (u < w.camera.width) & (v >= 0) & (v < w.camera.height) & (pc[:, 2] > 0)
+        i = np.clip(u.astype(np.int64), 0, w.camera.width - 1)
+        j = np.clip(v.astype(np.int64), 0, w.camera.height - 1)
+        dp = d[j, i].astype(np.float64) - pc[:, 2]
+        explained |= ok & (np.abs(dp + eps) < 1e-5)
+    assert np.all(explained)
+
+
+# --------------------------------------------------------------------------
+# Rigid pose inverse
+# --------------------------------------------------------------------------
+def test_pose_inverse(oracle_mod):
+    rng = np.random.default_rng(3)
+    for k in range(20):
+        T = synth.pose_from_forward(rng.uniform(-50, 50, 3), rng.uniform(-3, 3),
+                                    rng.uniform(-1.5, 1.5), rng.uniform(-3, 3))
+        R, t = oracle_mod.camera_from_world(T, 32)
+        Ti = np.eye(4)
+        Ti[:3, :3] = R
+        Ti[:3, 3] = t
+        assert np.abs(Ti @ T.astype(np.float64) - np.eye(4)).max() < 1e-5
+    # axis permutation with integer translation: exact
+    T = np.array([[0, 0, 1, 3], [-1, 0, 0, -2], [0, -1, 0, 5], [0, 0, 0, 1]], np.float32)
+    for prec in (32, 64):
+        R, t = oracle_mod.camera_from_world(T, prec)
+        Ti = np.eye(4)
+        Ti[:3, :3] = R
+        Ti[:3, 3] = t
+        assert np.array_equal(Ti @ T.astype(np.float64), np.eye(4))
+
+
+# --------------------------------------------------------------------------
+# Degenerate inputs
+# --------------------------------------------------------------------------
+def test_invalid_pixels_and_range(oracle_mod):
+    cam = synth.PinholeCamera(16, 12, 14.0, 14.0, 8.0, 6.0)
+    T = np.eye(4, dtype=np.float32)
+    params = synth.MapParams(0.1, 4.0, "constant", max_range=3.0)
+    for bad in (0.0, -1.0, np.nan, np.inf, -np.inf, 3.0001):
+        m = oracle_mod.OracleMap.from_params(params)
+        assert m.integrate(np.full((12, 16), bad, np.float32), cam.K, T) == 0
+        assert m.num_blocks() == 0
+    m = oracle_mod.OracleMap.from_params(params)
+    assert m.integrate(np.full((12, 16), 3.0, np.float32), cam.K, T) > 0   # d == max range is valid
+
+
+def test_rejects_bad_arguments(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.OracleMap(0.0, 4.0)
+    with pytest.raises(ValueError):
+        oracle_mod.OracleMap(0.05, -1.0)
+    m = oracle_mod.OracleMap(0.05, 4.0)
+    T = np.eye(4, dtype=np.float32)
+    with pytest.raises(ValueError):
+        m.integrate(np.ones((4, 4), np.float32), np.array([0, 1, 2, 2], np.float32), T)
+    T2 = T.copy()
+    T2[0, 3] = np.nan
+    with pytest.raises(ValueError):
+        m.integrate(np.ones((4, 4), np.float32), np.array([1, 1, 2, 2], np.float32), T2)
