@@ -1,0 +1,177 @@
+"""Throughput of projective TSDF integration on one MI355X.
+
+Workload: the 300-frame cluttered-room sequence (640x480 float32 depth, 8 x 6
+x 3 m room with 40 spheres and 20 boxes, spline path at 0.5 m/s and 30 fps,
+axial noise 0.0012 z^2 and 5 % dropped pixels; 4 cm voxels, truncation 4
+voxels, linear-dropoff weight, max range 5 m).  All frames are rendered and
+uploaded to HBM before timing.  One step = one integrate_depth call (all
+stages of the path: culling, allocation, projection, update, touched-block
+compaction) on the next frame of the sequence, into one running map.
+
+Prints one JSON line (rank 0) with voxel updates/s as the value, frames/s,
+the integration kernel's roofline (algorithmic bytes per launch over its mean
+HIP-event duration, against 8 TB/s) and the CPU oracle timed on a bounded
+sample of the same frames.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "integrate_depth_cluttered_room_pmc.json")
+KERNEL_SOURCES = ["paper_2311_00626_amd/csrc/integrate.hip", "paper_2311_00626_amd/csrc/tsdf_internal.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(updates: int, touched: int, new_blocks: int, pixels: int, frames: int) -> int:
+    """Bytes the method must move: one (distance, weight) read and write per
+    voxel update (16 B), one read of every depth pixel per frame (4 B), a hash
+    key and value read per touched block (12 B) plus its touched-list entry
+    (4 B), and a key, value and slot key per new block (20 B)."""
+    return 16 * updates + 4 * pixels * frames + 16 * touched + 20 * new_blocks
+
+
+def measured_traffic(launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        with open(PMC_SUMMARY) as f:
+            s = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if s.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return s.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, frames_host, budget_s: float):
+    import oracle
+    om = oracle.OracleMap.from_params(w.params)
+    updates, n, t0 = 0, 0, time.perf_counter()
+    for d, T in zip(frames_host, w.poses):
+        updates += om.integrate(d, w.camera.K, T)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "voxel updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} frames of the 300-frame sequence, binary32 oracle, one thread, "
+                      f"{dt:.1f} s, {n / dt:.1f} frames/s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=290)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (PMC scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path shards by space with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2311_00626_amd import synth
+    from paper_2311_00626_amd.tsdf import TsdfMap
+
+    dev = torch.device("cuda:0")
+    w = synth.cluttered_room_sequence(300)
+    t0 = time.perf_counter()
+    frames_host = w.frames(device="cuda")
+    log(f"rendered {len(frames_host)} frames in {time.perf_counter() - t0:.1f} s")
+    frames = torch.stack([torch.as_tensor(f) for f in frames_host]).to(dev).contiguous()
+    n_frames = frames.shape[0]
+    H, W = frames.shape[1], frames.shape[2]
+    K = w.camera.K
+    poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
+
+    m = TsdfMap.from_params(w.params, block_capacity=1 << 16)
+    for k in range(args.warmup):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    torch.cuda.synchronize()
+    b0, u0, t_0 = m.counters()
+    m.profile(True)
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+
+    kernel_ms, launches = m.profile_read()
+    m.profile(False)
+    b1, u1, t_1 = m.counters()
+    assert m.status() == 0, "map overflowed"
+    elapsed = t_end - t_start
+    updates = u1 - u0
+    touched = t_1 - t_0
+    new_blocks = b1 - b0
+    alg = algorithmic_bytes(updates, touched, new_blocks, H * W, args.steps)
+    alg_per_launch = alg / args.steps
+    mean_kernel_s = kernel_ms / 1e3 / max(launches, 1)
+    achieved = alg_per_launch / mean_kernel_s / 1e9
+
+    if args.copy_calibration_mib > 0:
+        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    result = {
+        "metric": "voxel updates/s (frames/s and achieved HBM GB/s alongside)",
+        "value": updates / elapsed,
+        "unit": "voxel updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "frames_per_s": args.steps / elapsed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded ray-cast room, rendered on device before timing)",
+        "config": {"workload": w.name, "frames": n_frames, "width": W, "height": H,
+                   "voxel_size_m": w.params.voxel_size, "truncation_vox": w.params.truncation_vox,
+                   "weighting": w.params.weighting, "max_range_m": w.params.max_range,
+                   "parallelism": "single GPU"},
+        "voxel_updates": updates,
+        "touched_blocks": touched,
+        "new_blocks": new_blocks,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(alg_per_launch),
+                     "kernel": "integrate_depth_kernel", "kernel_ms_mean": mean_kernel_s * 1e3,
+                     "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches},
+    }
+    if not args.skip_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, frames_host, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

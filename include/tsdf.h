@@ -1,0 +1,156 @@
+/*
+ * tsdf.h -- C ABI of the MI355X (gfx950) projective-TSDF integration library.
+ *
+ * The library implements the surface-reconstruction hot path of the nvblox
+ * paper (Millane et al., "nvblox: GPU-Accelerated Incremental Signed Distance
+ * Field Mapping"): a block-sparse TSDF layer (§IV-A: a GPU hash table from
+ * integer block index to 8x8x8-voxel blocks stored contiguously) into which
+ * depth frames are fused by projective integration (§IV-B: find the blocks in
+ * view, allocate the missing ones, project every voxel into the depth image,
+ * Eq. (1)-(2), and apply the truncated weighted-average TSDF update).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Frames.  T_world_cam is the sensor pose T_LC of §III: a row-major 4x4
+ *   float32 rigid transform taking camera coordinates to world (layer)
+ *   coordinates.  Camera frame: x right, y down, z forward.  A depth image
+ *   stores camera-frame z in metres.
+ * Voxels.  Voxel (gx, gy, gz) has its centre at ((g + 0.5) * voxel_size).
+ *   Block (bx, by, bz) holds voxels 8b .. 8b+7 on each axis; inside a block
+ *   voxel (lx, ly, lz) is stored at index lx + 8 ly + 64 lz.
+ *   Block indices must stay within [-(2^20 - 1), 2^20 - 1] on every axis.
+ * Pixels.  Pixel (i, j) covers [i, i+1) x [j, j+1); the depth image is
+ *   row-major, height rows of width float32 values.  A pixel is a valid
+ *   measurement iff 0 < d <= max_range; anything else (0, negative, NaN, Inf,
+ *   beyond range) is skipped and is not an error.
+ * Memory.  Pointers named *_dev are device pointers on the map's GPU; all
+ *   other pointers are host memory, read or written during the call only.
+ *   The map owns all of its device memory.  Device buffers passed in stay
+ *   owned by the caller and must stay alive until the stream has passed the
+ *   call.
+ * Streams.  hip_stream is a hipStream_t (NULL = the default stream).  Calls
+ *   that only enqueue GPU work return before it has run.  A map is not
+ *   thread-safe: calls on one map must be ordered on one stream.
+ * Errors.  Every function returns TSDF_OK (0) or a negative status; no
+ *   exception crosses the ABI.  Device-side overflow (block pool, hash table,
+ *   touched list) sets a sticky error word on the device that map_status()
+ *   and the synchronising queries report as TSDF_EFULL; once observed, the
+ *   map rejects further integration with TSDF_ESTATE.
+ */
+#ifndef TSDF_H
+#define TSDF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define TSDF_API __attribute__((visibility("default")))
+#else
+#define TSDF_API
+#endif
+
+#define TSDF_OK 0
+#define TSDF_EINVAL (-1)   /* bad argument: NULL pointer, size <= 0, non-finite or non-rigid pose, ... */
+#define TSDF_ENOMEM (-2)   /* device allocation failed */
+#define TSDF_EFULL (-3)    /* block pool, hash table or touched list overflowed (sticky) */
+#define TSDF_EDEVICE (-4)  /* a HIP runtime call failed */
+#define TSDF_ESTATE (-5)   /* the map is in a sticky error state */
+
+#define TSDF_WEIGHT_CONSTANT 0        /* f_w(d_p) = 1 */
+#define TSDF_WEIGHT_LINEAR_DROPOFF 1  /* 1 for d_p >= -voxel_size, then linear to 0 at -epsilon */
+
+typedef struct tsdf_map tsdf_map;
+
+typedef struct {
+    float voxel_size_m;        /* voxel edge, metres, > 0 */
+    float truncation_vox;      /* truncation distance epsilon in voxels, > 0 (epsilon = truncation_vox * voxel_size_m) */
+    float max_weight;          /* cap on the stored weight, > 0 */
+    float max_range_m;         /* measurements d > max_range_m are invalid, > 0 */
+    int weighting;             /* TSDF_WEIGHT_* */
+    int reserved0;             /* must be 0 */
+    long long block_capacity;  /* number of 8^3-voxel blocks the pool holds (4 KiB each), >= 1 */
+    long long hash_capacity;   /* hash slots; 0 = smallest power of two >= 2 * block_capacity */
+} tsdf_params;
+
+/* Fills *p with the defaults: max_weight 100, max_range 5 m, constant weight,
+ * 2^18 blocks (1 GiB of voxels), automatic hash size. */
+TSDF_API void tsdf_default_params(tsdf_params *p, float voxel_size_m, float truncation_vox);
+
+/* Creates an empty map on the current HIP device (§IV-A).  create_map uses
+ * the defaults above.  *out receives the handle; on failure *out is NULL and
+ * the status is TSDF_EINVAL (bad parameters), TSDF_ENOMEM or TSDF_EDEVICE.
+ * Synchronises the device once (initial clears). */
+TSDF_API int create_map(float voxel_size_m, float truncation_vox, tsdf_map **out);
+TSDF_API int create_map_ex(const tsdf_params *p, tsdf_map **out);
+
+/* Frees the map and all its device memory after the device is idle.  NULL is
+ * accepted (TSDF_OK). */
+TSDF_API int destroy_map(tsdf_map *m);
+
+/* Fuses one depth frame into the map (§IV-B, Eq. (1)-(2) and the TSDF update
+ * functor):
+ *   for every voxel v with centre p: p_C = T_CL p (T_CL = T_world_cam^{-1});
+ *   if z > 0 and (u, v) = (fx x/z + cx, fy y/z + cy) falls in the image, the
+ *   nearest pixel's depth d is valid, d_p = d - z >= -epsilon and the weight
+ *   w = f_w(d_p) > 0, then with x = min(d_p, epsilon):
+ *     D <- (D W + x w) / (W + w),   W <- min(W + w, max_weight).
+ *   A block is allocated (zero distance, zero weight) the first time any of
+ *   its voxels is updated; the blocks updated by this frame form the touched
+ *   list (query_touched).
+ * depth_dev: device float32[height][width].  K: host {fx, fy, cx, cy} with
+ * fx, fy > 0.  T_world_cam: host row-major 4x4; its bottom row must be
+ * (0 0 0 1) within 1e-6 and its rotation orthonormal within 1e-4.
+ * Only enqueues work on hip_stream (no host synchronisation).
+ * Errors: TSDF_EINVAL, TSDF_ESTATE, TSDF_EDEVICE. */
+TSDF_API int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height,
+                    const float K[4], const float T_world_cam[16], void *hip_stream);
+
+/* Writes the indices of all allocated blocks, sorted ascending by (x, y, z),
+ * as int32 triples to out_xyz_dev (room for `capacity` blocks; min(count,
+ * capacity) are written) and the total count to *out_count (host).
+ * Synchronises hip_stream.  (§IV-A: the set of allocated blocks.) */
+TSDF_API int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
+                 void *hip_stream);
+
+/* Gathers the voxels of n_blocks blocks (int32 triples at blocks_xyz_dev):
+ * out_dist_dev and out_weight_dev receive 512 float32 each per block in
+ * voxel order lx + 8 ly + 64 lz, zeros for blocks that are not allocated.
+ * Only enqueues work. */
+TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks,
+               float *out_dist_dev, float *out_weight_dev, void *hip_stream);
+
+/* Blocks with at least one voxel updated by the most recent integrate_depth
+ * call (the "updated blocks" that downstream layers consume, §IV-C), in
+ * unspecified order, as int32 triples; same capacity / count contract as
+ * query_blocks.  Synchronises hip_stream. */
+TSDF_API int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
+                  void *hip_stream);
+
+/* Number of allocated blocks, the running total of voxel updates (one per
+ * voxel per frame in which it was updated) and the running total of touched
+ * blocks (one per block per frame in which any of its voxels was updated).
+ * Synchronises hip_stream. */
+TSDF_API int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates,
+                       long long *n_touched_blocks, void *hip_stream);
+
+/* Sticky device-side status: TSDF_OK or TSDF_EFULL.  Synchronises the device. */
+TSDF_API int map_status(tsdf_map *m);
+
+/* Static description of a status code (never NULL). */
+TSDF_API const char *tsdf_strerror(int status);
+
+/* Kernel timing.  While enabled, every integrate_depth call records a pair of
+ * HIP events on its stream around its integration kernel.  tsdf_profile_read
+ * synchronises those events and returns the summed kernel time in
+ * milliseconds and the number of timed launches since the last enable; it
+ * then clears them.  At most 65536 launches are kept. */
+TSDF_API int tsdf_profile(tsdf_map *m, int enable);
+TSDF_API int tsdf_profile_read(tsdf_map *m, double *total_ms, long long *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSDF_H */

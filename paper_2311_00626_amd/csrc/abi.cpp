@@ -1,0 +1,508 @@
+// Host side of the C ABI declared in include/tsdf.h: argument validation,
+// the per-frame constants (pose inverse, truncation constants, block lattice),
+// map memory management and kernel launches.  No exception leaves this file.
+#include "tsdf.h"
+#include "tsdf_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace tsdf;
+
+struct tsdf_map {
+    tsdf_params p;
+    int device;
+    DeviceMap dm;
+    int sticky;                           // host copy of an observed device error (TSDF_EFULL) or 0
+    float eps, delta, span_inv;           // per-map constants in binary32
+    int max_groups;                       // cap on integration workgroups per launch
+    // kernel timing
+    bool profiling;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    size_t ev_used;
+};
+
+namespace {
+
+constexpr long long kDefaultBlocks = 1ll << 18;
+constexpr size_t kMaxTimedLaunches = 65536;
+
+bool finite_all(const float *v, int n)
+{
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(v[k]))
+            return false;
+    return true;
+}
+
+bool params_valid(const tsdf_params *p)
+{
+    if (!p)
+        return false;
+    if (!(p->voxel_size_m > 0 && std::isfinite(p->voxel_size_m)))
+        return false;
+    if (!(p->truncation_vox > 0 && std::isfinite(p->truncation_vox)))
+        return false;
+    if (!(p->max_weight > 0 && std::isfinite(p->max_weight)))
+        return false;
+    if (!(p->max_range_m > 0 && std::isfinite(p->max_range_m)))
+        return false;
+    if (p->weighting != TSDF_WEIGHT_CONSTANT && p->weighting != TSDF_WEIGHT_LINEAR_DROPOFF)
+        return false;
+    if (p->reserved0 != 0)
+        return false;
+    if (p->block_capacity < 1 || p->block_capacity > (1ll << 30))
+        return false;
+    if (p->hash_capacity < 0 || p->hash_capacity > (1ll << 31))
+        return false;
+    if (p->hash_capacity != 0 && (p->hash_capacity & (p->hash_capacity - 1)) != 0)
+        return false;
+    if (p->hash_capacity != 0 && p->hash_capacity < p->block_capacity)
+        return false;
+    return true;
+}
+
+// Rigid-pose check: bottom row (0 0 0 1) within 1e-6, R^T R = I within 1e-4.
+bool pose_valid(const float *T)
+{
+    if (!finite_all(T, 16))
+        return false;
+    if (std::fabs(T[12]) > 1e-6f || std::fabs(T[13]) > 1e-6f || std::fabs(T[14]) > 1e-6f ||
+        std::fabs(T[15] - 1.0f) > 1e-6f)
+        return false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k)
+                s += (double)T[4 * k + a] * (double)T[4 * k + b];
+            if (std::fabs(s - (a == b ? 1.0 : 0.0)) > 1e-4)
+                return false;
+        }
+    return true;
+}
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess)
+        return TSDF_OK;
+    if (e == hipErrorOutOfMemory)
+        return TSDF_ENOMEM;
+    return TSDF_EDEVICE;
+}
+
+void free_device(tsdf_map *m)
+{
+    DeviceMap &d = m->dm;
+    (void)hipFree(d.keys);
+    (void)hipFree(d.vals);
+    (void)hipFree(d.pool);
+    (void)hipFree(d.slot_keys);
+    (void)hipFree(d.touched);
+    (void)hipFree(d.counters);
+    (void)hipFree(d.totals);
+    d = DeviceMap{};
+}
+
+void free_events(tsdf_map *m)
+{
+    for (hipEvent_t e : m->ev_start)
+        (void)hipEventDestroy(e);
+    for (hipEvent_t e : m->ev_stop)
+        (void)hipEventDestroy(e);
+    m->ev_start.clear();
+    m->ev_stop.clear();
+    m->ev_used = 0;
+}
+
+// Per-frame constants (the a1 step): camera-from-world pose, intrinsics,
+// truncation constants, and the block lattice that can hold updated voxels.
+int frame_args(const tsdf_map *m, int width, int height, const float K[4], const float T[16], FrameArgs &fa)
+{
+    // Inverse of the rigid pose: R^T exactly; each component of -R^T t is
+    // accumulated in binary64 as ((R0i t0 + R1i t1) + R2i t2) and rounded once.
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            fa.R[3 * i + j] = T[4 * j + i];
+    for (int i = 0; i < 3; ++i) {
+        const double acc = ((double)T[0 * 4 + i] * (double)T[3] + (double)T[1 * 4 + i] * (double)T[7]) +
+                           (double)T[2 * 4 + i] * (double)T[11];
+        fa.t[i] = (float)(-acc);
+    }
+    fa.fx = K[0];
+    fa.fy = K[1];
+    fa.cx = K[2];
+    fa.cy = K[3];
+    fa.width = width;
+    fa.height = height;
+    fa.width_f = (float)width;
+    fa.height_f = (float)height;
+    fa.vs = m->p.voxel_size_m;
+    fa.eps = m->eps;
+    fa.delta = m->delta;
+    fa.span_inv = m->span_inv;
+    fa.w_max = m->p.max_weight;
+    fa.d_max = m->p.max_range_m;
+
+    // An updated voxel has 0 < z <= d + eps <= max_range + eps and projects
+    // into the image: it lies in the pyramid of the camera centre and the
+    // image corners at that depth.  Its box, widened by a voxel, bounds the
+    // lattice.
+    const double vs = (double)m->p.voxel_size_m;
+    const double zfar = (double)m->p.max_range_m + (double)m->eps;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a)
+        lo[a] = hi[a] = (double)T[4 * a + 3];
+    for (int c = 0; c < 4; ++c) {
+        const double u = (c & 1) ? (double)width : 0.0;
+        const double v = (c & 2) ? (double)height : 0.0;
+        const double pc[3] = {(u - K[2]) / K[0] * zfar, (v - K[3]) / K[1] * zfar, zfar};
+        for (int a = 0; a < 3; ++a) {
+            double w = (double)T[4 * a + 3];
+            for (int b = 0; b < 3; ++b)
+                w += (double)T[4 * a + b] * pc[b];
+            lo[a] = std::min(lo[a], w);
+            hi[a] = std::max(hi[a], w);
+        }
+    }
+    const double edge = 8.0 * vs;
+    double extent = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double bl = std::floor((lo[a] - vs) / edge);
+        const double bh = std::floor((hi[a] + vs) / edge);
+        if (!(bl >= -kBlockCoordMax && bh <= kBlockCoordMax))
+            return TSDF_EINVAL;
+        fa.lat_min[a] = (int)bl;
+        fa.lat_dim[a] = (int)(bh - bl) + 1;
+        extent = std::max(extent, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+    }
+    fa.n_lat = (long long)fa.lat_dim[0] * fa.lat_dim[1] * fa.lat_dim[2];
+    if (fa.n_lat >= (1ll << 31))
+        return TSDF_EINVAL;
+    fa.zfar = (float)zfar;
+    // Culling slack: half a voxel plus a generous bound on binary32 rounding
+    // of coordinates of magnitude `extent`, scaled into each plane's units.
+    const double e = 0.5 * vs + 1e-5 * (1.0 + extent + zfar);
+    fa.margin_u = (float)(e * ((double)K[0] + std::fabs((double)K[2]) + (double)width));
+    fa.margin_v = (float)(e * ((double)K[1] + std::fabs((double)K[3]) + (double)height));
+    fa.margin_z = (float)e;
+    return TSDF_OK;
+}
+
+int read_counters(tsdf_map *m, uint32_t *c, unsigned long long *totals, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(c, m->dm.counters, sizeof(uint32_t) * kNumCounters, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && totals)
+        e = hipMemcpyAsync(totals, m->dm.totals, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (c[kErrorBits] != 0)
+        m->sticky = TSDF_EFULL;
+    return TSDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tsdf_default_params(tsdf_params *p, float voxel_size_m, float truncation_vox)
+{
+    if (!p)
+        return;
+    std::memset(p, 0, sizeof(*p));
+    p->voxel_size_m = voxel_size_m;
+    p->truncation_vox = truncation_vox;
+    p->max_weight = 100.0f;
+    p->max_range_m = 5.0f;
+    p->weighting = TSDF_WEIGHT_CONSTANT;
+    p->block_capacity = kDefaultBlocks;
+    p->hash_capacity = 0;
+}
+
+int create_map_ex(const tsdf_params *p, tsdf_map **out)
+{
+    if (!out)
+        return TSDF_EINVAL;
+    *out = nullptr;
+    if (!params_valid(p))
+        return TSDF_EINVAL;
+    tsdf_map *m = new (std::nothrow) tsdf_map();
+    if (!m)
+        return TSDF_ENOMEM;
+    m->p = *p;
+    long long hc = p->hash_capacity;
+    if (hc == 0) {
+        hc = 64;
+        while (hc < 2 * p->block_capacity)
+            hc *= 2;
+    }
+    m->p.hash_capacity = hc;
+    // binary32 per-map constants, the same operations the oracle performs
+    m->eps = p->truncation_vox * p->voxel_size_m;
+    m->delta = p->voxel_size_m;
+    m->span_inv = m->eps > m->delta ? 1.0f / (m->eps - m->delta) : 0.0f;
+    m->max_groups = 2048;
+    m->profiling = false;
+    m->ev_used = 0;
+    m->sticky = 0;
+
+    hipError_t e = hipGetDevice(&m->device);
+    DeviceMap &d = m->dm;
+    const size_t bc = (size_t)p->block_capacity;
+    if (e == hipSuccess) e = hipMalloc(&d.keys, sizeof(unsigned long long) * (size_t)hc);
+    if (e == hipSuccess) e = hipMalloc(&d.vals, sizeof(uint32_t) * (size_t)hc);
+    if (e == hipSuccess) e = hipMalloc(&d.pool, sizeof(float2) * kBlockVoxels * bc);
+    if (e == hipSuccess) e = hipMalloc(&d.slot_keys, sizeof(unsigned long long) * bc);
+    if (e == hipSuccess) e = hipMalloc(&d.touched, sizeof(uint32_t) * bc);
+    if (e == hipSuccess) e = hipMalloc(&d.counters, sizeof(uint32_t) * kNumCounters);
+    if (e == hipSuccess) e = hipMalloc(&d.totals, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(d.keys, 0xFF, sizeof(unsigned long long) * (size_t)hc);
+    if (e == hipSuccess) e = hipMemset(d.vals, 0xFF, sizeof(uint32_t) * (size_t)hc);
+    if (e == hipSuccess) e = hipMemset(d.pool, 0, sizeof(float2) * kBlockVoxels * bc);
+    if (e == hipSuccess) e = hipMemset(d.slot_keys, 0xFF, sizeof(unsigned long long) * bc);
+    if (e == hipSuccess) e = hipMemset(d.counters, 0, sizeof(uint32_t) * kNumCounters);
+    if (e == hipSuccess) e = hipMemset(d.totals, 0, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_device(m);
+        delete m;
+        return hip_status(e);
+    }
+    d.hash_mask = (uint32_t)(hc - 1);
+    d.block_cap = (uint32_t)bc;
+    *out = m;
+    return TSDF_OK;
+}
+
+int create_map(float voxel_size_m, float truncation_vox, tsdf_map **out)
+{
+    tsdf_params p;
+    tsdf_default_params(&p, voxel_size_m, truncation_vox);
+    return create_map_ex(&p, out);
+}
+
+int destroy_map(tsdf_map *m)
+{
+    if (!m)
+        return TSDF_OK;
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    free_events(m);
+    free_device(m);
+    delete m;
+    return TSDF_OK;
+}
+
+int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
+                    const float T_world_cam[16], void *hip_stream)
+{
+    if (!m || !depth_dev || !K || !T_world_cam || width <= 0 || height <= 0)
+        return TSDF_EINVAL;
+    if ((long long)width * (long long)height > (1ll << 31) || width > (1 << 24) || height > (1 << 24))
+        return TSDF_EINVAL;
+    if (!finite_all(K, 4) || !(K[0] > 0) || !(K[1] > 0))
+        return TSDF_EINVAL;
+    if (!pose_valid(T_world_cam))
+        return TSDF_EINVAL;
+    if (m->sticky)
+        return TSDF_ESTATE;
+    FrameArgs fa;
+    int st = frame_args(m, width, height, K, T_world_cam, fa);
+    if (st != TSDF_OK)
+        return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    long long groups = (fa.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
+    groups = std::max(1ll, std::min(groups, (long long)m->max_groups));
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess)
+        return hip_status(e);
+    const bool timed = m->profiling && m->ev_used < kMaxTimedLaunches;
+    if (timed) {
+        if (m->ev_used == m->ev_start.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess)
+                return TSDF_EDEVICE;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return TSDF_EDEVICE;
+            }
+            m->ev_start.push_back(a);
+            m->ev_stop.push_back(b);
+        }
+        if (hipEventRecord(m->ev_start[m->ev_used], s) != hipSuccess)
+            return TSDF_EDEVICE;
+    }
+    e = launch_integrate_depth(m->dm, fa, m->p.weighting, depth_dev, (int)groups, s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    if (timed) {
+        if (hipEventRecord(m->ev_stop[m->ev_used], s) != hipSuccess)
+            return TSDF_EDEVICE;
+        ++m->ev_used;
+    }
+    return TSDF_OK;
+}
+
+int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count, void *hip_stream)
+{
+    if (!m || !out_count || capacity < 0 || (capacity > 0 && !out_xyz_dev))
+        return TSDF_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipSetDevice(m->device) != hipSuccess)
+        return TSDF_EDEVICE;
+    uint32_t c[kNumCounters];
+    int st = read_counters(m, c, nullptr, s);
+    if (st != TSDF_OK)
+        return st;
+    long long n = std::min<long long>(c[kNumBlocks], m->dm.block_cap);
+    *out_count = 0;
+    if (n == 0)
+        return m->sticky;
+    unsigned long long *sorted = nullptr;
+    hipError_t e = hipMalloc(&sorted, sizeof(unsigned long long) * (size_t)n);
+    if (e != hipSuccess)
+        return hip_status(e);
+    e = sort_keys(m->dm.slot_keys, sorted, n, s);
+    // slots reserved but never published keep kEmptyKey, which sorts last
+    long long valid = n;
+    if (e == hipSuccess) {
+        long long lo = 0, hi = n;   // first index holding kEmptyKey
+        while (lo < hi) {
+            const long long mid = (lo + hi) / 2;
+            unsigned long long k = 0;
+            e = hipMemcpy(&k, sorted + mid, sizeof(k), hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                break;
+            if (k == kEmptyKey)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        valid = lo;
+    }
+    if (e == hipSuccess && capacity > 0 && valid > 0)
+        e = launch_decode_keys(sorted, std::min(valid, capacity), out_xyz_dev, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    (void)hipFree(sorted);
+    if (e != hipSuccess)
+        return hip_status(e);
+    *out_count = valid;
+    return m->sticky;
+}
+
+int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks, float *out_dist_dev,
+               float *out_weight_dev, void *hip_stream)
+{
+    if (!m || n_blocks < 0 || (n_blocks > 0 && (!blocks_xyz_dev || !out_dist_dev || !out_weight_dev)))
+        return TSDF_EINVAL;
+    if (n_blocks == 0)
+        return TSDF_OK;
+    if (hipSetDevice(m->device) != hipSuccess)
+        return TSDF_EDEVICE;
+    return hip_status(launch_query_tsdf(m->dm, blocks_xyz_dev, n_blocks, out_dist_dev, out_weight_dev,
+                                        (hipStream_t)hip_stream));
+}
+
+int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count, void *hip_stream)
+{
+    if (!m || !out_count || capacity < 0 || (capacity > 0 && !out_xyz_dev))
+        return TSDF_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (hipSetDevice(m->device) != hipSuccess)
+        return TSDF_EDEVICE;
+    uint32_t c[kNumCounters];
+    int st = read_counters(m, c, nullptr, s);
+    if (st != TSDF_OK)
+        return st;
+    const long long n = c[kTouchedLast];
+    *out_count = n;
+    if (n > 0 && capacity > 0) {
+        hipError_t e = launch_gather_touched(m->dm, std::min(n, capacity), out_xyz_dev, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
+    return m->sticky;
+}
+
+int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates, long long *n_touched_blocks,
+              void *hip_stream)
+{
+    if (!m || !n_blocks || !n_voxel_updates || !n_touched_blocks)
+        return TSDF_EINVAL;
+    if (hipSetDevice(m->device) != hipSuccess)
+        return TSDF_EDEVICE;
+    uint32_t c[kNumCounters];
+    unsigned long long u[2] = {0, 0};
+    int st = read_counters(m, c, u, (hipStream_t)hip_stream);
+    if (st != TSDF_OK)
+        return st;
+    *n_blocks = std::min<long long>(c[kNumBlocks], m->dm.block_cap);
+    *n_voxel_updates = (long long)u[0];
+    *n_touched_blocks = (long long)u[1];
+    return TSDF_OK;
+}
+
+int map_status(tsdf_map *m)
+{
+    if (!m)
+        return TSDF_EINVAL;
+    if (hipSetDevice(m->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return TSDF_EDEVICE;
+    uint32_t c[kNumCounters];
+    int st = read_counters(m, c, nullptr, nullptr);
+    if (st != TSDF_OK)
+        return st;
+    return m->sticky;
+}
+
+const char *tsdf_strerror(int status)
+{
+    switch (status) {
+    case TSDF_OK: return "ok";
+    case TSDF_EINVAL: return "invalid argument";
+    case TSDF_ENOMEM: return "out of device memory";
+    case TSDF_EFULL: return "map capacity exceeded (block pool, hash table or touched list)";
+    case TSDF_EDEVICE: return "HIP runtime error";
+    case TSDF_ESTATE: return "map is in a sticky error state";
+    default: return "unknown status";
+    }
+}
+
+int tsdf_profile(tsdf_map *m, int enable)
+{
+    if (!m)
+        return TSDF_EINVAL;
+    m->profiling = enable != 0;
+    m->ev_used = 0;
+    return TSDF_OK;
+}
+
+int tsdf_profile_read(tsdf_map *m, double *total_ms, long long *launches)
+{
+    if (!m || !total_ms || !launches)
+        return TSDF_EINVAL;
+    double sum = 0;
+    for (size_t k = 0; k < m->ev_used; ++k) {
+        if (hipEventSynchronize(m->ev_stop[k]) != hipSuccess)
+            return TSDF_EDEVICE;
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, m->ev_start[k], m->ev_stop[k]) != hipSuccess)
+            return TSDF_EDEVICE;
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (long long)m->ev_used;
+    m->ev_used = 0;
+    return TSDF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+// Read-side kernels of the block map: voxel gathers by block index, key
+// decoding, touched-list export, and the key sort behind query_blocks.
+#include "tsdf_internal.hpp"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+namespace tsdf {
+namespace {
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// Read-only wave-cooperative probe: pool slot of `key`, or kInvalidSlot.
+__device__ uint32_t find_block(const DeviceMap &dm, unsigned long long key)
+{
+    const int lane = lane_id();
+    const uint32_t mask = dm.hash_mask;
+    const uint32_t h = (uint32_t)hash_key(key) & mask;
+    for (uint32_t base = 0; base <= mask; base += 64) {
+        const uint32_t pos = (h + base + (uint32_t)lane) & mask;
+        const unsigned long long k = dm.keys[pos];
+        const unsigned long long m_hit = __ballot(k == key);
+        const unsigned long long m_free = __ballot(k == kEmptyKey);
+        const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
+        const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
+        if (f_hit < f_free)
+            return dm.vals[(h + base + (uint32_t)f_hit) & mask];
+        if (f_free < 64)
+            return kInvalidSlot;
+    }
+    return kInvalidSlot;
+}
+
+__global__ __launch_bounds__(256) void query_tsdf_kernel(DeviceMap dm, const int32_t *__restrict__ xyz,
+                                                         long long n, float *__restrict__ dist,
+                                                         float *__restrict__ weight)
+{
+    const int lane = lane_id();
+    const long long stride = (long long)gridDim.x * kWavesPerGroup;
+    for (long long b = (long long)blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6); b < n; b += stride) {
+        const int x = xyz[3 * b], y = xyz[3 * b + 1], z = xyz[3 * b + 2];
+        const bool in_range = x >= -kBlockCoordMax && x <= kBlockCoordMax && y >= -kBlockCoordMax &&
+                              y <= kBlockCoordMax && z >= -kBlockCoordMax && z <= kBlockCoordMax;
+        uint32_t slot = kInvalidSlot;
+        if (in_range)
+            slot = find_block(dm, pack_key(x, y, z));
+        if (slot >= dm.block_cap)
+            slot = kInvalidSlot;
+        float *d = dist + b * kBlockVoxels;
+        float *w = weight + b * kBlockVoxels;
+        for (int k = lane; k < kBlockVoxels; k += 64) {
+            float2 v = make_float2(0.0f, 0.0f);
+            if (slot != kInvalidSlot)
+                v = dm.pool[(size_t)slot * kBlockVoxels + k];
+            d[k] = v.x;
+            w[k] = v.y;
+        }
+    }
+}
+
+__global__ void decode_keys_kernel(const unsigned long long *__restrict__ keys, long long n,
+                                   int32_t *__restrict__ xyz)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        int x, y, z;
+        unpack_key(keys[i], x, y, z);
+        xyz[3 * i] = x;
+        xyz[3 * i + 1] = y;
+        xyz[3 * i + 2] = z;
+    }
+}
+
+__global__ void gather_touched_kernel(DeviceMap dm, long long n, int32_t *__restrict__ xyz)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        int x, y, z;
+        unpack_key(dm.slot_keys[dm.touched[i]], x, y, z);
+        xyz[3 * i] = x;
+        xyz[3 * i + 1] = y;
+        xyz[3 * i + 2] = z;
+    }
+}
+
+int grid_for(long long n, int per_group)
+{
+    long long g = (n + per_group - 1) / per_group;
+    if (g < 1)
+        g = 1;
+    if (g > 16384)
+        g = 16384;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
+                             float *weight, hipStream_t stream)
+{
+    hipLaunchKernelGGL(query_tsdf_kernel, dim3(grid_for(n, kWavesPerGroup)), dim3(64 * kWavesPerGroup), 0,
+                       stream, dm, xyz, n, dist, weight);
+    return hipGetLastError();
+}
+
+hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz, hipStream_t stream)
+{
+    hipLaunchKernelGGL(decode_keys_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, keys, n, xyz);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_touched(const DeviceMap &dm, long long n, int32_t *xyz, hipStream_t stream)
+{
+    hipLaunchKernelGGL(gather_touched_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, dm, n, xyz);
+    return hipGetLastError();
+}
+
+// Ascending radix sort of packed keys; the packing puts x in the high bits, so
+// the order is lexicographic in (x, y, z).  Allocates its temporary storage.
+hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n, hipStream_t stream)
+{
+    size_t temp_bytes = 0;
+    hipError_t e = rocprim::radix_sort_keys(nullptr, temp_bytes, in, out, (size_t)n, 0, 64, stream);
+    if (e != hipSuccess)
+        return e;
+    void *temp = nullptr;
+    e = hipMalloc(&temp, temp_bytes > 0 ? temp_bytes : 1);
+    if (e != hipSuccess)
+        return e;
+    e = rocprim::radix_sort_keys(temp, temp_bytes, in, out, (size_t)n, 0, 64, stream);
+    hipError_t e2 = hipStreamSynchronize(stream);
+    (void)hipFree(temp);
+    return e != hipSuccess ? e : e2;
+}
+
+}  // namespace tsdf

@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP kernels and the host ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsdf {
+
+constexpr unsigned long long kEmptyKey = ~0ull;     // hash slot never used
+constexpr uint32_t kInvalidSlot = 0xFFFFFFFFu;      // hash value not yet published
+constexpr int kBlockVoxels = 512;                   // 8 x 8 x 8 voxels per block (§IV-A)
+constexpr int kKeyBits = 21;                        // bits per packed block coordinate
+constexpr int kKeyOffset = 1 << 20;                 // block coordinate bias
+constexpr int kBlockCoordMax = (1 << 20) - 1;       // |block index| limit on every axis
+constexpr int kWavesPerGroup = 4;                   // 256-thread workgroups of wave64
+
+// Indices into the per-map counter words.
+enum Counter : int {
+    kNumBlocks = 0,     // pool slots handed out (may exceed capacity after an overflow)
+    kTouched = 1,       // touched blocks of the frame in flight
+    kGroupsDone = 2,    // workgroups of the frame in flight that have finished
+    kTouchedLast = 3,   // touched blocks of the last completed frame
+    kErrorBits = 4,     // sticky ErrorBits
+    kNumCounters = 8
+};
+
+enum ErrorBits : uint32_t {
+    kErrPoolFull = 1u,
+    kErrHashFull = 2u,
+    kErrTouchedOverflow = 4u,
+    kErrInsertRace = 8u,
+};
+
+// Device-side view of a map.  Passed to kernels by value.
+struct DeviceMap {
+    unsigned long long *keys;        // [hash_mask + 1] packed block keys, kEmptyKey = free
+    uint32_t *vals;                  // [hash_mask + 1] pool slot of the key, kInvalidSlot until published
+    float2 *pool;                    // [block_cap * 512] (distance, weight) per voxel
+    unsigned long long *slot_keys;   // [block_cap] key of each pool slot
+    uint32_t *touched;               // [block_cap] pool slots touched by the last frame
+    uint32_t *counters;              // [kNumCounters]
+    unsigned long long *totals;      // [2] running totals: voxel updates, touched blocks
+    uint32_t hash_mask;
+    uint32_t block_cap;
+};
+
+// Per-frame constants (host-computed, passed by value).
+struct FrameArgs {
+    float R[9];             // camera-from-world rotation, row-major (T_CL of Eq. (1))
+    float t[3];             // camera-from-world translation
+    float fx, fy, cx, cy;   // pinhole intrinsics (Eq. (2))
+    float width_f, height_f;
+    int width, height;
+    float vs;               // voxel edge
+    float eps;              // truncation distance epsilon
+    float delta;            // start of the linear weight dropoff behind the surface
+    float span_inv;         // 1 / (epsilon - delta)
+    float w_max;            // weight cap
+    float d_max;            // max valid measurement
+    float zfar;             // no voxel beyond camera depth zfar can be updated
+    float margin_u, margin_v, margin_z;   // conservative slack of the block-culling planes
+    int lat_min[3];         // block lattice scanned by the frame (inclusive lower corner)
+    int lat_dim[3];
+    long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2]
+};
+
+__host__ __device__ inline unsigned long long pack_key(int x, int y, int z)
+{
+    return ((unsigned long long)(uint32_t)(x + kKeyOffset) << (2 * kKeyBits)) |
+           ((unsigned long long)(uint32_t)(y + kKeyOffset) << kKeyBits) |
+           (unsigned long long)(uint32_t)(z + kKeyOffset);
+}
+
+__host__ __device__ inline void unpack_key(unsigned long long k, int &x, int &y, int &z)
+{
+    const unsigned long long m = (1ull << kKeyBits) - 1ull;
+    x = (int)((k >> (2 * kKeyBits)) & m) - kKeyOffset;
+    y = (int)((k >> kKeyBits) & m) - kKeyOffset;
+    z = (int)(k & m) - kKeyOffset;
+}
+
+// splitmix64 finaliser: spreads packed keys over the table.
+__host__ __device__ inline unsigned long long hash_key(unsigned long long k)
+{
+    k ^= k >> 30;
+    k *= 0xBF58476D1CE4E5B9ull;
+    k ^= k >> 27;
+    k *= 0x94D049BB133111EBull;
+    k ^= k >> 31;
+    return k;
+}
+
+// Kernel launchers (integrate.hip, query.hip).
+hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting,
+                                  const float *depth, int groups, hipStream_t stream);
+hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
+                             float *weight, hipStream_t stream);
+hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
+                              hipStream_t stream);
+hipError_t launch_gather_touched(const DeviceMap &dm, long long n, int32_t *xyz, hipStream_t stream);
+hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n,
+                     hipStream_t stream);
+
+}  // namespace tsdf

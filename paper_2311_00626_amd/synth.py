@@ -117,57 +117,66 @@ def _ray_dirs_cam(cam: PinholeCamera, dev, dtype=torch.float64):
 
 
 def render_depth(scene: Scene, cam: PinholeCamera, T_world_cam: np.ndarray,
-                 device: str = "cpu") -> np.ndarray:
+                 device: str = "cpu", chunk: int = 1 << 16) -> np.ndarray:
     """Ray-cast z-depth (float32, H x W) of ``scene`` seen from ``T_world_cam``.
 
-    Pixels whose ray hits nothing get depth 0 (invalid).
+    Every object is intersected with every ray in float64 (spheres and boxes
+    vectorised over objects, rays processed in chunks); pixels whose ray hits
+    nothing get depth 0 (invalid).
     """
     dev = torch.device(device)
+    f64 = torch.float64
     T = torch.as_tensor(np.asarray(T_world_cam, dtype=np.float64), device=dev)
     R, o = T[:3, :3], T[:3, 3]
-    dc = _ray_dirs_cam(cam, dev)
-    d = dc @ R.T                                     # world directions; t == z-depth
-    d = torch.where(d == 0, torch.full_like(d, 1e-300), d)
-    inf = torch.tensor(float("inf"), device=dev, dtype=torch.float64)
-    t_best = torch.full(d.shape[:2], float("inf"), device=dev, dtype=torch.float64)
-
-    if scene.room is not None:
-        L = torch.tensor(scene.room, device=dev, dtype=torch.float64)
-        bound = torch.where(d > 0, L, torch.zeros_like(L))
-        t_axes = (bound - o) / d
-        t_axes = torch.where(t_axes > 0, t_axes, inf)
-        t_best = torch.minimum(t_best, t_axes.min(dim=-1).values)
-
-    for (c, r) in scene.spheres:
-        oc = o - torch.tensor(c, device=dev, dtype=torch.float64)
-        a = (d * d).sum(-1)
-        b = (d * oc).sum(-1)
-        cc = (oc * oc).sum() - r * r
-        disc = b * b - a * cc
-        sq = torch.sqrt(torch.clamp(disc, min=0.0))
-        t0 = (-b - sq) / a
-        t1 = (-b + sq) / a
-        t = torch.where(t0 > 0, t0, t1)
-        hit = (disc >= 0) & (t > 0)
-        t_best = torch.where(hit & (t < t_best), t, t_best)
-
-    for (bmin, bmax) in scene.boxes:
-        lo = torch.tensor(bmin, device=dev, dtype=torch.float64)
-        hi = torch.tensor(bmax, device=dev, dtype=torch.float64)
-        t1 = (lo - o) / d
-        t2 = (hi - o) / d
-        tn = torch.minimum(t1, t2).max(dim=-1).values
-        tf = torch.maximum(t1, t2).min(dim=-1).values
-        hit = (tn <= tf) & (tn > 0)
-        t_best = torch.where(hit & (tn < t_best), tn, t_best)
-
-    for (n, c) in scene.planes:
-        nv = torch.tensor(n, device=dev, dtype=torch.float64)
-        denom = (d * nv).sum(-1)
-        t = (c - torch.dot(nv, o)) / denom
-        hit = (denom > 0) & (t > 0)
-        t_best = torch.where(hit & (t < t_best), t, t_best)
-
+    dirs = (_ray_dirs_cam(cam, dev) @ R.T).reshape(-1, 3)   # world directions; t == z-depth
+    dirs = torch.where(dirs == 0, torch.full_like(dirs, 1e-300), dirs)
+    inf = float("inf")
+    room = torch.tensor(scene.room, device=dev, dtype=f64) if scene.room is not None else None
+    if scene.spheres:
+        sc = torch.tensor([c for c, _ in scene.spheres], device=dev, dtype=f64)      # (S, 3)
+        sr = torch.tensor([r for _, r in scene.spheres], device=dev, dtype=f64)      # (S,)
+        oc = o[None, :] - sc
+        cc = (oc * oc).sum(-1) - sr * sr
+    if scene.boxes:
+        blo = torch.tensor([b[0] for b in scene.boxes], device=dev, dtype=f64)       # (B, 3)
+        bhi = torch.tensor([b[1] for b in scene.boxes], device=dev, dtype=f64)
+    if scene.planes:
+        pn = torch.tensor([n for n, _ in scene.planes], device=dev, dtype=f64)       # (P, 3)
+        pc = torch.tensor([c for _, c in scene.planes], device=dev, dtype=f64)
+    out = []
+    for a in range(0, dirs.shape[0], chunk):
+        d = dirs[a:a + chunk]
+        t_best = torch.full(d.shape[:1], inf, device=dev, dtype=f64)
+        if room is not None:
+            bound = torch.where(d > 0, room, torch.zeros_like(room))
+            t_axes = (bound - o) / d
+            t_axes = torch.where(t_axes > 0, t_axes, torch.full_like(t_axes, inf))
+            t_best = torch.minimum(t_best, t_axes.min(dim=-1).values)
+        if scene.spheres:
+            aa = (d * d).sum(-1)[:, None]                            # (N, 1)
+            b = d @ oc.T                                             # (N, S)
+            disc = b * b - aa * cc[None, :]
+            sq = torch.sqrt(torch.clamp(disc, min=0.0))
+            t0 = (-b - sq) / aa
+            t1 = (-b + sq) / aa
+            t = torch.where(t0 > 0, t0, t1)
+            t = torch.where((disc >= 0) & (t > 0), t, torch.full_like(t, inf))
+            t_best = torch.minimum(t_best, t.min(dim=-1).values)
+        if scene.boxes:
+            inv = 1.0 / d
+            t1 = (blo[None] - o) * inv[:, None, :]                   # (N, B, 3)
+            t2 = (bhi[None] - o) * inv[:, None, :]
+            tn = torch.minimum(t1, t2).max(dim=-1).values
+            tf = torch.maximum(t1, t2).min(dim=-1).values
+            t = torch.where((tn <= tf) & (tn > 0), tn, torch.full_like(tn, inf))
+            t_best = torch.minimum(t_best, t.min(dim=-1).values)
+        if scene.planes:
+            denom = d @ pn.T                                         # (N, P)
+            t = (pc[None, :] - (pn @ o)[None, :]) / denom
+            t = torch.where((denom > 0) & (t > 0), t, torch.full_like(t, inf))
+            t_best = torch.minimum(t_best, t.min(dim=-1).values)
+        out.append(t_best)
+    t_best = torch.cat(out).reshape(cam.height, cam.width)
     depth = torch.where(torch.isfinite(t_best), t_best, torch.zeros_like(t_best))
     return depth.to(torch.float32).cpu().numpy()
 

@@ -1,0 +1,210 @@
+"""Thin ctypes binding of ``lib/libtsdf.so`` (the C ABI in include/tsdf.h).
+
+Argument marshalling only: every step of integration and every query runs in
+the library's HIP kernels.  PyTorch supplies device memory and the current
+stream.  Importing this module raises if the library has not been built:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libtsdf.so")
+
+OK, EINVAL, ENOMEM, EFULL, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+WEIGHTINGS = {"constant": 0, "linear_dropoff": 1}
+
+
+class TsdfError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {strerror(status)} (status {status})")
+        self.status = status
+
+
+class tsdf_params(C.Structure):
+    _fields_ = [("voxel_size_m", C.c_float), ("truncation_vox", C.c_float),
+                ("max_weight", C.c_float), ("max_range_m", C.c_float),
+                ("weighting", C.c_int), ("reserved0", C.c_int),
+                ("block_capacity", C.c_longlong), ("hash_capacity", C.c_longlong)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, ll, i = C.c_void_p, C.c_longlong, C.c_int
+    fp = C.POINTER(C.c_float)
+    lib.tsdf_default_params.argtypes = [C.POINTER(tsdf_params), C.c_float, C.c_float]
+    lib.tsdf_default_params.restype = None
+    lib.create_map.argtypes = [C.c_float, C.c_float, C.POINTER(vp)]
+    lib.create_map_ex.argtypes = [C.POINTER(tsdf_params), C.POINTER(vp)]
+    lib.destroy_map.argtypes = [vp]
+    lib.integrate_depth.argtypes = [vp, vp, i, i, fp, fp, vp]
+    lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
+    lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
+    lib.query_touched.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
+    lib.map_stats.argtypes = [vp, C.POINTER(ll), C.POINTER(ll), C.POINTER(ll), vp]
+    lib.map_status.argtypes = [vp]
+    lib.tsdf_strerror.argtypes = [i]
+    lib.tsdf_strerror.restype = C.c_char_p
+    lib.tsdf_profile.argtypes = [vp, i]
+    lib.tsdf_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ll)]
+    for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "query_blocks",
+                 "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
+                 "tsdf_profile_read"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "integrate_depth",
+            "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
+            "tsdf_strerror", "tsdf_profile", "tsdf_profile_read")
+
+
+def strerror(status: int) -> str:
+    return lib.tsdf_strerror(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise TsdfError(status, where)
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _host_f32(a, n: int) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(n))
+    return arr
+
+
+def default_params(voxel_size: float, truncation_vox: float) -> tsdf_params:
+    p = tsdf_params()
+    lib.tsdf_default_params(C.byref(p), voxel_size, truncation_vox)
+    return p
+
+
+class TsdfMap:
+    """A block-sparse TSDF layer on the current GPU (see include/tsdf.h)."""
+
+    def __init__(self, voxel_size: float, truncation_vox: float, *, max_weight: float = 100.0,
+                 max_range: float = 5.0, weighting: str = "constant",
+                 block_capacity: int = 1 << 18, hash_capacity: int = 0):
+        p = default_params(voxel_size, truncation_vox)
+        p.max_weight = max_weight
+        p.max_range_m = max_range
+        p.weighting = WEIGHTINGS[weighting]
+        p.block_capacity = block_capacity
+        p.hash_capacity = hash_capacity
+        h = C.c_void_p()
+        _check(lib.create_map_ex(C.byref(p), C.byref(h)), "create_map_ex")
+        self._h = h
+        self.params = p
+        self.block_capacity = block_capacity
+
+    @classmethod
+    def from_params(cls, params, **kw) -> "TsdfMap":
+        return cls(params.voxel_size, params.truncation_vox, max_weight=params.max_weight,
+                   max_range=params.max_range, weighting=params.weighting, **kw)
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib.destroy_map(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- integration --------------------------------------------------------
+    def integrate_depth(self, depth: torch.Tensor, K: Sequence[float], T_world_cam,
+                        stream: Optional[torch.cuda.Stream] = None) -> None:
+        if not (depth.is_cuda and depth.dtype == torch.float32 and depth.dim() == 2
+                and depth.is_contiguous()):
+            raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
+        Kh = _host_f32(K, 4)
+        Th = _host_f32(T_world_cam, 16)
+        H, W = depth.shape
+        st = lib.integrate_depth(self._h, C.c_void_p(depth.data_ptr()), int(W), int(H),
+                                 Kh.ctypes.data_as(C.POINTER(C.c_float)),
+                                 Th.ctypes.data_as(C.POINTER(C.c_float)), C.c_void_p(_stream_ptr(stream)))
+        _check(st, "integrate_depth")
+
+    # -- queries --------------------------------------------------------------
+    def query_blocks(self, stream=None) -> torch.Tensor:
+        """Allocated block indices, int32 (n, 3), sorted by (x, y, z)."""
+        n = C.c_longlong()
+        _check(lib.query_blocks(self._h, None, 0, C.byref(n), C.c_void_p(_stream_ptr(stream))), "query_blocks")
+        out = torch.empty((max(n.value, 1), 3), dtype=torch.int32, device="cuda")
+        n2 = C.c_longlong()
+        _check(lib.query_blocks(self._h, C.c_void_p(out.data_ptr()), n.value, C.byref(n2),
+                                C.c_void_p(_stream_ptr(stream))), "query_blocks")
+        return out[: n2.value]
+
+    def query_tsdf(self, blocks: torch.Tensor, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(dist, weight) float32 (n, 512) of int32 (n, 3) device block indices."""
+        blocks = blocks.to(device="cuda", dtype=torch.int32).contiguous()
+        n = blocks.shape[0]
+        d = torch.empty((n, 512), dtype=torch.float32, device="cuda")
+        w = torch.empty((n, 512), dtype=torch.float32, device="cuda")
+        if n:
+            _check(lib.query_tsdf(self._h, C.c_void_p(blocks.data_ptr()), n, C.c_void_p(d.data_ptr()),
+                                  C.c_void_p(w.data_ptr()), C.c_void_p(_stream_ptr(stream))), "query_tsdf")
+        return d, w
+
+    def query_touched(self, stream=None) -> torch.Tensor:
+        """Blocks updated by the last integrate_depth call, int32 (n, 3), unordered."""
+        n = C.c_longlong()
+        _check(lib.query_touched(self._h, None, 0, C.byref(n), C.c_void_p(_stream_ptr(stream))), "query_touched")
+        out = torch.empty((max(n.value, 1), 3), dtype=torch.int32, device="cuda")
+        n2 = C.c_longlong()
+        _check(lib.query_touched(self._h, C.c_void_p(out.data_ptr()), n.value, C.byref(n2),
+                                 C.c_void_p(_stream_ptr(stream))), "query_touched")
+        return out[: n2.value]
+
+    def stats(self, stream=None) -> Tuple[int, int]:
+        """(allocated blocks, running total of voxel updates)."""
+        b, u, _ = self.counters(stream)
+        return b, u
+
+    def counters(self, stream=None) -> Tuple[int, int, int]:
+        """(allocated blocks, total voxel updates, total touched blocks)."""
+        b, u, t = C.c_longlong(), C.c_longlong(), C.c_longlong()
+        _check(lib.map_stats(self._h, C.byref(b), C.byref(u), C.byref(t), C.c_void_p(_stream_ptr(stream))),
+               "map_stats")
+        return b.value, u.value, t.value
+
+    def status(self) -> int:
+        return lib.map_status(self._h)
+
+    def sorted_state(self):
+        """(blocks, dist, weight) on the host, sorted by block index."""
+        b = self.query_blocks()
+        d, w = self.query_tsdf(b)
+        torch.cuda.synchronize()
+        return b.cpu().numpy(), d.cpu().numpy(), w.cpu().numpy()
+
+    # -- kernel timing -------------------------------------------------------
+    def profile(self, enable: bool) -> None:
+        _check(lib.tsdf_profile(self._h, 1 if enable else 0), "tsdf_profile")
+
+    def profile_read(self) -> Tuple[float, int]:
+        ms, n = C.c_double(), C.c_longlong()
+        _check(lib.tsdf_profile_read(self._h, C.byref(ms), C.byref(n)), "tsdf_profile_read")
+        return ms.value, n.value

@@ -1,0 +1,54 @@
+"""Helpers shared by the GPU tests: run the HIP path and the oracle on the
+same seeded inputs and compare them to the stated bar."""
+import sys
+
+import numpy as np
+import torch
+
+# Parity bar: allocated block sets bit-exact, weights exact, distances within
+# 1e-5 m (binary32).
+DIST_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_map(params, **kw):
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    return TsdfMap.from_params(params, **kw)
+
+
+def integrate_both(params, frames, K, poses, gpu_kw=None, oracle_precision=32, check_touched=False):
+    """Integrates the frames on the GPU and in the oracle; returns both maps.
+    With check_touched, compares the touched list after every frame."""
+    import oracle
+    gm = gpu_map(params, **(gpu_kw or {}))
+    om = oracle.OracleMap.from_params(params, precision=oracle_precision)
+    for k, (d, T) in enumerate(zip(frames, poses)):
+        dt = torch.as_tensor(np.ascontiguousarray(d), device="cuda")
+        gm.integrate_depth(dt, K, T)
+        om.integrate(d, K, T)
+        if check_touched:
+            gt = gm.query_touched().cpu().numpy()
+            ot = om.touched()
+            assert {tuple(x) for x in gt} == {tuple(x) for x in ot}, f"touched set differs at frame {k}"
+            assert len(gt) == len(ot)
+    torch.cuda.synchronize()
+    return gm, om
+
+
+def assert_parity(gm, om, tol=DIST_TOL, exact_dist=False):
+    gb, gd, gw = gm.sorted_state()
+    ob, od, ow = om.sorted_state()
+    assert gb.shape == ob.shape, f"{len(gb)} GPU blocks vs {len(ob)} oracle blocks"
+    assert np.array_equal(gb, ob), "allocated block sets differ"
+    assert np.array_equal(gw.astype(np.float64), ow), "weights differ"
+    diff = np.abs(gd.astype(np.float64) - od)
+    assert diff.size == 0 or diff.max() <= tol, f"max |dist diff| {diff.max()}"
+    if exact_dist:
+        assert np.array_equal(gd.astype(np.float64), od), "distances not bit-identical"
+    return {"blocks": len(gb), "updated_voxels": int((gw > 0).sum()),
+            "bit_identical_dist": bool(np.array_equal(gd.astype(np.float64), od)),
+            "max_dist_diff": float(diff.max()) if diff.size else 0.0}
