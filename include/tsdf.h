@@ -100,7 +100,7 @@ TSDF_API int destroy_map(tsdf_map *m);
  *   A block is allocated (zero distance, zero weight) the first time any of
  *   its voxels is updated; the blocks updated by this frame form the touched
  *   list (query_touched).
- * depth_dev: device float32[height][width].  K: host {fx, fy, cx, cy} with
+ * depth_dev: device float32[height][width], width * height <= 2^28.  K: host {fx, fy, cx, cy} with
  * fx, fy > 0.  T_world_cam: host row-major 4x4; its bottom row must be
  * (0 0 0 1) within 1e-6 and its rotation orthonormal within 1e-4.
  * Only enqueues work on hip_stream (no host synchronisation).

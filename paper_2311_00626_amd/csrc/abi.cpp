@@ -21,6 +21,7 @@ struct tsdf_map {
     int sticky;                           // host copy of an observed device error (TSDF_EFULL) or 0
     float eps, delta, span_inv;           // per-map constants in binary32
     int max_groups;                       // cap on integration workgroups per launch
+    long long frames;                     // integrate calls launched so far (parity of the touched counters)
     // kernel timing
     bool profiling;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -193,18 +194,35 @@ int frame_args(const tsdf_map *m, int width, int height, const float K[4], const
     return TSDF_OK;
 }
 
-int read_counters(tsdf_map *m, uint32_t *c, unsigned long long *totals, hipStream_t s)
+struct CounterSnapshot {
+    uint32_t c[kNumCounterWords];
+    unsigned long long t[kNumTotalWords];
+};
+
+int read_counters(tsdf_map *m, CounterSnapshot &cs, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(c, m->dm.counters, sizeof(uint32_t) * kNumCounters, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && totals)
-        e = hipMemcpyAsync(totals, m->dm.totals, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(cs.c, m->dm.counters, sizeof(cs.c), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cs.t, m->dm.totals, sizeof(cs.t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return hip_status(e);
-    if (c[kErrorBits] != 0)
+    if (cs.c[kErrorBits] != 0)
         m->sticky = TSDF_EFULL;
     return TSDF_OK;
+}
+
+// Touched count of each sub-list for the most recent frame (zeros before the first).
+void last_touched_counts(const tsdf_map *m, const CounterSnapshot &cs, long long n[kSubLists])
+{
+    for (int k = 0; k < kSubLists; ++k)
+        n[k] = 0;
+    if (m->frames == 0)
+        return;
+    const int parity = (int)((m->frames - 1) & 1);
+    for (int k = 0; k < kSubLists; ++k)
+        n[k] = std::min<long long>(cs.c[touched_counter(parity, k)], m->dm.block_cap);
 }
 
 }  // namespace
@@ -247,7 +265,8 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     m->eps = p->truncation_vox * p->voxel_size_m;
     m->delta = p->voxel_size_m;
     m->span_inv = m->eps > m->delta ? 1.0f / (m->eps - m->delta) : 0.0f;
-    m->max_groups = 2048;
+    m->max_groups = 512;
+    m->frames = 0;
     m->profiling = false;
     m->ev_used = 0;
     m->sticky = 0;
@@ -259,15 +278,15 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     if (e == hipSuccess) e = hipMalloc(&d.vals, sizeof(uint32_t) * (size_t)hc);
     if (e == hipSuccess) e = hipMalloc(&d.pool, sizeof(float2) * kBlockVoxels * bc);
     if (e == hipSuccess) e = hipMalloc(&d.slot_keys, sizeof(unsigned long long) * bc);
-    if (e == hipSuccess) e = hipMalloc(&d.touched, sizeof(uint32_t) * bc);
-    if (e == hipSuccess) e = hipMalloc(&d.counters, sizeof(uint32_t) * kNumCounters);
-    if (e == hipSuccess) e = hipMalloc(&d.totals, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&d.touched, sizeof(uint32_t) * bc * kSubLists);
+    if (e == hipSuccess) e = hipMalloc(&d.counters, sizeof(uint32_t) * kNumCounterWords);
+    if (e == hipSuccess) e = hipMalloc(&d.totals, sizeof(unsigned long long) * kNumTotalWords);
     if (e == hipSuccess) e = hipMemset(d.keys, 0xFF, sizeof(unsigned long long) * (size_t)hc);
     if (e == hipSuccess) e = hipMemset(d.vals, 0xFF, sizeof(uint32_t) * (size_t)hc);
     if (e == hipSuccess) e = hipMemset(d.pool, 0, sizeof(float2) * kBlockVoxels * bc);
     if (e == hipSuccess) e = hipMemset(d.slot_keys, 0xFF, sizeof(unsigned long long) * bc);
-    if (e == hipSuccess) e = hipMemset(d.counters, 0, sizeof(uint32_t) * kNumCounters);
-    if (e == hipSuccess) e = hipMemset(d.totals, 0, 2 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(d.counters, 0, sizeof(uint32_t) * kNumCounterWords);
+    if (e == hipSuccess) e = hipMemset(d.totals, 0, sizeof(unsigned long long) * kNumTotalWords);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_device(m);
@@ -304,7 +323,8 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
 {
     if (!m || !depth_dev || !K || !T_world_cam || width <= 0 || height <= 0)
         return TSDF_EINVAL;
-    if ((long long)width * (long long)height > (1ll << 31) || width > (1 << 24) || height > (1 << 24))
+    // byte offsets into the depth image must stay below 2^31 (buffer addressing)
+    if ((long long)width * (long long)height > (1ll << 28) || width > (1 << 24) || height > (1 << 24))
         return TSDF_EINVAL;
     if (!finite_all(K, 4) || !(K[0] > 0) || !(K[1] > 0))
         return TSDF_EINVAL;
@@ -316,6 +336,7 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     int st = frame_args(m, width, height, K, T_world_cam, fa);
     if (st != TSDF_OK)
         return st;
+    fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     long long groups = (fa.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
     groups = std::max(1ll, std::min(groups, (long long)m->max_groups));
@@ -341,6 +362,7 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     e = launch_integrate_depth(m->dm, fa, m->p.weighting, depth_dev, (int)groups, s);
     if (e != hipSuccess)
         return hip_status(e);
+    ++m->frames;
     if (timed) {
         if (hipEventRecord(m->ev_stop[m->ev_used], s) != hipSuccess)
             return TSDF_EDEVICE;
@@ -356,11 +378,11 @@ int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lon
     hipStream_t s = (hipStream_t)hip_stream;
     if (hipSetDevice(m->device) != hipSuccess)
         return TSDF_EDEVICE;
-    uint32_t c[kNumCounters];
-    int st = read_counters(m, c, nullptr, s);
+    CounterSnapshot cs;
+    int st = read_counters(m, cs, s);
     if (st != TSDF_OK)
         return st;
-    long long n = std::min<long long>(c[kNumBlocks], m->dm.block_cap);
+    long long n = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
     *out_count = 0;
     if (n == 0)
         return m->sticky;
@@ -417,16 +439,28 @@ int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lo
     hipStream_t s = (hipStream_t)hip_stream;
     if (hipSetDevice(m->device) != hipSuccess)
         return TSDF_EDEVICE;
-    uint32_t c[kNumCounters];
-    int st = read_counters(m, c, nullptr, s);
+    CounterSnapshot cs;
+    int st = read_counters(m, cs, s);
     if (st != TSDF_OK)
         return st;
-    const long long n = c[kTouchedLast];
+    long long per[kSubLists];
+    last_touched_counts(m, cs, per);
+    long long n = 0;
+    for (int k = 0; k < kSubLists; ++k)
+        n += per[k];
     *out_count = n;
-    if (n > 0 && capacity > 0) {
-        hipError_t e = launch_gather_touched(m->dm, std::min(n, capacity), out_xyz_dev, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
+    long long written = 0;
+    for (int k = 0; k < kSubLists && written < capacity; ++k) {
+        const long long take = std::min(per[k], capacity - written);
+        if (take <= 0)
+            continue;
+        hipError_t e = launch_gather_touched(m->dm, k, take, out_xyz_dev + 3 * written, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+        written += take;
+    }
+    if (written > 0) {
+        hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess)
             return hip_status(e);
     }
@@ -440,14 +474,21 @@ int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates, long
         return TSDF_EINVAL;
     if (hipSetDevice(m->device) != hipSuccess)
         return TSDF_EDEVICE;
-    uint32_t c[kNumCounters];
-    unsigned long long u[2] = {0, 0};
-    int st = read_counters(m, c, u, (hipStream_t)hip_stream);
+    CounterSnapshot cs;
+    int st = read_counters(m, cs, (hipStream_t)hip_stream);
     if (st != TSDF_OK)
         return st;
-    *n_blocks = std::min<long long>(c[kNumBlocks], m->dm.block_cap);
-    *n_voxel_updates = (long long)u[0];
-    *n_touched_blocks = (long long)u[1];
+    *n_blocks = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
+    unsigned long long upd = 0;
+    for (int k = 0; k < kSubLists; ++k)
+        upd += cs.t[kTotalUpdates + k * kTotalsStride];
+    long long per[kSubLists];
+    last_touched_counts(m, cs, per);
+    long long touched = (long long)cs.t[kTotalTouched];
+    for (int k = 0; k < kSubLists; ++k)
+        touched += per[k];
+    *n_voxel_updates = (long long)upd;
+    *n_touched_blocks = touched;
     return TSDF_OK;
 }
 
@@ -457,8 +498,8 @@ int map_status(tsdf_map *m)
         return TSDF_EINVAL;
     if (hipSetDevice(m->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return TSDF_EDEVICE;
-    uint32_t c[kNumCounters];
-    int st = read_counters(m, c, nullptr, nullptr);
+    CounterSnapshot cs;
+    int st = read_counters(m, cs, nullptr);
     if (st != TSDF_OK)
         return st;
     return m->sticky;

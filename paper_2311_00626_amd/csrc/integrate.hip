@@ -33,43 +33,67 @@ namespace {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
+// Raw buffer descriptors (word 3 of the gfx9-family resource: 32-bit data
+// format).  A load whose offset is at or past num_records returns 0 and a
+// store there is dropped, which predicates memory per lane without a branch.
+constexpr int kBufferFlags = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x80000000u;
+typedef unsigned int b64_t __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ int wave_bcast(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Hash loads bypass the per-CU cache: other waves of the same launch insert keys.
 __device__ __forceinline__ unsigned long long load_key(const unsigned long long *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint32_t load_val(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Wave-cooperative find-or-insert of `key` (wave-uniform) in the block hash.
-// The 64 lanes probe 64 consecutive slots per step; the first slot in probe
-// order that holds the key or is empty decides.  Returns the pool slot, or
-// kInvalidSlot after recording an overflow in the error word.
-__device__ uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key)
+// The 64 lanes look at 64 consecutive slots per step; the first slot in probe
+// order that holds the key or is empty decides.  (k0, v0) is the first window,
+// loaded by the caller ahead of time so that its latency overlaps the depth
+// gathers.  Returns the pool slot, or kInvalidSlot after recording an overflow
+// in the error word.
+__device__ uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key, uint32_t h,
+                                   unsigned long long k0, uint32_t v0)
 {
     const int lane = lane_id();
     const uint32_t mask = dm.hash_mask;
-    const uint32_t h = (uint32_t)hash_key(key) & mask;
     uint32_t fresh = kInvalidSlot;   // pool slot reserved for an insert (wave-uniform)
     uint32_t base = 0;
+    unsigned long long k = k0;
+    uint32_t v = v0;
+    bool loaded = true;
     while (base <= mask) {
-        const uint32_t pos = (h + base + (uint32_t)lane) & mask;
-        const unsigned long long k = load_key(&dm.keys[pos]);
+        if (!loaded) {
+            const uint32_t pos = (h + base + (uint32_t)lane) & mask;
+            k = load_key(&dm.keys[pos]);
+            v = load_val(&dm.vals[pos]);
+        }
+        loaded = false;
         const unsigned long long m_hit = __ballot(k == key);
         const unsigned long long m_free = __ballot(k == kEmptyKey);
         const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
         const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
         if (f_hit < f_free) {
-            const uint32_t at = (h + base + (uint32_t)f_hit) & mask;
-            uint32_t slot = 0;
-            if (lane == 0) {
-                // a key is published before its value; wait (bounded) for the value
-                slot = __hip_atomic_load(&dm.vals[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int spin = 0; slot == kInvalidSlot && spin < (1 << 20); ++spin)
-                    slot = __hip_atomic_load(&dm.vals[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (slot == kInvalidSlot)
-                    atomicOr(&dm.counters[kErrorBits], kErrInsertRace);
+            uint32_t slot = (uint32_t)__shfl((int)v, f_hit);
+            if (slot == kInvalidSlot) {
+                // a key is published before its value: wait (bounded) for the value
+                const uint32_t at = (h + base + (uint32_t)f_hit) & mask;
+                if (lane == 0) {
+                    for (int spin = 0; slot == kInvalidSlot && spin < (1 << 20); ++spin)
+                        slot = load_val(&dm.vals[at]);
+                    if (slot == kInvalidSlot)
+                        atomicOr(&dm.counters[kErrorBits], kErrInsertRace);
+                }
+                slot = (uint32_t)wave_bcast((int)slot);
             }
-            return (uint32_t)wave_bcast((int)slot);
+            return slot;
         }
         if (f_free == 64) {
             base += 64;
@@ -91,8 +115,6 @@ __device__ uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key)
                     dm.slot_keys[fresh] = key;
                     __hip_atomic_store(&dm.vals[at], fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     won = 1;
-                } else if (prev == key) {
-                    won = 2;   // the same key landed concurrently: read it on the next probe
                 }
             }
         }
@@ -102,7 +124,7 @@ __device__ uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key)
             return kInvalidSlot;
         if (won == 1)
             return fresh;
-        // slot taken by another key (or by this key from elsewhere): probe this window again
+        // the slot went to another key (or to this key from elsewhere): reload this window
     }
     if (lane_id() == 0)
         atomicOr(&dm.counters[kErrorBits], kErrHashFull);
@@ -133,44 +155,31 @@ __device__ __forceinline__ bool block_in_view(const FrameArgs &fa, int bx, int b
              ((__ballot(out_n) & all) == all) || ((__ballot(out_f) & all) == all));
 }
 
-// Eq. (1)-(2) and the TSDF measurement for one voxel.  (ax, ay, az) are the
-// row partial sums R[r][0] px + R[r][1] py of the lane's column, shared by its
-// 8 voxels; adding R[r][2] pz and t[r] afterwards is the oracle's order
-// ((R0 px + R1 py) + R2 pz) + t.
-template <int WEIGHTING>
-__device__ __forceinline__ bool measure(const FrameArgs &fa, const float *__restrict__ depth,
-                                        float ax, float ay, float az, float pz, float &x, float &w)
+// Appends n pending touched slots of one wave (lane i holds the i-th) at
+// `base` of sub-list `sub`.
+__device__ __forceinline__ void write_touched(const DeviceMap &dm, int sub, uint32_t base, uint32_t pending, int n)
 {
-    const float xc = (ax + fa.R[2] * pz) + fa.t[0];
-    const float yc = (ay + fa.R[5] * pz) + fa.t[1];
-    const float zc = (az + fa.R[8] * pz) + fa.t[2];
-    if (!(zc > 0.0f))
-        return false;
-    const float r = 1.0f / zc;
-    const float u = fa.fx * (xc * r) + fa.cx;
-    const float v = fa.fy * (yc * r) + fa.cy;
-    if (!(u >= 0.0f && u < fa.width_f && v >= 0.0f && v < fa.height_f))
-        return false;
-    const int i = (int)u;
-    const int j = (int)v;
-    const float d = depth[(size_t)j * (size_t)fa.width + (size_t)i];
-    if (!(d > 0.0f && d <= fa.d_max))
-        return false;
-    const float dp = d - zc;
-    if (!(dp >= -fa.eps))
-        return false;
-    float wm = 1.0f;
-    if (WEIGHTING == 1 && dp < -fa.delta)
-        wm = (fa.eps + dp) * fa.span_inv;
-    if (!(wm > 0.0f))
-        return false;
-    x = dp < fa.eps ? dp : fa.eps;
-    w = wm;
-    return true;
+    const int lane = lane_id();
+    if (lane < n) {
+        const uint32_t at = base + (uint32_t)lane;
+        if (at < dm.block_cap)
+            dm.touched[(size_t)sub * dm.block_cap + at] = pending;
+        else
+            atomicOr(&dm.counters[kErrorBits], kErrTouchedOverflow);
+    }
+}
+
+// A wave whose private list is full reserves room on its own (rare).
+__device__ __forceinline__ void flush_wave(const DeviceMap &dm, int parity, int sub, uint32_t pending, int n)
+{
+    uint32_t base = 0;
+    if (lane_id() == 0)
+        base = atomicAdd(&dm.counters[touched_counter(parity, sub)], (uint32_t)n);
+    write_touched(dm, sub, (uint32_t)wave_bcast((int)base), pending, n);
 }
 
 template <int WEIGHTING>
-__global__ __launch_bounds__(256) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa,
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa,
                                                               const float *__restrict__ depth)
 {
     const int lane = lane_id();
@@ -180,6 +189,27 @@ __global__ __launch_bounds__(256) void integrate_depth_kernel(DeviceMap dm, Fram
     const uint32_t stride = gridDim.x * kWavesPerGroup;
     const uint32_t n_lat = (uint32_t)fa.n_lat;          // the host keeps it below 2^31
     const uint32_t dim_x = (uint32_t)fa.lat_dim[0], dim_y = (uint32_t)fa.lat_dim[1];
+    const uint32_t width = (uint32_t)fa.width;
+
+    const __amdgpu_buffer_rsrc_t depth_rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)depth, (short)0, (int)(4u * width * (uint32_t)fa.height), kBufferFlags);
+    const int parity = fa.parity;
+    const int sub = (int)(blockIdx.x % kSubLists);
+    __shared__ uint32_t s_count[kWavesPerGroup];
+    __shared__ uint32_t s_updates[kWavesPerGroup];
+    __shared__ uint32_t s_base;
+
+    // The previous frame (stream-ordered, complete) used the other parity:
+    // fold its touched count into the running total and clear it for the next frame.
+    if (blockIdx.x == 0 && threadIdx.x < kSubLists) {
+        const uint32_t prev = atomicExch(&dm.counters[touched_counter(parity ^ 1, (int)threadIdx.x)], 0u);
+        if (prev != 0)
+            atomicAdd(&dm.totals[kTotalTouched], (unsigned long long)prev);
+    }
+
+    uint32_t pending = kInvalidSlot;   // wave-local touched list: lane i holds entry i
+    int n_pending = 0;                 // wave-uniform
+    uint32_t n_updates = 0;            // wave-uniform
 
     for (uint32_t lb = blockIdx.x * kWavesPerGroup + (uint32_t)wave; lb < n_lat; lb += stride) {
         const uint32_t rest = lb / dim_x;
@@ -189,69 +219,119 @@ __global__ __launch_bounds__(256) void integrate_depth_kernel(DeviceMap dm, Fram
         if (!block_in_view(fa, bx, by, bz))
             continue;
 
-        // voxel centres: ((float)g + 0.5) * voxel_size
+        // first hash probe window, consumed only if the block is touched
+        const unsigned long long key = pack_key(bx, by, bz);
+        const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
+        const uint32_t pos0 = (h + (uint32_t)lane) & dm.hash_mask;
+        const unsigned long long k0 = load_key(&dm.keys[pos0]);
+        const uint32_t v0 = load_val(&dm.vals[pos0]);
+
+        // Eq. (1)-(2) for the lane's 8 voxels.  Voxel centre p = ((float)g + 0.5) * vs;
+        // p_C = ((R0 px + R1 py) + R2 pz) + t, the first sum shared by the column.
         const float px = ((float)(8 * bx + lx) + 0.5f) * fa.vs;
         const float py = ((float)(8 * by + ly) + 0.5f) * fa.vs;
         const float ax = fa.R[0] * px + fa.R[1] * py;
         const float ay = fa.R[3] * px + fa.R[4] * py;
         const float az = fa.R[6] * px + fa.R[7] * py;
+        float zc[8];
+        uint32_t pix_off[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const float pz = ((float)(8 * bz + s) + 0.5f) * fa.vs;
+            const float xc = (ax + fa.R[2] * pz) + fa.t[0];
+            const float yc = (ay + fa.R[5] * pz) + fa.t[1];
+            zc[s] = (az + fa.R[8] * pz) + fa.t[2];
+            const float r = 1.0f / zc[s];
+            const float u = fa.fx * (xc * r) + fa.cx;
+            const float v = fa.fy * (yc * r) + fa.cy;
+            // nearest pixel: (i, j) covers [i, i+1) x [j, j+1); a voxel outside the
+            // image gets an out-of-range offset, whose buffer load returns 0 (invalid)
+            const bool ok = zc[s] > 0.0f && u >= 0.0f && u < fa.width_f && v >= 0.0f && v < fa.height_f;
+            const uint32_t i = (uint32_t)(ok ? u : 0.0f);
+            const uint32_t j = (uint32_t)(ok ? v : 0.0f);
+            pix_off[s] = ok ? 4u * (j * width + i) : kOutOfRange;
+        }
+        // all 8 gathers in flight together
+        float d[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            d[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(depth_rsrc, pix_off[s], 0, 0));
+
+        // TSDF measurement: valid depth, truncation band, weight
         float xs[8], ws[8];
         uint32_t hit = 0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const float pz = ((float)(8 * bz + s) + 0.5f) * fa.vs;
-            xs[s] = 0.0f;
-            ws[s] = 0.0f;
-            if (measure<WEIGHTING>(fa, depth, ax, ay, az, pz, xs[s], ws[s]))
-                hit |= 1u << s;
+            const float dp = d[s] - zc[s];
+            float wm = 1.0f;
+            if (WEIGHTING == 1 && dp < -fa.delta)
+                wm = (fa.eps + dp) * fa.span_inv;
+            const bool upd = d[s] > 0.0f && d[s] <= fa.d_max && dp >= -fa.eps && wm > 0.0f;
+            xs[s] = dp < fa.eps ? dp : fa.eps;
+            ws[s] = wm;
+            hit |= (upd ? 1u : 0u) << s;
         }
         if (__ballot(hit != 0) == 0ull)
             continue;
 
-        const uint32_t slot = find_or_insert(dm, pack_key(bx, by, bz));
+        const uint32_t slot = (uint32_t)wave_bcast((int)find_or_insert(dm, key, h, k0, v0));
         if (slot == kInvalidSlot)
             continue;
 
-        float2 *vox = dm.pool + (size_t)slot * kBlockVoxels + lane;
-        int n_upd = 0;
+        // weighted average with capped weight on coalesced 512-byte slabs; lanes
+        // whose voxel is not updated use an out-of-range offset (no load, no store)
+        const __amdgpu_buffer_rsrc_t blk = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(dm.pool + (size_t)slot * kBlockVoxels), (short)0, kBlockVoxels * 8, kBufferFlags);
+        uint32_t off[8];
+        float2 dw[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            const unsigned long long m = __ballot((hit >> s) & 1u);
-            n_upd += __popcll(m);
-            if ((hit >> s) & 1u) {
-                float2 dw = vox[64 * s];
-                const float n = dw.x * dw.y + xs[s] * ws[s];
-                const float sum = dw.y + ws[s];
-                dw.x = n / sum;
-                dw.y = sum < fa.w_max ? sum : fa.w_max;
-                vox[64 * s] = dw;
-            }
+            off[s] = ((hit >> s) & 1u) ? 8u * (uint32_t)(64 * s + lane) : kOutOfRange;
+            dw[s] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(blk, off[s], 0, 0));
         }
-        if (lane == 0) {
-            const uint32_t at = atomicAdd(&dm.counters[kTouched], 1u);
-            if (at < dm.block_cap)
-                dm.touched[at] = slot;
-            else
-                atomicOr(&dm.counters[kErrorBits], kErrTouchedOverflow);
-            atomicAdd(&dm.totals[0], (unsigned long long)n_upd);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            // D <- (D W + x w) / (W + w),  W <- min(W + w, w_max)
+            const float n = dw[s].x * dw[s].y + xs[s] * ws[s];
+            const float sum = dw[s].y + ws[s];
+            dw[s].x = n / sum;
+            dw[s].y = sum < fa.w_max ? sum : fa.w_max;
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            n_updates += (uint32_t)__popcll(__ballot((hit >> s) & 1u));
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, dw[s]), blk, off[s], 0, 0);
+        }
+        // touched-block compaction: the wave keeps its list in one register
+        if (lane == n_pending)
+            pending = slot;
+        if (++n_pending == 64) {
+            flush_wave(dm, parity, sub, pending, n_pending);
+            n_pending = 0;
         }
     }
-
-    // The last workgroup to finish publishes the frame's touched count and
-    // clears the per-frame counters for the next launch.
+    // Workgroup compaction of the touched list: prefix sum over the waves'
+    // counts, one atomic per workgroup on its sub-list counter.
+    if (lane == 0) {
+        s_count[wave] = (uint32_t)n_pending;
+        s_updates[wave] = n_updates;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t done = atomicAdd(&dm.counters[kGroupsDone], 1u);
-        if (done == gridDim.x - 1) {
-            __threadfence();
-            const uint32_t n = atomicAdd(&dm.counters[kTouched], 0u);
-            atomicExch(&dm.counters[kTouchedLast], n < dm.block_cap ? n : dm.block_cap);
-            atomicAdd(&dm.totals[1], (unsigned long long)n);
-            atomicExch(&dm.counters[kTouched], 0u);
-            atomicExch(&dm.counters[kGroupsDone], 0u);
+        uint32_t total = 0, upd = 0;
+        for (int k = 0; k < kWavesPerGroup; ++k) {
+            total += s_count[k];
+            upd += s_updates[k];
         }
+        s_base = total ? atomicAdd(&dm.counters[touched_counter(parity, sub)], total) : 0u;
+        if (upd)
+            atomicAdd(&dm.totals[kTotalUpdates + sub * kTotalsStride], (unsigned long long)upd);
     }
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < wave; ++k)
+        before += s_count[k];
+    write_touched(dm, sub, s_base + before, pending, n_pending);
 }
 
 }  // namespace

@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void query_tsdf_kernel(DeviceMap dm, const int
                                                          float *__restrict__ weight)
 {
     const int lane = lane_id();
-    const long long stride = (long long)gridDim.x * kWavesPerGroup;
-    for (long long b = (long long)blockIdx.x * kWavesPerGroup + (threadIdx.x >> 6); b < n; b += stride) {
+    const long long stride = (long long)gridDim.x * kQueryWavesPerGroup;
+    for (long long b = (long long)blockIdx.x * kQueryWavesPerGroup + (threadIdx.x >> 6); b < n; b += stride) {
         const int x = xyz[3 * b], y = xyz[3 * b + 1], z = xyz[3 * b + 2];
         const bool in_range = x >= -kBlockCoordMax && x <= kBlockCoordMax && y >= -kBlockCoordMax &&
                               y <= kBlockCoordMax && z >= -kBlockCoordMax && z <= kBlockCoordMax;
@@ -70,12 +70,13 @@ __global__ void decode_keys_kernel(const unsigned long long *__restrict__ keys, 
     }
 }
 
-__global__ void gather_touched_kernel(DeviceMap dm, long long n, int32_t *__restrict__ xyz)
+__global__ void gather_touched_kernel(DeviceMap dm, int sub, long long n, int32_t *__restrict__ xyz)
 {
+    const uint32_t *list = dm.touched + (size_t)sub * dm.block_cap;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         int x, y, z;
-        unpack_key(dm.slot_keys[dm.touched[i]], x, y, z);
+        unpack_key(dm.slot_keys[list[i]], x, y, z);
         xyz[3 * i] = x;
         xyz[3 * i + 1] = y;
         xyz[3 * i + 2] = z;
@@ -97,7 +98,7 @@ int grid_for(long long n, int per_group)
 hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
                              float *weight, hipStream_t stream)
 {
-    hipLaunchKernelGGL(query_tsdf_kernel, dim3(grid_for(n, kWavesPerGroup)), dim3(64 * kWavesPerGroup), 0,
+    hipLaunchKernelGGL(query_tsdf_kernel, dim3(grid_for(n, kQueryWavesPerGroup)), dim3(64 * kQueryWavesPerGroup), 0,
                        stream, dm, xyz, n, dist, weight);
     return hipGetLastError();
 }
@@ -108,9 +109,9 @@ hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32
     return hipGetLastError();
 }
 
-hipError_t launch_gather_touched(const DeviceMap &dm, long long n, int32_t *xyz, hipStream_t stream)
+hipError_t launch_gather_touched(const DeviceMap &dm, int sub, long long n, int32_t *xyz, hipStream_t stream)
 {
-    hipLaunchKernelGGL(gather_touched_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, dm, n, xyz);
+    hipLaunchKernelGGL(gather_touched_kernel, dim3(grid_for(n, 256)), dim3(256), 0, stream, dm, sub, n, xyz);
     return hipGetLastError();
 }
 

@@ -12,16 +12,28 @@ constexpr int kBlockVoxels = 512;                   // 8 x 8 x 8 voxels per bloc
 constexpr int kKeyBits = 21;                        // bits per packed block coordinate
 constexpr int kKeyOffset = 1 << 20;                 // block coordinate bias
 constexpr int kBlockCoordMax = (1 << 20) - 1;       // |block index| limit on every axis
-constexpr int kWavesPerGroup = 4;                   // 256-thread workgroups of wave64
+constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of wave64
+constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
+constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
+constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
-// Indices into the per-map counter words.
+// Counter words, one hot counter per 128-byte line so that atomics on
+// different counters never share a line.
 enum Counter : int {
-    kNumBlocks = 0,     // pool slots handed out (may exceed capacity after an overflow)
-    kTouched = 1,       // touched blocks of the frame in flight
-    kGroupsDone = 2,    // workgroups of the frame in flight that have finished
-    kTouchedLast = 3,   // touched blocks of the last completed frame
-    kErrorBits = 4,     // sticky ErrorBits
-    kNumCounters = 8
+    kNumBlocks = 0,                                  // pool slots handed out (may exceed capacity after overflow)
+    kErrorBits = 1 * kLineWords,                     // sticky ErrorBits
+    kTouchedBase = 2 * kLineWords,                   // [parity][sub-list] touched counts
+    kNumCounterWords = (2 + 2 * kSubLists) * kLineWords
+};
+__host__ __device__ constexpr int touched_counter(int parity, int sub)
+{
+    return kTouchedBase + (parity * kSubLists + sub) * kLineWords;
+}
+constexpr int kTotalsStride = 16;                   // 64-bit words per 128-byte line
+enum Total : int {
+    kTotalUpdates = 0,                               // kSubLists lines of voxel-update sub-totals
+    kTotalTouched = kSubLists * kTotalsStride,       // touched blocks of completed earlier frames
+    kNumTotalWords = (kSubLists + 1) * kTotalsStride
 };
 
 enum ErrorBits : uint32_t {
@@ -37,9 +49,9 @@ struct DeviceMap {
     uint32_t *vals;                  // [hash_mask + 1] pool slot of the key, kInvalidSlot until published
     float2 *pool;                    // [block_cap * 512] (distance, weight) per voxel
     unsigned long long *slot_keys;   // [block_cap] key of each pool slot
-    uint32_t *touched;               // [block_cap] pool slots touched by the last frame
-    uint32_t *counters;              // [kNumCounters]
-    unsigned long long *totals;      // [2] running totals: voxel updates, touched blocks
+    uint32_t *touched;               // [kSubLists][block_cap] pool slots touched by the last frame
+    uint32_t *counters;              // [kNumCounterWords]
+    unsigned long long *totals;      // [kNumTotalWords] running totals
     uint32_t hash_mask;
     uint32_t block_cap;
 };
@@ -62,6 +74,7 @@ struct FrameArgs {
     int lat_min[3];         // block lattice scanned by the frame (inclusive lower corner)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2]
+    int parity;             // frame counter & 1: selects this frame's touched counters
 };
 
 __host__ __device__ inline unsigned long long pack_key(int x, int y, int z)
@@ -97,7 +110,7 @@ hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long 
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
                               hipStream_t stream);
-hipError_t launch_gather_touched(const DeviceMap &dm, long long n, int32_t *xyz, hipStream_t stream);
+hipError_t launch_gather_touched(const DeviceMap &dm, int sub, long long n, int32_t *xyz, hipStream_t stream);
 hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n,
                      hipStream_t stream);
 
