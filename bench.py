@@ -27,7 +27,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "integrate_depth_cluttered_room_pmc.json")
-KERNEL_SOURCES = ["paper_2311_00626_amd/csrc/integrate.hip", "paper_2311_00626_amd/csrc/tsdf_internal.hpp"]
+KERNEL_SOURCES = ["paper_2311_00626_amd/csrc/integrate.hip", "paper_2311_00626_amd/csrc/device_common.hpp",
+                  "paper_2311_00626_amd/csrc/tsdf_internal.hpp"]
 
 
 def log(*a):
@@ -44,9 +45,10 @@ def kernel_source_hash() -> str:
 
 def algorithmic_bytes(updates: int, touched: int, new_blocks: int, pixels: int, frames: int) -> int:
     """Bytes the method must move: one (distance, weight) read and write per
-    voxel update (16 B), one read of every depth pixel per frame (4 B), a hash
+    updated voxel (16 B), one read of every depth pixel per frame (4 B), a hash
     key and value read per touched block (12 B) plus its touched-list entry
-    (4 B), and a key, value and slot key per new block (20 B)."""
+    (4 B), and a key, value and slot key per new block (20 B).  For a batched
+    launch the voxel term counts each voxel once per launch (voxel writes)."""
     return 16 * updates + 4 * pixels * frames + 16 * touched + 20 * new_blocks
 
 
@@ -85,6 +87,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=16, help="views per launch of the batched leg (1 = skip it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (PMC scaling)")
     args = ap.parse_args()
@@ -108,11 +111,16 @@ def main():
     K = w.camera.K
     poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
 
+    def counters(m):
+        st = m.full_stats()
+        return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
+
+    # ---- plain path: one integrate_depth launch per frame -------------------
     m = TsdfMap.from_params(w.params, block_capacity=1 << 16)
     for k in range(args.warmup):
         m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
     torch.cuda.synchronize()
-    b0, u0, t_0 = m.counters()
+    b0, u0, w0_, t_0 = counters(m)
     m.profile(True)
 
     torch.cuda.synchronize()
@@ -124,7 +132,7 @@ def main():
 
     kernel_ms, launches = m.profile_read()
     m.profile(False)
-    b1, u1, t_1 = m.counters()
+    b1, u1, w1_, t_1 = counters(m)
     assert m.status() == 0, "map overflowed"
     elapsed = t_end - t_start
     updates = u1 - u0
@@ -134,6 +142,41 @@ def main():
     alg_per_launch = alg / args.steps
     mean_kernel_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = alg_per_launch / mean_kernel_s / 1e9
+    del m
+
+    # ---- batched path: integrate_depth_views, several frames per launch ------
+    batched = None
+    if args.batch > 1:
+        B = args.batch
+        mb = TsdfMap.from_params(w.params, block_capacity=1 << 16)
+        first = n_frames % B or B           # warm-up batch, so that the rest splits evenly
+        mb.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
+        torch.cuda.synchronize()
+        bb0, ub0, wb0, tb0 = counters(mb)
+        mb.profile(True)
+        torch.cuda.synchronize()
+        tb_start = time.perf_counter()
+        for a in range(first, n_frames, B):
+            mb.integrate_depth_views([frames[k] for k in range(a, a + B)], [K] * B, poses[a:a + B])
+        torch.cuda.synchronize()
+        tb_end = time.perf_counter()
+        kms, kl = mb.profile_read()
+        mb.profile(False)
+        bb1, ub1, wb1, tb1 = counters(mb)
+        assert mb.status() == 0, "map overflowed"
+        nfb = n_frames - first
+        eb = tb_end - tb_start
+        alg_b = (16 * (wb1 - wb0) + 4 * H * W * nfb + 16 * (tb1 - tb0) + 20 * (bb1 - bb0)) / max(kl, 1)
+        kb = kms / 1e3 / max(kl, 1)
+        batched = {"views_per_launch": B, "frames": nfb, "launches": kl,
+                   "value": (ub1 - ub0) / eb, "unit": "voxel updates/s",
+                   "frames_per_s": nfb / eb, "ms_per_launch": eb / kl * 1e3,
+                   "voxel_updates": ub1 - ub0, "voxel_writes": wb1 - wb0,
+                   "roofline": {"bound": "hbm", "achieved": alg_b / kb / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": alg_b / kb / 1e9 / HBM_PEAK_GBS,
+                                "kernel": "integrate_views_kernel", "kernel_ms_mean": kb * 1e3,
+                                "algorithmic_bytes_per_launch": alg_b}}
+        del mb
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
@@ -168,6 +211,8 @@ def main():
                      "kernel": "integrate_depth_kernel", "kernel_ms_mean": mean_kernel_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches},
     }
+    if batched is not None:
+        result["batched"] = batched
     if not args.skip_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, frames_host, args.cpu_budget)
     print(json.dumps(result), flush=True)

@@ -108,6 +108,30 @@ TSDF_API int destroy_map(tsdf_map *m);
 TSDF_API int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height,
                     const float K[4], const float T_world_cam[16], void *hip_stream);
 
+/* One depth view of a batch: a depth image, its sensor model and its pose,
+ * with the same meaning and constraints as the arguments of integrate_depth. */
+#define TSDF_MAX_VIEWS 16
+#define TSDF_MODEL_PINHOLE 0
+typedef struct {
+    const float *depth_dev;    /* device float32[height][width], z-depth in metres */
+    int width, height;
+    int model;                 /* TSDF_MODEL_PINHOLE */
+    float max_range_m;         /* valid measurements are <= this; 0 = the map's max range */
+    float K[4];                /* fx, fy, cx, cy */
+    float reserved;            /* must be 0 */
+    float reserved2;           /* must be 0 */
+    float T_world_cam[16];     /* row-major rigid pose */
+} tsdf_depth_view;
+
+/* Fuses n_views (1 .. TSDF_MAX_VIEWS) depth views in one launch.  The map
+ * afterwards is bit-identical to calling integrate_depth on views[0],
+ * views[1], ... in that order (§IV-B applied per view, per voxel, in order);
+ * the views may be consecutive frames of one camera or the cameras of a rig,
+ * of different sizes.  Each voxel's state is read once and written once per
+ * call.  The touched list (query_touched) holds the blocks updated by any of
+ * the views.  Only enqueues work; errors as integrate_depth. */
+TSDF_API int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream);
+
 /* Writes the indices of all allocated blocks, sorted ascending by (x, y, z),
  * as int32 triples to out_xyz_dev (room for `capacity` blocks; min(count,
  * capacity) are written) and the total count to *out_count (host).
@@ -123,18 +147,23 @@ TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_
                float *out_dist_dev, float *out_weight_dev, void *hip_stream);
 
 /* Blocks with at least one voxel updated by the most recent integrate_depth
- * call (the "updated blocks" that downstream layers consume, §IV-C), in
+ * or integrate_depth_views call (the "updated blocks" that downstream layers consume, §IV-C), in
  * unspecified order, as int32 triples; same capacity / count contract as
  * query_blocks.  Synchronises hip_stream. */
 TSDF_API int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
                   void *hip_stream);
 
-/* Number of allocated blocks, the running total of voxel updates (one per
- * voxel per frame in which it was updated) and the running total of touched
- * blocks (one per block per frame in which any of its voxels was updated).
- * Synchronises hip_stream. */
-TSDF_API int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates,
-                       long long *n_touched_blocks, void *hip_stream);
+/* Running counters of a map. */
+typedef struct {
+    long long blocks;          /* allocated blocks */
+    long long voxel_updates;   /* one per voxel per view that updated it */
+    long long voxel_writes;    /* one per voxel per call that updated it (stores to the pool) */
+    long long touched_blocks;  /* one per block per call in which any of its voxels was updated */
+    long long launches;        /* integration calls enqueued */
+} tsdf_stats;
+
+/* Fills *out.  Synchronises hip_stream. */
+TSDF_API int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream);
 
 /* Sticky device-side status: TSDF_OK or TSDF_EFULL.  Synchronises the device. */
 TSDF_API int map_status(tsdf_map *m);

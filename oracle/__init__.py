@@ -35,6 +35,8 @@ def _load():
     lib.ora_destroy.argtypes = [C.c_void_p]
     lib.ora_integrate_depth.restype = C.c_longlong
     lib.ora_integrate_depth.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
+    lib.ora_integrate_depth_range.restype = C.c_longlong
+    lib.ora_integrate_depth_range.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p, C.c_float]
     lib.ora_num_blocks.restype = C.c_longlong
     lib.ora_num_blocks.argtypes = [C.c_void_p]
     lib.ora_blocks.argtypes = [C.c_void_p, i32p]
@@ -85,10 +87,15 @@ class OracleMap:
             _lib.ora_destroy(h)
             self._h = None
 
-    def integrate(self, depth: np.ndarray, K, T_world_cam) -> int:
+    def integrate(self, depth: np.ndarray, K, T_world_cam, max_range: float = 0.0) -> int:
+        """One frame; max_range > 0 replaces the map's max range for it."""
         depth = _f32(depth)
         H, W = depth.shape
-        n = _lib.ora_integrate_depth(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16))
+        if max_range > 0:
+            n = _lib.ora_integrate_depth_range(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16),
+                                               max_range)
+        else:
+            n = _lib.ora_integrate_depth(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16))
         if n < 0:
             raise ValueError("oracle rejected the frame")
         return int(n)

@@ -212,6 +212,18 @@ long long ora_integrate_depth(ora_map *m, const float *depth, int width, int hei
                               : integrate_f64(m, depth, width, height, K, T);
 }
 
+long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, int height,
+                                    const float K[4], const float T[16], float max_range)
+{
+    if (!m || !(max_range > 0) || !isfinite(max_range))
+        return -1;
+    const float saved = m->p.max_range;
+    m->p.max_range = max_range;
+    const long long n = ora_integrate_depth(m, depth, width, height, K, T);
+    m->p.max_range = saved;
+    return n;
+}
+
 long long ora_num_blocks(const ora_map *m) { return m ? m->n_blocks : 0; }
 
 void ora_blocks(const ora_map *m, int32_t *xyz)

@@ -52,6 +52,9 @@ void ora_destroy(ora_map *m);
  * Returns the number of voxel updates, or -1 on bad arguments / no memory. */
 long long ora_integrate_depth(ora_map *m, const float *depth, int width, int height,
                               const float K[4], const float T_world_cam[16]);
+/* Same, with this frame's own max range (> 0) in place of the map's. */
+long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, int height,
+                                    const float K[4], const float T_world_cam[16], float max_range);
 
 long long ora_num_blocks(const ora_map *m);
 /* Block indices (x, y, z), 3 int32 per block, in insertion order. */

@@ -14,6 +14,9 @@
 
 using namespace tsdf;
 
+static_assert(TSDF_MAX_VIEWS == kMaxViews, "view batch limit");
+static_assert(sizeof(ViewsArgs) <= 4096, "kernel argument size");
+
 struct tsdf_map {
     tsdf_params p;
     int device;
@@ -120,42 +123,37 @@ void free_events(tsdf_map *m)
     m->ev_used = 0;
 }
 
-// Per-frame constants (the a1 step): camera-from-world pose, intrinsics,
-// truncation constants, and the block lattice that can hold updated voxels.
-int frame_args(const tsdf_map *m, int width, int height, const float K[4], const float T[16], FrameArgs &fa)
+// Per-view constants (the a1 step): camera-from-world pose and intrinsics,
+// plus the world box that holds every voxel the view can update.
+int camera_view(const tsdf_map *m, const float *depth, int width, int height, const float K[4],
+                const float T[16], float max_range, CameraView &cv, double lo[3], double hi[3])
 {
     // Inverse of the rigid pose: R^T exactly; each component of -R^T t is
     // accumulated in binary64 as ((R0i t0 + R1i t1) + R2i t2) and rounded once.
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-            fa.R[3 * i + j] = T[4 * j + i];
+            cv.R[3 * i + j] = T[4 * j + i];
     for (int i = 0; i < 3; ++i) {
         const double acc = ((double)T[0 * 4 + i] * (double)T[3] + (double)T[1 * 4 + i] * (double)T[7]) +
                            (double)T[2 * 4 + i] * (double)T[11];
-        fa.t[i] = (float)(-acc);
+        cv.t[i] = (float)(-acc);
     }
-    fa.fx = K[0];
-    fa.fy = K[1];
-    fa.cx = K[2];
-    fa.cy = K[3];
-    fa.width = width;
-    fa.height = height;
-    fa.width_f = (float)width;
-    fa.height_f = (float)height;
-    fa.vs = m->p.voxel_size_m;
-    fa.eps = m->eps;
-    fa.delta = m->delta;
-    fa.span_inv = m->span_inv;
-    fa.w_max = m->p.max_weight;
-    fa.d_max = m->p.max_range_m;
+    cv.fx = K[0];
+    cv.fy = K[1];
+    cv.cx = K[2];
+    cv.cy = K[3];
+    cv.width = width;
+    cv.height = height;
+    cv.width_f = (float)width;
+    cv.height_f = (float)height;
+    cv.depth = depth;
+    cv.d_max = max_range;
 
     // An updated voxel has 0 < z <= d + eps <= max_range + eps and projects
     // into the image: it lies in the pyramid of the camera centre and the
-    // image corners at that depth.  Its box, widened by a voxel, bounds the
-    // lattice.
-    const double vs = (double)m->p.voxel_size_m;
-    const double zfar = (double)m->p.max_range_m + (double)m->eps;
-    double lo[3], hi[3];
+    // image corners at that depth.
+    const double zfar = (double)max_range + (double)m->eps;
+    cv.zfar = (float)zfar;
     for (int a = 0; a < 3; ++a)
         lo[a] = hi[a] = (double)T[4 * a + 3];
     for (int c = 0; c < 4; ++c) {
@@ -170,28 +168,96 @@ int frame_args(const tsdf_map *m, int width, int height, const float K[4], const
             hi[a] = std::max(hi[a], w);
         }
     }
-    const double edge = 8.0 * vs;
     double extent = 0;
+    for (int a = 0; a < 3; ++a)
+        extent = std::max(extent, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+    // Culling slack: half a voxel plus a generous bound on binary32 rounding
+    // of coordinates of magnitude `extent`, scaled into each plane's units.
+    const double e = 0.5 * (double)m->p.voxel_size_m + 1e-5 * (1.0 + extent + zfar);
+    cv.margin_u = (float)(e * ((double)K[0] + std::fabs((double)K[2]) + (double)width));
+    cv.margin_v = (float)(e * ((double)K[1] + std::fabs((double)K[3]) + (double)height));
+    return TSDF_OK;
+}
+
+void map_consts(const tsdf_map *m, double max_extent, double max_zfar, MapConsts &mc)
+{
+    mc.vs = m->p.voxel_size_m;
+    mc.eps = m->eps;
+    mc.delta = m->delta;
+    mc.span_inv = m->span_inv;
+    mc.w_max = m->p.max_weight;
+    mc.margin_z = (float)(0.5 * (double)m->p.voxel_size_m + 1e-5 * (1.0 + max_extent + max_zfar));
+}
+
+// Block lattice of a world box, widened by one voxel.
+int lattice_of(const tsdf_map *m, const double lo[3], const double hi[3], Lattice &lat)
+{
+    const double vs = (double)m->p.voxel_size_m;
+    const double edge = 8.0 * vs;
     for (int a = 0; a < 3; ++a) {
         const double bl = std::floor((lo[a] - vs) / edge);
         const double bh = std::floor((hi[a] + vs) / edge);
         if (!(bl >= -kBlockCoordMax && bh <= kBlockCoordMax))
             return TSDF_EINVAL;
-        fa.lat_min[a] = (int)bl;
-        fa.lat_dim[a] = (int)(bh - bl) + 1;
-        extent = std::max(extent, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+        lat.lat_min[a] = (int)bl;
+        lat.lat_dim[a] = (int)(bh - bl) + 1;
     }
-    fa.n_lat = (long long)fa.lat_dim[0] * fa.lat_dim[1] * fa.lat_dim[2];
-    if (fa.n_lat >= (1ll << 31))
+    lat.n_lat = (long long)lat.lat_dim[0] * lat.lat_dim[1] * lat.lat_dim[2];
+    if (lat.n_lat >= (1ll << 31))
         return TSDF_EINVAL;
-    fa.zfar = (float)zfar;
-    // Culling slack: half a voxel plus a generous bound on binary32 rounding
-    // of coordinates of magnitude `extent`, scaled into each plane's units.
-    const double e = 0.5 * vs + 1e-5 * (1.0 + extent + zfar);
-    fa.margin_u = (float)(e * ((double)K[0] + std::fabs((double)K[2]) + (double)width));
-    fa.margin_v = (float)(e * ((double)K[1] + std::fabs((double)K[3]) + (double)height));
-    fa.margin_z = (float)e;
     return TSDF_OK;
+}
+
+double box_extent(const double lo[3], const double hi[3])
+{
+    double e = 0;
+    for (int a = 0; a < 3; ++a)
+        e = std::max(e, std::max(std::fabs(lo[a]), std::fabs(hi[a])));
+    return e;
+}
+
+// Argument checks shared by the integration entry points.
+bool view_args_valid(const float *depth_dev, int width, int height, const float K[4], const float T[16])
+{
+    if (!depth_dev || !K || !T || width <= 0 || height <= 0)
+        return false;
+    // byte offsets into the depth image must stay below 2^31 (buffer addressing)
+    if ((long long)width * (long long)height > (1ll << 28) || width > (1 << 24) || height > (1 << 24))
+        return false;
+    if (!finite_all(K, 4) || !(K[0] > 0) || !(K[1] > 0))
+        return false;
+    return pose_valid(T);
+}
+
+// Optional kernel timing around one launch.
+bool timing_begin(tsdf_map *m, hipStream_t s)
+{
+    if (!m->profiling || m->ev_used >= kMaxTimedLaunches)
+        return false;
+    if (m->ev_used == m->ev_start.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess)
+            return false;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return false;
+        }
+        m->ev_start.push_back(a);
+        m->ev_stop.push_back(b);
+    }
+    return hipEventRecord(m->ev_start[m->ev_used], s) == hipSuccess;
+}
+
+void timing_end(tsdf_map *m, hipStream_t s, bool timed)
+{
+    if (timed && hipEventRecord(m->ev_stop[m->ev_used], s) == hipSuccess)
+        ++m->ev_used;
+}
+
+int groups_for(const tsdf_map *m, long long n_lat)
+{
+    long long groups = (n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
+    return (int)std::max(1ll, std::min(groups, (long long)m->max_groups));
 }
 
 struct CounterSnapshot {
@@ -321,53 +387,79 @@ int destroy_map(tsdf_map *m)
 int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
                     const float T_world_cam[16], void *hip_stream)
 {
-    if (!m || !depth_dev || !K || !T_world_cam || width <= 0 || height <= 0)
-        return TSDF_EINVAL;
-    // byte offsets into the depth image must stay below 2^31 (buffer addressing)
-    if ((long long)width * (long long)height > (1ll << 28) || width > (1 << 24) || height > (1 << 24))
-        return TSDF_EINVAL;
-    if (!finite_all(K, 4) || !(K[0] > 0) || !(K[1] > 0))
-        return TSDF_EINVAL;
-    if (!pose_valid(T_world_cam))
+    if (!m || !view_args_valid(depth_dev, width, height, K, T_world_cam))
         return TSDF_EINVAL;
     if (m->sticky)
         return TSDF_ESTATE;
     FrameArgs fa;
-    int st = frame_args(m, width, height, K, T_world_cam, fa);
+    double lo[3], hi[3];
+    int st = camera_view(m, depth_dev, width, height, K, T_world_cam, m->p.max_range_m, fa.cam, lo, hi);
+    if (st == TSDF_OK)
+        st = lattice_of(m, lo, hi, fa.lat);
     if (st != TSDF_OK)
         return st;
+    map_consts(m, box_extent(lo, hi), (double)fa.cam.zfar, fa.mc);
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
-    long long groups = (fa.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
-    groups = std::max(1ll, std::min(groups, (long long)m->max_groups));
     hipError_t e = hipSetDevice(m->device);
     if (e != hipSuccess)
         return hip_status(e);
-    const bool timed = m->profiling && m->ev_used < kMaxTimedLaunches;
-    if (timed) {
-        if (m->ev_used == m->ev_start.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess)
-                return TSDF_EDEVICE;
-            if (hipEventCreate(&b) != hipSuccess) {
-                (void)hipEventDestroy(a);
-                return TSDF_EDEVICE;
-            }
-            m->ev_start.push_back(a);
-            m->ev_stop.push_back(b);
-        }
-        if (hipEventRecord(m->ev_start[m->ev_used], s) != hipSuccess)
-            return TSDF_EDEVICE;
-    }
-    e = launch_integrate_depth(m->dm, fa, m->p.weighting, depth_dev, (int)groups, s);
+    const bool timed = timing_begin(m, s);
+    e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups_for(m, fa.lat.n_lat), s);
     if (e != hipSuccess)
         return hip_status(e);
+    timing_end(m, s, timed);
     ++m->frames;
-    if (timed) {
-        if (hipEventRecord(m->ev_stop[m->ev_used], s) != hipSuccess)
-            return TSDF_EDEVICE;
-        ++m->ev_used;
+    return TSDF_OK;
+}
+
+int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream)
+{
+    if (!m || !views || n_views < 1 || n_views > TSDF_MAX_VIEWS)
+        return TSDF_EINVAL;
+    for (int v = 0; v < n_views; ++v) {
+        const tsdf_depth_view &w = views[v];
+        if (w.model != TSDF_MODEL_PINHOLE || w.reserved != 0.0f)
+            return TSDF_EINVAL;
+        if (!(w.max_range_m >= 0.0f && std::isfinite(w.max_range_m)))
+            return TSDF_EINVAL;
+        if (!view_args_valid(w.depth_dev, w.width, w.height, w.K, w.T_world_cam))
+            return TSDF_EINVAL;
     }
+    if (m->sticky)
+        return TSDF_ESTATE;
+    ViewsArgs va;
+    std::memset(&va, 0, sizeof(va));
+    double lo[3], hi[3], max_zfar = 0;
+    for (int v = 0; v < n_views; ++v) {
+        double vlo[3], vhi[3];
+        const float range = views[v].max_range_m > 0.0f ? views[v].max_range_m : m->p.max_range_m;
+        const int st = camera_view(m, views[v].depth_dev, views[v].width, views[v].height, views[v].K,
+                                   views[v].T_world_cam, range, va.cam[v], vlo, vhi);
+        max_zfar = std::max(max_zfar, (double)va.cam[v].zfar);
+        if (st != TSDF_OK)
+            return st;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = v == 0 ? vlo[a] : std::min(lo[a], vlo[a]);
+            hi[a] = v == 0 ? vhi[a] : std::max(hi[a], vhi[a]);
+        }
+    }
+    int st = lattice_of(m, lo, hi, va.lat);
+    if (st != TSDF_OK)
+        return st;
+    va.n_views = n_views;
+    map_consts(m, box_extent(lo, hi), max_zfar, va.mc);
+    va.parity = (int)(m->frames & 1);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(m->device);
+    if (e != hipSuccess)
+        return hip_status(e);
+    const bool timed = timing_begin(m, s);
+    e = launch_integrate_views(m->dm, va, m->p.weighting, groups_for(m, va.lat.n_lat), s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    timing_end(m, s, timed);
+    ++m->frames;
     return TSDF_OK;
 }
 
@@ -467,10 +559,9 @@ int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lo
     return m->sticky;
 }
 
-int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates, long long *n_touched_blocks,
-              void *hip_stream)
+int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream)
 {
-    if (!m || !n_blocks || !n_voxel_updates || !n_touched_blocks)
+    if (!m || !out)
         return TSDF_EINVAL;
     if (hipSetDevice(m->device) != hipSuccess)
         return TSDF_EDEVICE;
@@ -478,17 +569,21 @@ int map_stats(tsdf_map *m, long long *n_blocks, long long *n_voxel_updates, long
     int st = read_counters(m, cs, (hipStream_t)hip_stream);
     if (st != TSDF_OK)
         return st;
-    *n_blocks = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
-    unsigned long long upd = 0;
-    for (int k = 0; k < kSubLists; ++k)
+    unsigned long long upd = 0, wr = 0;
+    for (int k = 0; k < kSubLists; ++k) {
         upd += cs.t[kTotalUpdates + k * kTotalsStride];
+        wr += cs.t[kTotalWrites + k * kTotalsStride];
+    }
     long long per[kSubLists];
     last_touched_counts(m, cs, per);
     long long touched = (long long)cs.t[kTotalTouched];
     for (int k = 0; k < kSubLists; ++k)
         touched += per[k];
-    *n_voxel_updates = (long long)upd;
-    *n_touched_blocks = touched;
+    out->blocks = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
+    out->voxel_updates = (long long)upd;
+    out->voxel_writes = (long long)wr;
+    out->touched_blocks = touched;
+    out->launches = m->frames;
     return TSDF_OK;
 }
 

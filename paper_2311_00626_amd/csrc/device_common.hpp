@@ -1,0 +1,342 @@
+// Device-side building blocks shared by the integration kernels: wave
+// primitives, raw buffer access, the block hash (find / find-or-insert),
+// frustum culling of blocks, the per-voxel measurement of a pinhole depth
+// image and the touched-list compaction.
+//
+// Every floating-point statement in measure_pinhole and fuse is one IEEE
+// binary32 operation in the order the CPU oracle uses (files including this
+// header are compiled with -ffp-contract=off and correctly rounded division).
+#pragma once
+
+#include "tsdf_internal.hpp"
+
+namespace tsdf {
+namespace dev {
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ int wave_bcast(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Raw buffer descriptors (word 3 of the gfx9-family resource: 32-bit data
+// format).  A load whose offset is at or past num_records returns 0 and a
+// store there is dropped, which predicates memory per lane without a branch.
+constexpr int kBufferFlags = 0x00020000;
+constexpr uint32_t kOutOfRange = 0x80000000u;
+typedef unsigned int b64_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, kBufferFlags);
+}
+
+__device__ __forceinline__ float2 load_f2(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), r, off, 0, 0);
+}
+
+// Hash loads bypass the per-CU cache: other waves of the same launch insert keys.
+__device__ __forceinline__ unsigned long long load_key(const unsigned long long *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t load_val(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// First 64-slot probe window of a key (lane l reads slot h + l).
+struct ProbeWindow {
+    unsigned long long k;
+    uint32_t v;
+};
+
+__device__ __forceinline__ ProbeWindow load_window(const DeviceMap &dm, uint32_t h, uint32_t base)
+{
+    const uint32_t pos = (h + base + (uint32_t)lane_id()) & dm.hash_mask;
+    return ProbeWindow{load_key(&dm.keys[pos]), load_val(&dm.vals[pos])};
+}
+
+// Pool slot behind a hit found at window position f_hit (waits, bounded, for
+// a value that is published after its key).
+__device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t h, uint32_t base, int f_hit,
+                                               uint32_t v)
+{
+    uint32_t slot = (uint32_t)__shfl((int)v, f_hit);
+    if (slot == kInvalidSlot) {
+        const uint32_t at = (h + base + (uint32_t)f_hit) & dm.hash_mask;
+        if (lane_id() == 0) {
+            for (int spin = 0; slot == kInvalidSlot && spin < (1 << 20); ++spin)
+                slot = load_val(&dm.vals[at]);
+            if (slot == kInvalidSlot)
+                atomicOr(&dm.counters[kErrorBits], kErrInsertRace);
+        }
+        slot = (uint32_t)wave_bcast((int)slot);
+    }
+    return slot;
+}
+
+// Read-only lookup of `key` (wave-uniform) starting from a preloaded first
+// window: the pool slot, or kInvalidSlot if the key is absent.
+__device__ inline uint32_t find_block(const DeviceMap &dm, unsigned long long key, uint32_t h, ProbeWindow w)
+{
+    for (uint32_t base = 0; base <= dm.hash_mask; base += 64) {
+        if (base != 0)
+            w = load_window(dm, h, base);
+        const unsigned long long m_hit = __ballot(w.k == key);
+        const unsigned long long m_free = __ballot(w.k == kEmptyKey);
+        const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
+        const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
+        if (f_hit < f_free)
+            return (uint32_t)wave_bcast((int)slot_of_hit(dm, h, base, f_hit, w.v));
+        if (f_free < 64)
+            return kInvalidSlot;
+    }
+    return kInvalidSlot;
+}
+
+// Wave-cooperative find-or-insert of `key` (wave-uniform).  The 64 lanes look
+// at 64 consecutive slots per step; the first slot in probe order that holds
+// the key or is empty decides.  w is the first window, loaded ahead of time.
+// Returns the pool slot, or kInvalidSlot after recording an overflow.
+__device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key, uint32_t h, ProbeWindow w)
+{
+    const int lane = lane_id();
+    const uint32_t mask = dm.hash_mask;
+    uint32_t fresh = kInvalidSlot;   // pool slot reserved for an insert (wave-uniform)
+    uint32_t base = 0;
+    bool loaded = true;
+    while (base <= mask) {
+        if (!loaded)
+            w = load_window(dm, h, base);
+        loaded = false;
+        const unsigned long long m_hit = __ballot(w.k == key);
+        const unsigned long long m_free = __ballot(w.k == kEmptyKey);
+        const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
+        const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
+        if (f_hit < f_free)
+            return (uint32_t)wave_bcast((int)slot_of_hit(dm, h, base, f_hit, w.v));
+        if (f_free == 64) {
+            base += 64;
+            continue;
+        }
+        const uint32_t at = (h + base + (uint32_t)f_free) & mask;
+        int won = 0;
+        if (lane == 0) {
+            if (fresh == kInvalidSlot) {
+                fresh = atomicAdd(&dm.counters[kNumBlocks], 1u);
+                if (fresh >= dm.block_cap) {
+                    atomicOr(&dm.counters[kErrorBits], kErrPoolFull);
+                    fresh = kInvalidSlot;
+                }
+            }
+            if (fresh != kInvalidSlot) {
+                const unsigned long long prev = atomicCAS(&dm.keys[at], kEmptyKey, key);
+                if (prev == kEmptyKey) {
+                    dm.slot_keys[fresh] = key;
+                    __hip_atomic_store(&dm.vals[at], fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    won = 1;
+                }
+            }
+        }
+        fresh = (uint32_t)wave_bcast((int)fresh);
+        won = wave_bcast(won);
+        if (fresh == kInvalidSlot)
+            return kInvalidSlot;
+        if (won == 1)
+            return fresh;
+        // the slot went to another key (or to this key from elsewhere): reload this window
+    }
+    if (lane == 0)
+        atomicOr(&dm.counters[kErrorBits], kErrHashFull);
+    return kInvalidSlot;
+}
+
+// Block culling against a view's frustum.  Lane c (mod 8) evaluates corner c;
+// the block is dropped when all 8 corners are outside one plane by more than
+// the margin, which exceeds the binary32 error of any voxel's projection.
+__device__ __forceinline__ bool block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+{
+    const int c = lane_id() & 7;
+    const float X = (float)(8 * bx + ((c & 1) ? 8 : 0)) * mc.vs;
+    const float Y = (float)(8 * by + ((c & 2) ? 8 : 0)) * mc.vs;
+    const float Z = (float)(8 * bz + ((c & 4) ? 8 : 0)) * mc.vs;
+    const float xc = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
+    const float yc = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
+    const float zc = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
+    const bool out_l = cv.fx * xc + cv.cx * zc < -cv.margin_u;
+    const bool out_r = (cv.width_f - cv.cx) * zc - cv.fx * xc < -cv.margin_u;
+    const bool out_t = cv.fy * yc + cv.cy * zc < -cv.margin_v;
+    const bool out_b = (cv.height_f - cv.cy) * zc - cv.fy * yc < -cv.margin_v;
+    const bool out_n = zc < -mc.margin_z;
+    const bool out_f = zc > cv.zfar + mc.margin_z;
+    const unsigned long long all = 0xFFull;
+    return !(((__ballot(out_l) & all) == all) || ((__ballot(out_r) & all) == all) ||
+             ((__ballot(out_t) & all) == all) || ((__ballot(out_b) & all) == all) ||
+             ((__ballot(out_n) & all) == all) || ((__ballot(out_f) & all) == all));
+}
+
+// Eq. (1)-(2) and the TSDF measurement (§IV-B) of the lane's 8 voxels
+// (column (px, py), z-slabs of block row bz) against one pinhole view.
+// Returns the hit mask (bit s: voxel of slab s is updated) with the truncated
+// distance xs[s] and weight ws[s].  The 8 depth gathers are issued together;
+// a voxel outside the image reads through an out-of-range offset (value 0,
+// an invalid depth).
+template <int WEIGHTING>
+__device__ __forceinline__ uint32_t measure_pinhole(const CameraView &cv, const MapConsts &mc, float px, float py,
+                                                    int bz, float xs[8], float ws[8])
+{
+    const uint32_t width = (uint32_t)cv.width;
+    const __amdgpu_buffer_rsrc_t depth = make_rsrc(cv.depth, 4u * width * (uint32_t)cv.height);
+    // p_C = ((R0 px + R1 py) + R2 pz) + t; the first sum is shared by the column
+    const float ax = cv.R[0] * px + cv.R[1] * py;
+    const float ay = cv.R[3] * px + cv.R[4] * py;
+    const float az = cv.R[6] * px + cv.R[7] * py;
+    float zc[8];
+    uint32_t pix_off[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const float pz = ((float)(8 * bz + s) + 0.5f) * mc.vs;
+        const float xc = (ax + cv.R[2] * pz) + cv.t[0];
+        const float yc = (ay + cv.R[5] * pz) + cv.t[1];
+        zc[s] = (az + cv.R[8] * pz) + cv.t[2];
+        const float r = 1.0f / zc[s];
+        const float u = cv.fx * (xc * r) + cv.cx;
+        const float v = cv.fy * (yc * r) + cv.cy;
+        // nearest pixel: (i, j) covers [i, i+1) x [j, j+1)
+        const bool ok = zc[s] > 0.0f && u >= 0.0f && u < cv.width_f && v >= 0.0f && v < cv.height_f;
+        const uint32_t i = (uint32_t)(ok ? u : 0.0f);
+        const uint32_t j = (uint32_t)(ok ? v : 0.0f);
+        pix_off[s] = ok ? 4u * (j * width + i) : kOutOfRange;
+    }
+    float d[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        d[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(depth, pix_off[s], 0, 0));
+    uint32_t hit = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        // valid measurement, truncation band (skip below -eps), weight > 0
+        const float dp = d[s] - zc[s];
+        float wm = 1.0f;
+        if (WEIGHTING == 1 && dp < -mc.delta)
+            wm = (mc.eps + dp) * mc.span_inv;
+        const bool upd = d[s] > 0.0f && d[s] <= cv.d_max && dp >= -mc.eps && wm > 0.0f;
+        xs[s] = dp < mc.eps ? dp : mc.eps;
+        ws[s] = wm;
+        hit |= (upd ? 1u : 0u) << s;
+    }
+    return hit;
+}
+
+// Weighted average with capped weight (§IV-B):
+// D <- (D W + x w) / (W + w),  W <- min(W + w, w_max).
+__device__ __forceinline__ float2 fuse(float2 dw, float x, float w, float w_max)
+{
+    const float n = dw.x * dw.y + x * w;
+    const float sum = dw.y + w;
+    return make_float2(n / sum, sum < w_max ? sum : w_max);
+}
+
+// Touched-list compaction helpers.  Each wave keeps its touched pool slots in
+// one register (lane i holds entry i); a workgroup reserves room for all of its
+// waves with one atomic on its sub-list counter.
+__device__ __forceinline__ void write_touched(const DeviceMap &dm, int sub, uint32_t base, uint32_t pending, int n)
+{
+    const int lane = lane_id();
+    if (lane < n) {
+        const uint32_t at = base + (uint32_t)lane;
+        if (at < dm.block_cap)
+            dm.touched[(size_t)sub * dm.block_cap + at] = pending;
+        else
+            atomicOr(&dm.counters[kErrorBits], kErrTouchedOverflow);
+    }
+}
+
+// A wave whose private list is full reserves room on its own (rare).
+__device__ __forceinline__ void flush_wave(const DeviceMap &dm, int parity, int sub, uint32_t pending, int n)
+{
+    uint32_t base = 0;
+    if (lane_id() == 0)
+        base = atomicAdd(&dm.counters[touched_counter(parity, sub)], (uint32_t)n);
+    write_touched(dm, sub, (uint32_t)wave_bcast((int)base), pending, n);
+}
+
+// Records `slot` in the wave's private list.
+__device__ __forceinline__ void push_touched(const DeviceMap &dm, int parity, int sub, uint32_t slot,
+                                             uint32_t &pending, int &n_pending)
+{
+    if (lane_id() == n_pending)
+        pending = slot;
+    if (++n_pending == 64) {
+        flush_wave(dm, parity, sub, pending, n_pending);
+        n_pending = 0;
+    }
+}
+
+// End of a launch: prefix sum over the workgroup's waves, one atomic on the
+// sub-list counter, entries written; voxel-update counts summed likewise.
+template <int WAVES>
+__device__ __forceinline__ void finish_group(const DeviceMap &dm, int parity, int sub, uint32_t pending,
+                                             int n_pending, uint32_t n_updates, uint32_t n_writes)
+{
+    __shared__ uint32_t s_count[WAVES];
+    __shared__ uint32_t s_updates[WAVES];
+    __shared__ uint32_t s_writes[WAVES];
+    __shared__ uint32_t s_base;
+    const int wave = (int)(threadIdx.x >> 6);
+    if (lane_id() == 0) {
+        s_count[wave] = (uint32_t)n_pending;
+        s_updates[wave] = n_updates;
+        s_writes[wave] = n_writes;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t total = 0, upd = 0, wr = 0;
+        for (int k = 0; k < WAVES; ++k) {
+            total += s_count[k];
+            upd += s_updates[k];
+            wr += s_writes[k];
+        }
+        s_base = total ? atomicAdd(&dm.counters[touched_counter(parity, sub)], total) : 0u;
+        if (upd)
+            atomicAdd(&dm.totals[kTotalUpdates + sub * kTotalsStride], (unsigned long long)upd);
+        if (wr)
+            atomicAdd(&dm.totals[kTotalWrites + sub * kTotalsStride], (unsigned long long)wr);
+    }
+    __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < wave; ++k)
+        before += s_count[k];
+    write_touched(dm, sub, s_base + before, pending, n_pending);
+}
+
+// Start of a launch: the previous launch (stream-ordered, complete) counted
+// into the other parity; fold its touched count into the running total and
+// clear it for the next launch.
+__device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kSubLists) {
+        const uint32_t prev = atomicExch(&dm.counters[touched_counter(parity ^ 1, (int)threadIdx.x)], 0u);
+        if (prev != 0)
+            atomicAdd(&dm.totals[kTotalTouched], (unsigned long long)prev);
+    }
+}
+
+// Block index of lattice entry lb (x fastest).
+__device__ __forceinline__ void lattice_block(const Lattice &lat, uint32_t lb, int &bx, int &by, int &bz)
+{
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    const uint32_t rest = lb / dim_x;
+    bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+    by = lat.lat_min[1] + (int)(rest % dim_y);
+    bz = lat.lat_min[2] + (int)(rest / dim_y);
+}
+
+}  // namespace dev
+}  // namespace tsdf

@@ -1,0 +1,139 @@
+// Projective TSDF integration of a batch of depth views in one launch
+// (nvblox §IV-B applied to several frames or sensors at once).
+//
+// The result is bit-identical to integrating the views one after another in
+// array order: every voxel is owned by one wave, which loads its (distance,
+// weight) once, applies the views' updates in order in registers (each update
+// is the same sequence of binary32 operations as a single-frame launch) and
+// stores it once.  Block allocation follows the same rule as for one frame: a
+// block exists once any view updates any of its voxels.
+//
+// Per block of the union lattice of all views:
+//   1. culling against every view's frustum -> view mask (wave-uniform);
+//   2. view 0 of the mask is measured while the first hash window is in flight;
+//   3. the block is looked up; an existing block's 512 voxels are loaded while
+//      the next view is being measured (software pipeline of depth 2);
+//   4. each view's updates are fused in registers, in view order;
+//   5. a block with any updated voxel is inserted if new, the updated voxels
+//      are stored (buffer stores predicated per lane) and its pool slot joins
+//      the touched list.
+#include "device_common.hpp"
+
+namespace tsdf {
+namespace {
+
+using namespace dev;
+
+template <int WEIGHTING>
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
+{
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const int lx = lane & 7;
+    const int ly = lane >> 3;
+    const uint32_t stride = gridDim.x * kWavesPerGroup;
+    const uint32_t n_lat = (uint32_t)va.lat.n_lat;
+    const int parity = va.parity;
+    const int sub = (int)(blockIdx.x % kSubLists);
+    begin_launch(dm, parity);
+
+    uint32_t pending = kInvalidSlot;
+    int n_pending = 0;
+    uint32_t n_updates = 0;   // voxel updates, one per voxel per view
+    uint32_t n_writes = 0;    // voxels stored, one per voxel per launch
+
+    for (uint32_t lb = blockIdx.x * kWavesPerGroup + (uint32_t)wave; lb < n_lat; lb += stride) {
+        int bx, by, bz;
+        lattice_block(va.lat, lb, bx, by, bz);
+        uint32_t vmask = 0;
+        for (int v = 0; v < va.n_views; ++v)
+            if (block_in_view(va.cam[v], va.mc, bx, by, bz))
+                vmask |= 1u << v;
+        if (vmask == 0)
+            continue;
+
+        const unsigned long long key = pack_key(bx, by, bz);
+        const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
+        const ProbeWindow w0 = load_window(dm, h, 0);
+
+        const float px = ((float)(8 * bx + lx) + 0.5f) * va.mc.vs;
+        const float py = ((float)(8 * by + ly) + 0.5f) * va.mc.vs;
+
+        // view pipeline: (xa, wa, ha) holds the measured, not yet fused view
+        float xa[8], wa[8];
+        int v = __builtin_ctz(vmask);
+        uint32_t rest = vmask & (vmask - 1);
+        uint32_t ha = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xa, wa);
+
+        // state of an existing block, loaded while the next view is measured
+        const uint32_t found = find_block(dm, key, h, w0);
+        float2 dw[8];
+        if (found != kInvalidSlot) {
+            const __amdgpu_buffer_rsrc_t blk = make_rsrc(dm.pool + (size_t)found * kBlockVoxels, kBlockVoxels * 8u);
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                dw[s] = load_f2(blk, 8u * (uint32_t)(64 * s + lane));
+        } else {
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                dw[s] = make_float2(0.0f, 0.0f);
+        }
+
+        uint32_t any = 0;
+        while (true) {
+            float xb[8], wb[8];
+            uint32_t hb = 0;
+            const bool more = rest != 0;
+            if (more) {
+                v = __builtin_ctz(rest);
+                rest &= rest - 1;
+                hb = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xb, wb);
+            }
+            // fuse the pending view, in view order
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                n_updates += (uint32_t)__popcll(__ballot((ha >> s) & 1u));
+                if ((ha >> s) & 1u)
+                    dw[s] = fuse(dw[s], xa[s], wa[s], va.mc.w_max);
+            }
+            any |= ha;
+            if (!more)
+                break;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                xa[s] = xb[s];
+                wa[s] = wb[s];
+            }
+            ha = hb;
+        }
+        if (__ballot(any != 0) == 0ull)
+            continue;
+
+        const uint32_t slot = found != kInvalidSlot ? found : find_or_insert(dm, key, h, w0);
+        if (slot == kInvalidSlot)
+            continue;
+        const __amdgpu_buffer_rsrc_t blk = make_rsrc(dm.pool + (size_t)slot * kBlockVoxels, kBlockVoxels * 8u);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            n_writes += (uint32_t)__popcll(__ballot((any >> s) & 1u));
+            store_f2(blk, ((any >> s) & 1u) ? 8u * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
+        }
+        push_touched(dm, parity, sub, slot, pending, n_pending);
+    }
+    finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes);
+}
+
+}  // namespace
+
+hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
+                                  hipStream_t stream)
+{
+    const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
+    if (weighting == 1)
+        hipLaunchKernelGGL(integrate_views_kernel<1>, grid, block, 0, stream, dm, va);
+    else
+        hipLaunchKernelGGL(integrate_views_kernel<0>, grid, block, 0, stream, dm, va);
+    return hipGetLastError();
+}
+
+}  // namespace tsdf

@@ -32,8 +32,9 @@ __host__ __device__ constexpr int touched_counter(int parity, int sub)
 constexpr int kTotalsStride = 16;                   // 64-bit words per 128-byte line
 enum Total : int {
     kTotalUpdates = 0,                               // kSubLists lines of voxel-update sub-totals
-    kTotalTouched = kSubLists * kTotalsStride,       // touched blocks of completed earlier frames
-    kNumTotalWords = (kSubLists + 1) * kTotalsStride
+    kTotalWrites = kSubLists * kTotalsStride,        // kSubLists lines of voxel-write sub-totals
+    kTotalTouched = 2 * kSubLists * kTotalsStride,   // touched blocks of completed earlier launches
+    kNumTotalWords = (2 * kSubLists + 1) * kTotalsStride
 };
 
 enum ErrorBits : uint32_t {
@@ -56,25 +57,52 @@ struct DeviceMap {
     uint32_t block_cap;
 };
 
-// Per-frame constants (host-computed, passed by value).
-struct FrameArgs {
+// One pinhole depth image and its pose (host-computed, passed by value).
+struct CameraView {
     float R[9];             // camera-from-world rotation, row-major (T_CL of Eq. (1))
     float t[3];             // camera-from-world translation
     float fx, fy, cx, cy;   // pinhole intrinsics (Eq. (2))
     float width_f, height_f;
     int width, height;
+    const float *depth;     // device float32[height][width]
+    float d_max;            // max valid measurement of this view
+    float zfar;             // no voxel beyond camera depth zfar can be updated
+    float margin_u, margin_v;   // conservative slack of the side culling planes
+};
+
+// Per-map constants in binary32.
+struct MapConsts {
     float vs;               // voxel edge
     float eps;              // truncation distance epsilon
     float delta;            // start of the linear weight dropoff behind the surface
     float span_inv;         // 1 / (epsilon - delta)
     float w_max;            // weight cap
-    float d_max;            // max valid measurement
-    float zfar;             // no voxel beyond camera depth zfar can be updated
-    float margin_u, margin_v, margin_z;   // conservative slack of the block-culling planes
-    int lat_min[3];         // block lattice scanned by the frame (inclusive lower corner)
+    float margin_z;         // conservative slack of the near/far culling planes
+};
+
+// Block lattice scanned by one launch.
+struct Lattice {
+    int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
-    long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2]
-    int parity;             // frame counter & 1: selects this frame's touched counters
+    long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
+};
+
+// Arguments of a single-frame launch.
+struct FrameArgs {
+    CameraView cam;
+    MapConsts mc;
+    Lattice lat;
+    int parity;             // launch counter & 1: selects this launch's touched counters
+};
+
+// Arguments of a multi-view launch: views are fused per voxel in array order.
+constexpr int kMaxViews = 16;
+struct ViewsArgs {
+    CameraView cam[kMaxViews];
+    int n_views;
+    MapConsts mc;
+    Lattice lat;
+    int parity;
 };
 
 __host__ __device__ inline unsigned long long pack_key(int x, int y, int z)
@@ -104,8 +132,10 @@ __host__ __device__ inline unsigned long long hash_key(unsigned long long k)
 }
 
 // Kernel launchers (integrate.hip, query.hip).
-hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting,
-                                  const float *depth, int groups, hipStream_t stream);
+hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
+                                  hipStream_t stream);
+hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
+                                  hipStream_t stream);
 hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,

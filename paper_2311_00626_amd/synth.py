@@ -363,3 +363,46 @@ def random_frame(cam: PinholeCamera, rng: np.random.Generator, lo: float = 0.3, 
     choice = rng.integers(0, 4, d.shape)
     vals = np.array([0.0, -1.0, np.nan, np.inf])[choice]
     return np.where(bad, vals, d).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Multi-sensor rig
+# --------------------------------------------------------------------------
+RIG_SIZES = ((640, 480), (848, 480), (424, 240), (1280, 720))
+
+
+@dataclass
+class RigStep:
+    cameras: List[PinholeCamera]
+    poses: List[np.ndarray]
+
+
+def rig_cameras() -> List[PinholeCamera]:
+    """Four pinhole depth cameras of uneven sizes, f = 0.875 W, centred principal point."""
+    return [PinholeCamera(w, h, 0.875 * w, 0.875 * w, w / 2.0, h / 2.0) for (w, h) in RIG_SIZES]
+
+
+def rig_extrinsics(seed: int = 3) -> List[Tuple[float, float]]:
+    """Yaw (0, 90, 180, 270 deg, each +- U(10 deg)) and pitch U(+-5 deg) of the rig cameras."""
+    rng = np.random.default_rng(seed)
+    return [(math.radians(90.0 * k + rng.uniform(-10, 10)), math.radians(rng.uniform(-5, 5)))
+            for k in range(4)]
+
+
+def rig_sequence(n_steps: int, room=(20.0, 15.0, 3.0), speed: float = 0.5, rate: float = 10.0,
+                 seed_path: int = 1, seed_scene: int = 0, seed_rig: int = 3):
+    """Cameras of the rig carried along a spline path through a cluttered room
+    (40 spheres, 20 boxes): returns (scene, steps)."""
+    base = spline_trajectory(room, n_steps, np.random.default_rng(seed_path), margin=1.0,
+                             speed=speed, fps=rate, pitch_deg=0.0)
+    spheres, boxes = random_objects(room, np.random.default_rng(seed_scene), 40, 20,
+                                    _path_positions(base), clearance=0.6)
+    cams = rig_cameras()
+    ext = rig_extrinsics(seed_rig)
+    steps = []
+    for T in base:
+        Tb = T.astype(np.float64)
+        yaw0 = math.atan2(Tb[1, 2], Tb[0, 2])
+        poses = [pose_from_forward(Tb[:3, 3], yaw0 + dy, dp) for (dy, dp) in ext]
+        steps.append(RigStep(cams, poses))
+    return Scene(room=room, spheres=spheres, boxes=boxes), steps

@@ -27,6 +27,21 @@ class TsdfError(RuntimeError):
         self.status = status
 
 
+class tsdf_stats(C.Structure):
+    _fields_ = [("blocks", C.c_longlong), ("voxel_updates", C.c_longlong),
+                ("voxel_writes", C.c_longlong), ("touched_blocks", C.c_longlong),
+                ("launches", C.c_longlong)]
+
+
+class tsdf_depth_view(C.Structure):
+    _fields_ = [("depth_dev", C.c_void_p), ("width", C.c_int), ("height", C.c_int),
+                ("model", C.c_int), ("max_range_m", C.c_float), ("K", C.c_float * 4),
+                ("reserved", C.c_float), ("reserved2", C.c_float), ("T_world_cam", C.c_float * 16)]
+
+
+MAX_VIEWS = 16
+
+
 class tsdf_params(C.Structure):
     _fields_ = [("voxel_size_m", C.c_float), ("truncation_vox", C.c_float),
                 ("max_weight", C.c_float), ("max_range_m", C.c_float),
@@ -49,13 +64,15 @@ def _load() -> C.CDLL:
     lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
     lib.query_touched.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
-    lib.map_stats.argtypes = [vp, C.POINTER(ll), C.POINTER(ll), C.POINTER(ll), vp]
+    lib.map_stats.argtypes = [vp, C.POINTER(tsdf_stats), vp]
+    lib.integrate_depth_views.argtypes = [vp, C.POINTER(tsdf_depth_view), i, vp]
     lib.map_status.argtypes = [vp]
     lib.tsdf_strerror.argtypes = [i]
     lib.tsdf_strerror.restype = C.c_char_p
     lib.tsdf_profile.argtypes = [vp, i]
     lib.tsdf_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ll)]
-    for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "query_blocks",
+    for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "integrate_depth_views",
+                 "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
                  "tsdf_profile_read"):
         getattr(lib, name).restype = C.c_int
@@ -65,6 +82,7 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "integrate_depth",
+            "integrate_depth_views",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
             "tsdf_strerror", "tsdf_profile", "tsdf_profile_read")
 
@@ -146,6 +164,26 @@ class TsdfMap:
                                  Th.ctypes.data_as(C.POINTER(C.c_float)), C.c_void_p(_stream_ptr(stream)))
         _check(st, "integrate_depth")
 
+    def integrate_depth_views(self, depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None,
+                              stream: Optional[torch.cuda.Stream] = None) -> None:
+        """Fuses up to MAX_VIEWS views in one launch; bit-identical to calling
+        integrate_depth on each in order (per-view max range, 0 = map default)."""
+        n = len(depths)
+        max_ranges = [0.0] * n if max_ranges is None else list(max_ranges)
+        if not 1 <= n <= MAX_VIEWS or len(Ks) != n or len(Ts) != n:
+            raise ValueError(f"need 1..{MAX_VIEWS} views with matching K and T")
+        arr = (tsdf_depth_view * n)()
+        for k, (d, K, T) in enumerate(zip(depths, Ks, Ts)):
+            if not (d.is_cuda and d.dtype == torch.float32 and d.dim() == 2 and d.is_contiguous()):
+                raise ValueError("each depth must be a contiguous 2-D float32 CUDA tensor")
+            arr[k].depth_dev = d.data_ptr()
+            arr[k].height, arr[k].width = int(d.shape[0]), int(d.shape[1])
+            arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
+            arr[k].max_range_m = float(max_ranges[k])
+            arr[k].T_world_cam[:] = [float(x) for x in _host_f32(T, 16)]
+        _check(lib.integrate_depth_views(self._h, arr, n, C.c_void_p(_stream_ptr(stream))),
+               "integrate_depth_views")
+
     # -- queries --------------------------------------------------------------
     def query_blocks(self, stream=None) -> torch.Tensor:
         """Allocated block indices, int32 (n, 3), sorted by (x, y, z)."""
@@ -185,10 +223,13 @@ class TsdfMap:
 
     def counters(self, stream=None) -> Tuple[int, int, int]:
         """(allocated blocks, total voxel updates, total touched blocks)."""
-        b, u, t = C.c_longlong(), C.c_longlong(), C.c_longlong()
-        _check(lib.map_stats(self._h, C.byref(b), C.byref(u), C.byref(t), C.c_void_p(_stream_ptr(stream))),
-               "map_stats")
-        return b.value, u.value, t.value
+        st = self.full_stats(stream)
+        return st["blocks"], st["voxel_updates"], st["touched_blocks"]
+
+    def full_stats(self, stream=None) -> dict:
+        out = tsdf_stats()
+        _check(lib.map_stats(self._h, C.byref(out), C.c_void_p(_stream_ptr(stream))), "map_stats")
+        return {name: getattr(out, name) for name, _ in tsdf_stats._fields_}
 
     def status(self) -> int:
         return lib.map_status(self._h)

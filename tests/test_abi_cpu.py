@@ -34,6 +34,11 @@ def test_every_declared_symbol_is_exported(t):
     assert set(t.EXPORTED) == set(declared_functions())
 
 
+def test_struct_layouts(t):
+    assert C.sizeof(t.tsdf_depth_view) == 112
+    assert C.sizeof(t.tsdf_stats) == 40
+
+
 def test_params_struct_layout(t):
     assert C.sizeof(t.tsdf_params) == 40
     p = t.default_params(0.04, 4.0)
@@ -74,6 +79,9 @@ def test_null_map_rejected(t):
     assert t.lib.query_blocks(None, None, 0, C.byref(n), None) == t.EINVAL
     assert t.lib.query_touched(None, None, 0, C.byref(n), None) == t.EINVAL
     assert t.lib.query_tsdf(None, None, 0, None, None, None) == t.EINVAL
-    assert t.lib.map_stats(None, C.byref(n), C.byref(n), C.byref(n), None) == t.EINVAL
+    st = t.tsdf_stats()
+    assert t.lib.map_stats(None, C.byref(st), None) == t.EINVAL
+    views = (t.tsdf_depth_view * 2)()
+    assert t.lib.integrate_depth_views(None, views, 1, None) == t.EINVAL
     assert t.lib.map_status(None) == t.EINVAL
     assert t.lib.destroy_map(None) == t.OK
