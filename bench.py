@@ -43,13 +43,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def algorithmic_bytes(updates: int, touched: int, new_blocks: int, pixels: int, frames: int) -> int:
-    """Bytes the method must move: one (distance, weight) read and write per
-    updated voxel (16 B), one read of every depth pixel per frame (4 B), a hash
-    key and value read per touched block (12 B) plus its touched-list entry
-    (4 B), and a key, value and slot key per new block (20 B).  For a batched
-    launch the voxel term counts each voxel once per launch (voxel writes)."""
-    return 16 * updates + 4 * pixels * frames + 16 * touched + 20 * new_blocks
+def algorithmic_bytes(voxel_rw: int, touched: int, new_blocks: int, pixels: int, frames: int,
+                      voxel_bytes: int = 8) -> int:
+    """Bytes the method must move: one (distance, weight) read and one write per
+    voxel read-modify-written (2 x 8 B binary32, 2 x 4 B binary16), one read of
+    every depth pixel per frame (4 B), a hash key and value read per touched
+    block (12 B) plus its touched-list entry (4 B), and a key, value and slot
+    key per new block (20 B).  A single-frame launch read-modify-writes a voxel
+    once per update; a batched launch once per launch (voxel writes)."""
+    return 2 * voxel_bytes * voxel_rw + 4 * pixels * frames + 16 * touched + 20 * new_blocks
 
 
 def measured_traffic(launches_bytes: float):
@@ -115,34 +117,46 @@ def main():
         st = m.full_stats()
         return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
 
-    # ---- plain path: one integrate_depth launch per frame -------------------
-    m = TsdfMap.from_params(w.params, block_capacity=1 << 16)
-    for k in range(args.warmup):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
-    torch.cuda.synchronize()
-    b0, u0, w0_, t_0 = counters(m)
-    m.profile(True)
+    def plain_leg(storage: str):
+        """One integrate_depth launch per frame; HIP events around each launch."""
+        m = TsdfMap.from_params(w.params, storage=storage, block_capacity=1 << 16)
+        for k in range(args.warmup):
+            m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        torch.cuda.synchronize()
+        b0, u0, _, t0_ = counters(m)
+        m.profile(True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        torch.cuda.synchronize()
+        t_end = time.perf_counter()
+        kernel_ms, launches = m.profile_read()
+        m.profile(False)
+        b1, u1, _, t1_ = counters(m)
+        assert m.status() == 0, "map overflowed"
+        alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, args.steps,
+                                4 if storage == "fp16" else 8) / args.steps
+        kern = kernel_ms / 1e3 / max(launches, 1)
+        return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
+                "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9}
 
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
+    # ---- plain path, binary32 storage: the headline value ------------------
+    p32 = plain_leg("fp32")
+    elapsed, updates = p32["elapsed"], p32["updates"]
+    touched, new_blocks = p32["touched"], p32["new_blocks"]
+    alg_per_launch, mean_kernel_s, achieved = p32["alg_per_launch"], p32["kernel_s"], p32["achieved"]
+    launches = p32["launches"]
 
-    kernel_ms, launches = m.profile_read()
-    m.profile(False)
-    b1, u1, w1_, t_1 = counters(m)
-    assert m.status() == 0, "map overflowed"
-    elapsed = t_end - t_start
-    updates = u1 - u0
-    touched = t_1 - t_0
-    new_blocks = b1 - b0
-    alg = algorithmic_bytes(updates, touched, new_blocks, H * W, args.steps)
-    alg_per_launch = alg / args.steps
-    mean_kernel_s = kernel_ms / 1e3 / max(launches, 1)
-    achieved = alg_per_launch / mean_kernel_s / 1e9
-    del m
+    # ---- plain path, binary16 storage ---------------------------------------
+    p16 = plain_leg("fp16")
+    fp16 = {"storage": "binary16 distance + binary16 weight, binary32 update arithmetic",
+            "value": p16["updates"] / p16["elapsed"], "unit": "voxel updates/s",
+            "frames_per_s": args.steps / p16["elapsed"], "ms_per_step": p16["elapsed"] / args.steps * 1e3,
+            "roofline": {"bound": "hbm", "achieved": p16["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": p16["achieved"] / HBM_PEAK_GBS, "kernel": "integrate_depth_kernel<fp16>",
+                         "kernel_ms_mean": p16["kernel_s"] * 1e3,
+                         "algorithmic_bytes_per_launch": p16["alg_per_launch"]}}
 
     # ---- batched path: integrate_depth_views, several frames per launch ------
     batched = None
@@ -166,7 +180,7 @@ def main():
         assert mb.status() == 0, "map overflowed"
         nfb = n_frames - first
         eb = tb_end - tb_start
-        alg_b = (16 * (wb1 - wb0) + 4 * H * W * nfb + 16 * (tb1 - tb0) + 20 * (bb1 - bb0)) / max(kl, 1)
+        alg_b = algorithmic_bytes(wb1 - wb0, tb1 - tb0, bb1 - bb0, H * W, nfb) / max(kl, 1)
         kb = kms / 1e3 / max(kl, 1)
         batched = {"views_per_launch": B, "frames": nfb, "launches": kl,
                    "value": (ub1 - ub0) / eb, "unit": "voxel updates/s",
@@ -211,6 +225,7 @@ def main():
                      "kernel": "integrate_depth_kernel", "kernel_ms_mean": mean_kernel_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches},
     }
+    result["fp16"] = fp16
     if batched is not None:
         result["batched"] = batched
     if not args.skip_cpu_baseline:

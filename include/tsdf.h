@@ -62,6 +62,10 @@ extern "C" {
 #define TSDF_WEIGHT_CONSTANT 0        /* f_w(d_p) = 1 */
 #define TSDF_WEIGHT_LINEAR_DROPOFF 1  /* 1 for d_p >= -voxel_size, then linear to 0 at -epsilon */
 
+#define TSDF_STORAGE_FP32 0   /* (distance, weight) as two binary32: 8 B per voxel, 4 KiB per block */
+#define TSDF_STORAGE_FP16 1   /* two binary16, rounded to nearest-even after each binary32 update:
+                                 4 B per voxel, 2 KiB per block */
+
 typedef struct tsdf_map tsdf_map;
 
 typedef struct {
@@ -70,13 +74,13 @@ typedef struct {
     float max_weight;          /* cap on the stored weight, > 0 */
     float max_range_m;         /* measurements d > max_range_m are invalid, > 0 */
     int weighting;             /* TSDF_WEIGHT_* */
-    int reserved0;             /* must be 0 */
-    long long block_capacity;  /* number of 8^3-voxel blocks the pool holds (4 KiB each), >= 1 */
+    int storage;               /* TSDF_STORAGE_*; the update arithmetic is binary32 either way */
+    long long block_capacity;  /* number of 8^3-voxel blocks the pool holds, >= 1 */
     long long hash_capacity;   /* hash slots; 0 = smallest power of two >= 2 * block_capacity */
 } tsdf_params;
 
 /* Fills *p with the defaults: max_weight 100, max_range 5 m, constant weight,
- * 2^18 blocks (1 GiB of voxels), automatic hash size. */
+ * binary32 storage, 2^18 blocks (1 GiB of voxels), automatic hash size. */
 TSDF_API void tsdf_default_params(tsdf_params *p, float voxel_size_m, float truncation_vox);
 
 /* Creates an empty map on the current HIP device (§IV-A).  create_map uses
@@ -141,7 +145,8 @@ TSDF_API int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity,
 
 /* Gathers the voxels of n_blocks blocks (int32 triples at blocks_xyz_dev):
  * out_dist_dev and out_weight_dev receive 512 float32 each per block in
- * voxel order lx + 8 ly + 64 lz, zeros for blocks that are not allocated.
+ * voxel order lx + 8 ly + 64 lz (binary16 storage widens exactly), zeros for
+ * blocks that are not allocated.
  * Only enqueues work. */
 TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks,
                float *out_dist_dev, float *out_weight_dev, void *hip_stream);

@@ -13,7 +13,9 @@ from typing import Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libtsdf_oracle.so")
+# TSDF_ORACLE_LIB points the wrapper at another build of the same sources
+# (the mutation test builds deliberately broken copies to check the pins).
+_LIB_PATH = os.environ.get("TSDF_ORACLE_LIB") or os.path.join(_HERE, "libtsdf_oracle.so")
 _lib = None
 
 WEIGHTINGS = {"constant": 0, "linear_dropoff": 1}
@@ -33,6 +35,10 @@ def _load():
     lib.ora_create.restype = C.c_void_p
     lib.ora_create.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int]
     lib.ora_destroy.argtypes = [C.c_void_p]
+    lib.ora_set_storage16.restype = C.c_int
+    lib.ora_set_storage16.argtypes = [C.c_void_p]
+    lib.ora_round_binary16.restype = C.c_float
+    lib.ora_round_binary16.argtypes = [C.c_float]
     lib.ora_integrate_depth.restype = C.c_longlong
     lib.ora_integrate_depth.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
     lib.ora_integrate_depth_range.restype = C.c_longlong
@@ -66,7 +72,8 @@ class OracleMap:
     the parity oracle) or binary64 (``precision=64``, the error oracle)."""
 
     def __init__(self, voxel_size: float, truncation_vox: float, *, precision: int = 32,
-                 max_weight: float = 100.0, max_range: float = 5.0, weighting: str = "constant"):
+                 max_weight: float = 100.0, max_range: float = 5.0, weighting: str = "constant",
+                 storage: str = "fp32"):
         lib = _load()
         self.precision = precision
         self.voxel_size = voxel_size
@@ -74,12 +81,14 @@ class OracleMap:
                                  WEIGHTINGS[weighting])
         if not self._h:
             raise ValueError("invalid oracle map parameters")
+        if storage == "fp16" and lib.ora_set_storage16(self._h) != 0:
+            raise ValueError("binary16 storage needs precision 32")
 
     @classmethod
-    def from_params(cls, params, precision: int = 32) -> "OracleMap":
+    def from_params(cls, params, precision: int = 32, storage: str = "fp32") -> "OracleMap":
         return cls(params.voxel_size, params.truncation_vox, precision=precision,
                    max_weight=params.max_weight, max_range=params.max_range,
-                   weighting=params.weighting)
+                   weighting=params.weighting, storage=storage)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -139,6 +148,10 @@ class OracleMap:
         d, w = self.voxels()
         order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
         return b[order], d[order], w[order]
+
+
+def round_binary16(x: float) -> float:
+    return float(_load().ora_round_binary16(x))
 
 
 def camera_from_world(T_world_cam, precision: int = 32):

@@ -206,6 +206,10 @@ static long long FN(integrate)(ora_map *m, const float *depth, int width, int he
                 for (int k = 0; k < 512; ++k)
                     if (hit[k]) {
                         FN(voxel_fuse)(&D[k], &W[k], xs[k], ws[k], f.w_max);
+                        if (m->storage16) {
+                            D[k] = (REAL)ora_round_binary16((float)D[k]);
+                            W[k] = (REAL)ora_round_binary16((float)W[k]);
+                        }
                         ++updates;
                     }
             }

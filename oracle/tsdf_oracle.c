@@ -29,6 +29,7 @@ typedef struct {
 
 struct ora_map {
     int precision;            /* 32 or 64 */
+    int storage16;            /* 1: voxels stored as binary16 (precision 32 only) */
     ora_params p;
     ora_slot *table;          /* hash table, size table_size (power of two) */
     long long table_size;
@@ -129,6 +130,25 @@ static long long map_find_or_insert(ora_map *m, int32_t x, int32_t y, int32_t z)
     return b;
 }
 
+/* IEEE 754 rounding of a binary32 value to binary16 (11 significant bits,
+ * exponents down to -14, subnormal quantum 2^-24, largest finite 65504). */
+float ora_round_binary16(float x)
+{
+    if (!isfinite(x) || x == 0.0f)
+        return x;
+    float ax = fabsf(x);
+    int e;
+    (void)frexpf(ax, &e);                /* ax = m 2^e, 0.5 <= m < 1 */
+    int qexp = e - 11;                   /* quantum of an 11-bit significand */
+    if (qexp < -24)
+        qexp = -24;                      /* subnormal range */
+    const float q = ldexpf(1.0f, qexp);
+    float r = nearbyintf(ax / q) * q;    /* exact scaling; nearest, ties to even */
+    if (r > 65504.0f)
+        r = INFINITY;
+    return copysignf(r, x);
+}
+
 static int touched_push(ora_map *m, long long b)
 {
     if (m->n_touched == m->cap_touched) {
@@ -177,6 +197,14 @@ ora_map *ora_create(int precision, float voxel_size, float truncation_vox, float
     m->p.weighting = weighting;
     m->scan_max[0] = m->scan_max[1] = m->scan_max[2] = -1;
     return m;
+}
+
+int ora_set_storage16(ora_map *m)
+{
+    if (!m || m->precision != 32 || m->n_blocks != 0)
+        return -1;
+    m->storage16 = 1;
+    return 0;
 }
 
 void ora_destroy(ora_map *m)

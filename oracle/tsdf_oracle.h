@@ -47,6 +47,16 @@ ora_map *ora_create(int precision, float voxel_size, float truncation_vox,
                     float max_weight, float max_range, int weighting);
 void ora_destroy(ora_map *m);
 
+/* binary16 voxel storage for a binary32 map (precision 32 only, before the
+ * first frame): after every update the stored distance and weight are
+ * rounded to the nearest binary16 value, ties to even; the update arithmetic
+ * stays binary32.  Returns 0, or -1 if not allowed. */
+int ora_set_storage16(ora_map *m);
+
+/* The binary16 value nearest to x (ties to even, overflow to infinity), as a
+ * binary32; NaN, infinities and zeros pass through. */
+float ora_round_binary16(float x);
+
 /* Integrates one depth frame (row-major float32, width x height, metres) seen
  * from T_world_cam (row-major 4x4 float32) with K = {fx, fy, cx, cy}.
  * Returns the number of voxel updates, or -1 on bad arguments / no memory. */

@@ -58,7 +58,7 @@ bool params_valid(const tsdf_params *p)
         return false;
     if (p->weighting != TSDF_WEIGHT_CONSTANT && p->weighting != TSDF_WEIGHT_LINEAR_DROPOFF)
         return false;
-    if (p->reserved0 != 0)
+    if (p->storage != TSDF_STORAGE_FP32 && p->storage != TSDF_STORAGE_FP16)
         return false;
     if (p->block_capacity < 1 || p->block_capacity > (1ll << 30))
         return false;
@@ -342,14 +342,15 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     const size_t bc = (size_t)p->block_capacity;
     if (e == hipSuccess) e = hipMalloc(&d.keys, sizeof(unsigned long long) * (size_t)hc);
     if (e == hipSuccess) e = hipMalloc(&d.vals, sizeof(uint32_t) * (size_t)hc);
-    if (e == hipSuccess) e = hipMalloc(&d.pool, sizeof(float2) * kBlockVoxels * bc);
+    const size_t vb = voxel_bytes(p->storage);
+    if (e == hipSuccess) e = hipMalloc(&d.pool, vb * kBlockVoxels * bc);
     if (e == hipSuccess) e = hipMalloc(&d.slot_keys, sizeof(unsigned long long) * bc);
     if (e == hipSuccess) e = hipMalloc(&d.touched, sizeof(uint32_t) * bc * kSubLists);
     if (e == hipSuccess) e = hipMalloc(&d.counters, sizeof(uint32_t) * kNumCounterWords);
     if (e == hipSuccess) e = hipMalloc(&d.totals, sizeof(unsigned long long) * kNumTotalWords);
     if (e == hipSuccess) e = hipMemset(d.keys, 0xFF, sizeof(unsigned long long) * (size_t)hc);
     if (e == hipSuccess) e = hipMemset(d.vals, 0xFF, sizeof(uint32_t) * (size_t)hc);
-    if (e == hipSuccess) e = hipMemset(d.pool, 0, sizeof(float2) * kBlockVoxels * bc);
+    if (e == hipSuccess) e = hipMemset(d.pool, 0, vb * kBlockVoxels * bc);
     if (e == hipSuccess) e = hipMemset(d.slot_keys, 0xFF, sizeof(unsigned long long) * bc);
     if (e == hipSuccess) e = hipMemset(d.counters, 0, sizeof(uint32_t) * kNumCounterWords);
     if (e == hipSuccess) e = hipMemset(d.totals, 0, sizeof(unsigned long long) * kNumTotalWords);
@@ -361,6 +362,7 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     }
     d.hash_mask = (uint32_t)(hc - 1);
     d.block_cap = (uint32_t)bc;
+    d.storage = p->storage;
     *out = m;
     return TSDF_OK;
 }

@@ -39,6 +39,51 @@ __device__ __forceinline__ void store_f2(__amdgpu_buffer_rsrc_t r, uint32_t off,
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(b64_t, v), r, off, 0, 0);
 }
 
+// Voxel storage: a (distance, weight) pair as two binary32 (STORAGE 0) or as
+// two binary16 rounded to nearest-even (STORAGE 1, IEEE conversion); the
+// update arithmetic is binary32 in both cases and binary16 widens exactly.
+template <int STORAGE> struct VoxelIO;
+
+template <> struct VoxelIO<0> {
+    static constexpr uint32_t kBytes = 8;
+    // the value a store followed by a load would give back
+    __device__ static __forceinline__ float2 quantize(float2 v) { return v; }
+    __device__ static __forceinline__ float2 load(__amdgpu_buffer_rsrc_t r, uint32_t off) { return load_f2(r, off); }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v)
+    {
+        store_f2(r, off, v);
+    }
+};
+
+template <> struct VoxelIO<1> {
+    static constexpr uint32_t kBytes = 4;
+    __device__ static __forceinline__ float2 quantize(float2 v)
+    {
+        return make_float2((float)(_Float16)v.x, (float)(_Float16)v.y);
+    }
+    __device__ static __forceinline__ float2 load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+    {
+        const uint32_t bits = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        const _Float16 d = __builtin_bit_cast(_Float16, (unsigned short)(bits & 0xFFFFu));
+        const _Float16 w = __builtin_bit_cast(_Float16, (unsigned short)(bits >> 16));
+        return make_float2((float)d, (float)w);
+    }
+    __device__ static __forceinline__ void store(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v)
+    {
+        const unsigned short d = __builtin_bit_cast(unsigned short, (_Float16)v.x);
+        const unsigned short w = __builtin_bit_cast(unsigned short, (_Float16)v.y);
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)d | ((uint32_t)w << 16), r, off, 0, 0);
+    }
+};
+
+// Buffer descriptor of one block of the pool.
+template <int STORAGE>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const DeviceMap &dm, uint32_t slot)
+{
+    constexpr uint32_t bytes = kBlockVoxels * VoxelIO<STORAGE>::kBytes;
+    return make_rsrc((const char *)dm.pool + (size_t)slot * bytes, bytes);
+}
+
 // Hash loads bypass the per-CU cache: other waves of the same launch insert keys.
 __device__ __forceinline__ unsigned long long load_key(const unsigned long long *p)
 {

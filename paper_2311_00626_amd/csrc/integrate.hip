@@ -27,7 +27,7 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING>
+template <int WEIGHTING, int STORAGE>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa)
 {
     const int lane = lane_id();
@@ -68,13 +68,14 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
             continue;
 
         // lanes whose voxel is not updated use an out-of-range offset: no load, no store
-        const __amdgpu_buffer_rsrc_t blk = make_rsrc(dm.pool + (size_t)slot * kBlockVoxels, kBlockVoxels * 8u);
+        using IO = VoxelIO<STORAGE>;
+        const __amdgpu_buffer_rsrc_t blk = block_rsrc<STORAGE>(dm, slot);
         uint32_t off[8];
         float2 dw[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-            off[s] = ((hit >> s) & 1u) ? 8u * (uint32_t)(64 * s + lane) : kOutOfRange;
-            dw[s] = load_f2(blk, off[s]);
+            off[s] = ((hit >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange;
+            dw[s] = IO::load(blk, off[s]);
         }
 #pragma unroll
         for (int s = 0; s < 8; ++s)
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             n_updates += (uint32_t)__popcll(__ballot((hit >> s) & 1u));
-            store_f2(blk, off[s], dw[s]);
+            IO::store(blk, off[s], dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
     }
@@ -96,10 +97,14 @@ hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int 
                                   hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (weighting == 1)
-        hipLaunchKernelGGL(integrate_depth_kernel<1>, grid, block, 0, stream, dm, fa);
+    if (weighting == 1 && dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 1>), grid, block, 0, stream, dm, fa);
+    else if (weighting == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 0>), grid, block, 0, stream, dm, fa);
+    else if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 1>), grid, block, 0, stream, dm, fa);
     else
-        hipLaunchKernelGGL(integrate_depth_kernel<0>, grid, block, 0, stream, dm, fa);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 0>), grid, block, 0, stream, dm, fa);
     return hipGetLastError();
 }
 

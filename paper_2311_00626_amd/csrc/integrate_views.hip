@@ -8,6 +8,9 @@
 // stores it once.  Block allocation follows the same rule as for one frame: a
 // block exists once any view updates any of its voxels.
 //
+// With binary16 storage the register state is rounded to binary16 after each
+// view, so the batch stays bit-identical to storing and reloading per view.
+//
 // Per block of the union lattice of all views:
 //   1. culling against every view's frustum -> view mask (wave-uniform);
 //   2. view 0 of the mask is measured while the first hash window is in flight;
@@ -24,7 +27,7 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING>
+template <int WEIGHTING, int STORAGE>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
 {
     const int lane = lane_id();
@@ -66,13 +69,14 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
         uint32_t ha = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xa, wa);
 
         // state of an existing block, loaded while the next view is measured
+        using IO = VoxelIO<STORAGE>;
         const uint32_t found = find_block(dm, key, h, w0);
         float2 dw[8];
         if (found != kInvalidSlot) {
-            const __amdgpu_buffer_rsrc_t blk = make_rsrc(dm.pool + (size_t)found * kBlockVoxels, kBlockVoxels * 8u);
+            const __amdgpu_buffer_rsrc_t blk = block_rsrc<STORAGE>(dm, found);
 #pragma unroll
             for (int s = 0; s < 8; ++s)
-                dw[s] = load_f2(blk, 8u * (uint32_t)(64 * s + lane));
+                dw[s] = IO::load(blk, IO::kBytes * (uint32_t)(64 * s + lane));
         } else {
 #pragma unroll
             for (int s = 0; s < 8; ++s)
@@ -89,12 +93,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
                 rest &= rest - 1;
                 hb = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xb, wb);
             }
-            // fuse the pending view, in view order
+            // fuse the pending view, in view order; the state is rounded to the
+            // storage precision after every view, exactly as a store and reload would
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 n_updates += (uint32_t)__popcll(__ballot((ha >> s) & 1u));
                 if ((ha >> s) & 1u)
-                    dw[s] = fuse(dw[s], xa[s], wa[s], va.mc.w_max);
+                    dw[s] = IO::quantize(fuse(dw[s], xa[s], wa[s], va.mc.w_max));
             }
             any |= ha;
             if (!more)
@@ -112,11 +117,11 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
         const uint32_t slot = found != kInvalidSlot ? found : find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
             continue;
-        const __amdgpu_buffer_rsrc_t blk = make_rsrc(dm.pool + (size_t)slot * kBlockVoxels, kBlockVoxels * 8u);
+        const __amdgpu_buffer_rsrc_t blk = block_rsrc<STORAGE>(dm, slot);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             n_writes += (uint32_t)__popcll(__ballot((any >> s) & 1u));
-            store_f2(blk, ((any >> s) & 1u) ? 8u * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
+            IO::store(blk, ((any >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
     }
@@ -129,10 +134,14 @@ hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int 
                                   hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (weighting == 1)
-        hipLaunchKernelGGL(integrate_views_kernel<1>, grid, block, 0, stream, dm, va);
+    if (weighting == 1 && dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 1>), grid, block, 0, stream, dm, va);
+    else if (weighting == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 0>), grid, block, 0, stream, dm, va);
+    else if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 1>), grid, block, 0, stream, dm, va);
     else
-        hipLaunchKernelGGL(integrate_views_kernel<0>, grid, block, 0, stream, dm, va);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 0>), grid, block, 0, stream, dm, va);
     return hipGetLastError();
 }
 

@@ -49,8 +49,15 @@ __global__ __launch_bounds__(256) void query_tsdf_kernel(DeviceMap dm, const int
         float *w = weight + b * kBlockVoxels;
         for (int k = lane; k < kBlockVoxels; k += 64) {
             float2 v = make_float2(0.0f, 0.0f);
-            if (slot != kInvalidSlot)
-                v = dm.pool[(size_t)slot * kBlockVoxels + k];
+            if (slot != kInvalidSlot) {
+                const size_t at = (size_t)slot * kBlockVoxels + k;
+                if (dm.storage == 1) {
+                    const _Float16 *p = (const _Float16 *)dm.pool + 2 * at;
+                    v = make_float2((float)p[0], (float)p[1]);
+                } else {
+                    v = ((const float2 *)dm.pool)[at];
+                }
+            }
             d[k] = v.x;
             w[k] = v.y;
         }

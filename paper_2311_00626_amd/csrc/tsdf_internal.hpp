@@ -48,14 +48,17 @@ enum ErrorBits : uint32_t {
 struct DeviceMap {
     unsigned long long *keys;        // [hash_mask + 1] packed block keys, kEmptyKey = free
     uint32_t *vals;                  // [hash_mask + 1] pool slot of the key, kInvalidSlot until published
-    float2 *pool;                    // [block_cap * 512] (distance, weight) per voxel
+    void *pool;                      // [block_cap * 512] (distance, weight) per voxel: float2 or half2
     unsigned long long *slot_keys;   // [block_cap] key of each pool slot
     uint32_t *touched;               // [kSubLists][block_cap] pool slots touched by the last frame
     uint32_t *counters;              // [kNumCounterWords]
     unsigned long long *totals;      // [kNumTotalWords] running totals
     uint32_t hash_mask;
     uint32_t block_cap;
+    int storage;                     // 0: binary32 pairs, 1: binary16 pairs
 };
+
+constexpr uint32_t voxel_bytes(int storage) { return storage == 1 ? 4u : 8u; }
 
 // One pinhole depth image and its pose (host-computed, passed by value).
 struct CameraView {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libtsdf.so")
 
 OK, EINVAL, ENOMEM, EFULL, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 WEIGHTINGS = {"constant": 0, "linear_dropoff": 1}
+STORAGES = {"fp32": 0, "fp16": 1}
 
 
 class TsdfError(RuntimeError):
@@ -45,7 +46,7 @@ MAX_VIEWS = 16
 class tsdf_params(C.Structure):
     _fields_ = [("voxel_size_m", C.c_float), ("truncation_vox", C.c_float),
                 ("max_weight", C.c_float), ("max_range_m", C.c_float),
-                ("weighting", C.c_int), ("reserved0", C.c_int),
+                ("weighting", C.c_int), ("storage", C.c_int),
                 ("block_capacity", C.c_longlong), ("hash_capacity", C.c_longlong)]
 
 
@@ -116,12 +117,13 @@ class TsdfMap:
     """A block-sparse TSDF layer on the current GPU (see include/tsdf.h)."""
 
     def __init__(self, voxel_size: float, truncation_vox: float, *, max_weight: float = 100.0,
-                 max_range: float = 5.0, weighting: str = "constant",
+                 max_range: float = 5.0, weighting: str = "constant", storage: str = "fp32",
                  block_capacity: int = 1 << 18, hash_capacity: int = 0):
         p = default_params(voxel_size, truncation_vox)
         p.max_weight = max_weight
         p.max_range_m = max_range
         p.weighting = WEIGHTINGS[weighting]
+        p.storage = STORAGES[storage]
         p.block_capacity = block_capacity
         p.hash_capacity = hash_capacity
         h = C.c_void_p()

@@ -59,7 +59,7 @@ def test_invalid_create_arguments_rejected_before_device(t):
         assert t.lib.create_map(vs, tau, C.byref(h)) == t.EINVAL
         assert not h.value
     p = t.default_params(0.05, 4.0)
-    for field, bad in (("max_weight", 0.0), ("max_range_m", -1.0), ("weighting", 7), ("reserved0", 1),
+    for field, bad in (("max_weight", 0.0), ("max_range_m", -1.0), ("weighting", 7), ("storage", 2),
                        ("block_capacity", 0), ("hash_capacity", 3), ("hash_capacity", -8)):
         q = t.default_params(0.05, 4.0)
         setattr(q, field, bad)

@@ -486,3 +486,48 @@ def test_rejects_bad_arguments(oracle_mod):
     T2[0, 3] = np.nan
     with pytest.raises(ValueError):
         m.integrate(np.ones((4, 4), np.float32), np.array([1, 1, 2, 2], np.float32), T2)
+
+
+# --------------------------------------------------------------------------
+# binary16 voxel storage
+# --------------------------------------------------------------------------
+def test_binary16_rounding_matches_ieee_conversion(oracle_mod):
+    """The oracle's float -> binary16 rounding equals numpy's IEEE conversion
+    (nearest, ties to even) on normals, subnormals, ties and overflow."""
+    rng = np.random.default_rng(0)
+    xs = rng.standard_normal(5000) * 10.0 ** rng.uniform(-9, 5, 5000)
+    edge = [65504, 65519, 65520, 65536, 1e-8, 2 ** -24, 2 ** -25, 3 * 2 ** -26, 6e-5,
+            0.5 + 2 ** -12, 1 + 2 ** -11, 1 + 3 * 2 ** -11, -0.0, 0.0]
+    xs = np.concatenate([xs, edge, -np.asarray(edge)]).astype(np.float32)
+    with np.errstate(over="ignore"):
+        ref = xs.astype(np.float16).astype(np.float32)
+    got = np.array([oracle_mod.round_binary16(float(x)) for x in xs], np.float32)
+    assert np.array_equal(got, ref)
+
+
+def test_fp16_storage_single_frame_and_bound(oracle_mod):
+    """binary16 storage: one frame stores round16(min(d_p, eps)) and weight 1;
+    over a sequence the binary16-stored distance stays within a few binary16
+    ulps of the binary32-stored one (same update decisions, constant weights)."""
+    w = synth.box_room_sequence(0.05, n_frames=12)
+    frames = w.frames()
+    m16 = oracle_mod.OracleMap.from_params(w.params, storage="fp16")
+    m32 = oracle_mod.OracleMap.from_params(w.params)
+    m16.integrate(frames[0], w.camera.K, w.poses[0])
+    m32.integrate(frames[0], w.camera.K, w.poses[0])
+    b16, d16, w16 = m16.sorted_state()
+    b32, d32, w32 = m32.sorted_state()
+    assert np.array_equal(b16, b32) and np.array_equal(w16, w32)
+    assert np.array_equal(d16, d32.astype(np.float32).astype(np.float16).astype(np.float64))
+    for d, T in zip(frames[1:], w.poses[1:]):
+        m16.integrate(d, w.camera.K, T)
+        m32.integrate(d, w.camera.K, T)
+    b16, d16, w16 = m16.sorted_state()
+    b32, d32, w32 = m32.sorted_state()
+    assert np.array_equal(b16, b32)
+    assert np.array_equal(w16, w32)          # integer weights are exact in binary16
+    # each store rounds to half a binary16 ulp (<= 2^-11 relative); the running
+    # average contracts earlier errors, so a few ulps of epsilon bound the total
+    err = np.abs(d16 - d32)[w32 > 0]
+    assert err.max() <= 4 * 2.0 ** -11 * 0.2, err.max()
+    assert err.max() > 0                      # storage rounding is really applied

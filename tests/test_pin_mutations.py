@@ -1,0 +1,62 @@
+"""The pins must catch plausible mistakes in the oracle.  Each case plants one
+mistake in a temporary copy of the oracle sources (on the CPU), builds it, and
+runs the pin suite against it; the suite has to fail."""
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+# (name, file, original text, planted mistake)
+MUTANTS = [
+    ("sign_of_projective_distance", "oracle_impl.h", "REAL dp = d - zc;", "REAL dp = zc - d;"),
+    ("rotation_not_transposed", "oracle_impl.h", "f->R[3 * i + j] = (REAL)T[4 * j + i];",
+     "f->R[3 * i + j] = (REAL)T[4 * i + j];"),
+    ("translation_sign", "oracle_impl.h", "f->t[i] = (REAL)(-acc);", "f->t[i] = (REAL)(acc);"),
+    ("pixel_rounded_to_nearest", "oracle_impl.h", "int32_t i = (int32_t)u;",
+     "int32_t i = (int32_t)u; if (u - (REAL)i > (REAL)0.5 && i + 1 < f->width) i += 1;"),
+    ("x_and_y_swapped_in_projection", "oracle_impl.h", "REAL u = f->fx * (xc * r) + f->cx;",
+     "REAL u = f->fx * (yc * r) + f->cx;"),
+    ("principal_point_dropped", "oracle_impl.h", "REAL v = f->fy * (yc * r) + f->cy;",
+     "REAL v = f->fy * (yc * r);"),
+    ("fx_fy_swapped", "oracle_impl.h", "REAL u = f->fx * (xc * r) + f->cx;",
+     "REAL u = f->fy * (xc * r) + f->cx;"),
+    ("image_indexed_transposed", "oracle_impl.h",
+     "f->depth[(size_t)j * (size_t)f->width + (size_t)i]", "f->depth[(size_t)i * (size_t)f->height + (size_t)j]"),
+    ("clamp_instead_of_skip_behind_surface", "oracle_impl.h", "if (!(dp >= -f->eps))\n        return 0;",
+     "if (dp < -f->eps)\n        dp = -f->eps;"),
+    ("weight_not_capped", "oracle_impl.h", "*W = s < w_max ? s : w_max;", "*W = s;"),
+    ("average_drops_old_weight", "oracle_impl.h", "REAL n = *D * *W + x * wm;", "REAL n = *D + x * wm;"),
+    ("voxel_centre_missing_half", "oracle_impl.h", "REAL px = ((REAL)gx + half) * f->vs;",
+     "REAL px = ((REAL)gx) * f->vs;"),
+    ("dropoff_sign", "oracle_impl.h", "w = (f->eps + dp) * f->span_inv;", "w = (f->eps - dp) * f->span_inv;"),
+    ("max_range_exclusive", "oracle_impl.h", "if (!(d > 0 && d <= f->d_max))", "if (!(d > 0 && d < f->d_max))"),
+    ("scan_box_misses_truncation_band", "oracle_impl.h", "double zfar = zmax + (double)f->eps;",
+     "double zfar = zmax - (double)f->eps;"),
+    ("binary16_rounds_toward_zero", "tsdf_oracle.c", "float r = nearbyintf(ax / q) * q;",
+     "float r = truncf(ax / q) * q;"),
+]
+
+
+@pytest.mark.parametrize("name,fname,orig,mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, fname, orig, mutant):
+    with tempfile.TemporaryDirectory() as tmp:
+        for f in ("tsdf_oracle.c", "tsdf_oracle.h", "oracle_impl.h"):
+            shutil.copy(os.path.join(ORACLE, f), tmp)
+        path = os.path.join(tmp, fname)
+        text = open(path).read()
+        assert text.count(orig) == 1, f"mutation anchor not found once: {orig}"
+        open(path, "w").write(text.replace(orig, mutant))
+        lib = os.path.join(tmp, "libmutant.so")
+        subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+                        "-o", lib, os.path.join(tmp, "tsdf_oracle.c"), "-lm"], check=True, cwd=tmp)
+        env = dict(os.environ, TSDF_ORACLE_LIB=lib)
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"pins did not catch the planted mistake '{name}'"
