@@ -112,18 +112,48 @@ TSDF_API int destroy_map(tsdf_map *m);
 TSDF_API int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height,
                     const float K[4], const float T_world_cam[16], void *hip_stream);
 
-/* One depth view of a batch: a depth image, its sensor model and its pose,
- * with the same meaning and constraints as the arguments of integrate_depth. */
+/* A rotating LiDAR's range image (§III: Omega is the beam angles; Eq. (3)).
+ * Row-major float32[height][width] of Euclidean ranges in metres; sensor frame
+ * x forward, y left, z up.  Column i covers azimuths (atan2(y, x)) from
+ * azimuth_start + i / alpha to azimuth_start + (i + 1) / alpha with
+ * alpha = width / azimuth_fov; row j covers polar angles (from +z) from
+ * polar_start + j / beta with beta = height / polar_fov; each beam sits at the
+ * centre of its pixel.  A voxel's range is interpolated bilinearly between
+ * the 4 beams around its direction, only when all 4 are valid and differ by
+ * at most interp_max_diff_m (no interpolation across depth edges); the voxel
+ * depth d_v is the Euclidean range of the voxel centre.  azimuth_fov >= 2 pi
+ * (binary32 2 pi) makes columns wrap around. */
+typedef struct {
+    int width, height;            /* >= 2 each */
+    float azimuth_start_rad;      /* finite */
+    float azimuth_fov_rad;        /* (0, 2 pi] */
+    float polar_start_rad;        /* [0, pi) */
+    float polar_fov_rad;          /* > 0, polar_start + polar_fov <= pi */
+    float interp_max_diff_m;      /* >= 0 */
+    float max_range_m;            /* valid ranges are <= this; 0 = the map's max range */
+} tsdf_lidar_model;
+
+/* Fuses one range image into the map: integrate_depth with the spherical
+ * projection of Eq. (3) in place of the pinhole and the interpolated range in
+ * place of the nearest depth.  T_world_sensor as T_world_cam.  Only enqueues
+ * work; errors as integrate_depth. */
+TSDF_API int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model *lidar,
+                             const float T_world_sensor[16], void *hip_stream);
+
+/* One view of a batch: a depth or range image, its sensor model and its pose,
+ * with the meaning and constraints of integrate_depth / integrate_range. */
 #define TSDF_MAX_VIEWS 16
 #define TSDF_MODEL_PINHOLE 0
+#define TSDF_MODEL_SPHERICAL 1
 typedef struct {
-    const float *depth_dev;    /* device float32[height][width], z-depth in metres */
+    const float *depth_dev;    /* device float32[height][width]: z-depth (pinhole) or range (spherical) */
     int width, height;
-    int model;                 /* TSDF_MODEL_PINHOLE */
+    int model;                 /* TSDF_MODEL_PINHOLE or TSDF_MODEL_SPHERICAL */
     float max_range_m;         /* valid measurements are <= this; 0 = the map's max range */
-    float K[4];                /* fx, fy, cx, cy */
+    float K[4];                /* pinhole: fx, fy, cx, cy; spherical: azimuth start, azimuth fov,
+                                  polar start, polar fov (radians) */
+    float interp_max_diff_m;   /* spherical: as in tsdf_lidar_model; pinhole: must be 0 */
     float reserved;            /* must be 0 */
-    float reserved2;           /* must be 0 */
     float T_world_cam[16];     /* row-major rigid pose */
 } tsdf_depth_view;
 
@@ -175,6 +205,19 @@ TSDF_API int map_status(tsdf_map *m);
 
 /* Static description of a status code (never NULL). */
 TSDF_API const char *tsdf_strerror(int status);
+
+/* Launch shape of the integration kernels (tuning only: results do not
+ * depend on it).  Zero fields mean automatic.
+ *   max_groups  cap on workgroups of 512 threads per launch (rounded down to a
+ *               multiple of 8), 1 .. 65536;
+ *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
+ *               each XCD reads about 1/8 of every depth image;
+ *   chunk       lattice blocks a wave culls per pass, 1 .. 64.
+ * NULL restores the automatic choice.  Errors: TSDF_EINVAL. */
+typedef struct {
+    int max_groups, partitions, chunk, reserved;
+} tsdf_launch_config;
+TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);
 
 /* Kernel timing.  While enabled, every integrate_depth call records a pair of
  * HIP events on its stream around its integration kernel.  tsdf_profile_read

@@ -43,6 +43,13 @@ def _load():
     lib.ora_integrate_depth.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
     lib.ora_integrate_depth_range.restype = C.c_longlong
     lib.ora_integrate_depth_range.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p, C.c_float]
+    lib.ora_integrate_range.restype = C.c_longlong
+    lib.ora_integrate_range.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
+    lib.ora_dense_integrate_range.restype = C.c_longlong
+    lib.ora_dense_integrate_range.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
+                                              f32p, C.c_int, C.c_int, f32p, f32p, i32p, i32p, f64p, f64p]
+    lib.ora_atan2_f32.restype = C.c_float
+    lib.ora_atan2_f32.argtypes = [C.c_float, C.c_float]
     lib.ora_num_blocks.restype = C.c_longlong
     lib.ora_num_blocks.argtypes = [C.c_void_p]
     lib.ora_blocks.argtypes = [C.c_void_p, i32p]
@@ -109,6 +116,16 @@ class OracleMap:
             raise ValueError("oracle rejected the frame")
         return int(n)
 
+    def integrate_range(self, rng: np.ndarray, lidar, T_world_sensor) -> int:
+        """One spherical range image; lidar has .params() = float32 [azimuth
+        start, azimuth fov, polar start, polar fov, interp max diff, max range]."""
+        rng = _f32(rng)
+        H, W = rng.shape
+        n = _lib.ora_integrate_range(self._h, rng, W, H, _f32(lidar.params(), 6), _f32(T_world_sensor, 16))
+        if n < 0:
+            raise ValueError("oracle rejected the range image")
+        return int(n)
+
     def num_blocks(self) -> int:
         return int(_lib.ora_num_blocks(self._h))
 
@@ -148,6 +165,31 @@ class OracleMap:
         d, w = self.voxels()
         order = np.lexsort((b[:, 2], b[:, 1], b[:, 0]))
         return b[order], d[order], w[order]
+
+
+def dense_integrate_range(params, images, lidar, poses, gmin, gdim, precision: int = 32):
+    """Dense brute force of range images over a voxel box; (dist, weight)
+    shaped (gdim[2], gdim[1], gdim[0])."""
+    lib = _load()
+    gmin = np.ascontiguousarray(np.asarray(gmin, np.int32))
+    gdim = np.ascontiguousarray(np.asarray(gdim, np.int32))
+    n = int(np.prod(gdim.astype(np.int64)))
+    dist = np.zeros(n, np.float64)
+    weight = np.zeros(n, np.float64)
+    for img, T in zip(images, poses):
+        img = _f32(img)
+        H, W = img.shape
+        r = lib.ora_dense_integrate_range(precision, params.voxel_size, params.truncation_vox, params.max_weight,
+                                          params.max_range, WEIGHTINGS[params.weighting], img, W, H,
+                                          _f32(lidar.params(), 6), _f32(T, 16), gmin, gdim, dist, weight)
+        if r < 0:
+            raise ValueError("oracle rejected the range image")
+    shape = (int(gdim[2]), int(gdim[1]), int(gdim[0]))
+    return dist.reshape(shape), weight.reshape(shape)
+
+
+def atan2_f32(y: float, x: float) -> float:
+    return float(_load().ora_atan2_f32(y, x))
 
 
 def round_binary16(x: float) -> float:

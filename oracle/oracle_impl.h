@@ -29,6 +29,11 @@ typedef struct {
     REAL w_max, d_max;
     int weighting;
     const float *depth;
+    /* spherical range images (Eq. (3)) */
+    REAL az_start, alpha;     /* azimuth of column 0's left edge; columns per radian */
+    REAL pol_start, beta;     /* polar angle (from +z) of row 0's top edge; rows per radian */
+    REAL interp_diff;         /* largest spread of the 4 interpolated ranges */
+    int full_circle;          /* columns wrap around (azimuth field of view >= 2 pi) */
 } FN(frame);
 
 /* Frame set-up.  The inverse of a rigid pose is (R^T, -R^T t).  R^T is exact;
@@ -66,6 +71,23 @@ static void FN(frame_setup)(FN(frame) *f, const ora_params *p, const float *dept
     f->depth = depth;
 }
 
+/* The TSDF functor after sampling (§IV-B): truncation band, weight, clamp.
+ * d is a valid measurement and dp = d - d_v the projective distance. */
+static int FN(measure_tail)(const FN(frame) *f, REAL dp, REAL *x, REAL *wm)
+{
+    /* voxels more than epsilon behind the surface are skipped, not clamped */
+    if (!(dp >= -f->eps))
+        return 0;
+    REAL w = (REAL)1;
+    if (f->weighting == ORA_WEIGHT_LINEAR_DROPOFF && dp < -f->delta)
+        w = (f->eps + dp) * f->span_inv;
+    if (!(w > 0))
+        return 0;
+    *x = dp < f->eps ? dp : f->eps;
+    *wm = w;
+    return 1;
+}
+
 /* One voxel against one frame (§IV-B, Eq. (1)-(2) and the TSDF functor).
  * g = global voxel index.  Returns 1 and the truncated distance *x and the
  * measurement weight *wm when the voxel is updated; 0 when it is not. */
@@ -98,17 +120,79 @@ static int FN(voxel_measure)(const FN(frame) *f, int32_t gx, int32_t gy, int32_t
         return 0;
     /* projective distance; voxel depth d_v is the camera-frame z for a depth image */
     REAL dp = d - zc;
-    /* voxels more than epsilon behind the surface are skipped, not clamped */
-    if (!(dp >= -f->eps))
+    return FN(measure_tail)(f, dp, x, wm);
+}
+
+/* One voxel against a spherical range image (Eq. (3)).  Sensor frame: x
+ * forward, y left, z up; azimuth theta = atan2(y, x), polar angle phi measured
+ * from +z (computed as atan2(sqrt(x^2 + y^2), z), the same angle as acos(z/r));
+ * column coordinate u = (theta - theta_start) alpha, row v = (phi - phi_start)
+ * beta, pixel (i, j) covering [i, i+1) x [j, j+1) with its beam at the centre.
+ * The range is interpolated bilinearly between the four beam centres around
+ * (u, v), and only when all four are valid and their spread is at most
+ * interp_diff, so that no value is interpolated across a foreground/background
+ * edge.  The voxel depth d_v is the Euclidean range of the voxel centre. */
+static int FN(voxel_measure_range)(const FN(frame) *f, int32_t gx, int32_t gy, int32_t gz, REAL *x, REAL *wm)
+{
+    const REAL half = (REAL)0.5, one = (REAL)1;
+    REAL px = ((REAL)gx + half) * f->vs;
+    REAL py = ((REAL)gy + half) * f->vs;
+    REAL pz = ((REAL)gz + half) * f->vs;
+    REAL xc = ((f->R[0] * px + f->R[1] * py) + f->R[2] * pz) + f->t[0];
+    REAL yc = ((f->R[3] * px + f->R[4] * py) + f->R[5] * pz) + f->t[1];
+    REAL zc = ((f->R[6] * px + f->R[7] * py) + f->R[8] * pz) + f->t[2];
+    REAL rv = SQRT((xc * xc + yc * yc) + zc * zc);
+    if (!(rv > 0))
         return 0;
-    REAL w = (REAL)1;
-    if (f->weighting == ORA_WEIGHT_LINEAR_DROPOFF && dp < -f->delta)
-        w = (f->eps + dp) * f->span_inv;
-    if (!(w > 0))
+    REAL theta = ATAN2(yc, xc);
+    REAL phi = ATAN2(SQRT(xc * xc + yc * yc), zc);
+    REAL uc = (theta - f->az_start) * f->alpha - half;
+    REAL vc = (phi - f->pol_start) * f->beta - half;
+    REAL fi = FLOOR(uc), fj = FLOOR(vc);
+    REAL fu = uc - fi, fv = vc - fj;
+    int32_t j0 = (int32_t)fj;
+    if (j0 < 0 || j0 + 1 > f->height - 1)
         return 0;
-    *x = dp < f->eps ? dp : f->eps;
-    *wm = w;
-    return 1;
+    int32_t i0 = (int32_t)fi, i1;
+    if (f->full_circle) {
+        i0 = ((i0 % f->width) + f->width) % f->width;
+        i1 = (i0 + 1) % f->width;
+    } else {
+        if (i0 < 0 || i0 + 1 > f->width - 1)
+            return 0;
+        i1 = i0 + 1;
+    }
+    const float *row0 = f->depth + (size_t)j0 * (size_t)f->width;
+    const float *row1 = row0 + f->width;
+    REAL r00 = (REAL)row0[i0], r10 = (REAL)row0[i1], r01 = (REAL)row1[i0], r11 = (REAL)row1[i1];
+    if (!(r00 > 0 && r00 <= f->d_max && r10 > 0 && r10 <= f->d_max && r01 > 0 && r01 <= f->d_max &&
+          r11 > 0 && r11 <= f->d_max))
+        return 0;
+    REAL mn = r00 < r10 ? r00 : r10, mx = r00 < r10 ? r10 : r00;
+    mn = r01 < mn ? r01 : mn;
+    mx = r01 > mx ? r01 : mx;
+    mn = r11 < mn ? r11 : mn;
+    mx = r11 > mx ? r11 : mx;
+    if (!(mx - mn <= f->interp_diff))
+        return 0;
+    REAL d = (one - fv) * ((one - fu) * r00 + fu * r10) + fv * ((one - fu) * r01 + fu * r11);
+    REAL dp = d - rv;
+    return FN(measure_tail)(f, dp, x, wm);
+}
+
+/* Frame set-up of a spherical range image: pose as for a camera, then the
+ * angular model (columns and rows per radian computed in REAL). */
+static void FN(range_setup)(FN(frame) *f, const ora_params *p, const float *range, int width, int height,
+                            const float model[5], const float T[16])
+{
+    const float K[4] = {1, 1, 0, 0};
+    FN(frame_setup)(f, p, range, width, height, K, T);
+    f->az_start = (REAL)model[0];
+    f->alpha = (REAL)width / (REAL)model[1];
+    f->pol_start = (REAL)model[2];
+    f->beta = (REAL)height / (REAL)model[3];
+    f->interp_diff = (REAL)model[4];
+    f->full_circle = (REAL)model[1] >= (REAL)6.28318548f;
 }
 
 /* Weighted average with capped weight sum (§IV-B): the running distance is
@@ -161,20 +245,64 @@ static int FN(scan_box)(const FN(frame) *f, const float K[4], const float T[16],
     return 1;
 }
 
+/* Block box of a spherical range image: every updated voxel lies within
+ * max valid range + epsilon of the sensor and inside the polar band, so inside
+ * the sensor-frame box [-R, R]^2 x [min(0, R cos phi_end), max(0, R cos phi_start)],
+ * whose world box, widened by one voxel, is returned.  0 if no pixel is valid. */
+static int FN(scan_box_range)(const FN(frame) *f, const float model[5], const float T[16],
+                              int32_t bmin[3], int32_t bmax[3])
+{
+    double rmax = -1.0;
+    for (size_t k = 0; k < (size_t)f->width * (size_t)f->height; ++k) {
+        float d = f->depth[k];
+        if (d > 0 && d <= (float)f->d_max && (double)d > rmax)
+            rmax = (double)d;
+    }
+    if (rmax <= 0)
+        return 0;
+    const double R = rmax + (double)f->eps;
+    const double zlo = fmin(0.0, R * cos((double)model[2] + (double)model[3]));
+    const double zhi = fmax(0.0, R * cos((double)model[2]));
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a)
+        lo[a] = hi[a] = (double)T[4 * a + 3];
+    for (int c = 0; c < 8; ++c) {
+        const double pc[3] = {(c & 1) ? R : -R, (c & 2) ? R : -R, (c & 4) ? zhi : zlo};
+        for (int a = 0; a < 3; ++a) {
+            double w = (double)T[4 * a + 3];
+            for (int b = 0; b < 3; ++b)
+                w += (double)T[4 * a + b] * pc[b];
+            if (w < lo[a]) lo[a] = w;
+            if (w > hi[a]) hi[a] = w;
+        }
+    }
+    double edge = 8.0 * (double)f->vs;
+    for (int a = 0; a < 3; ++a) {
+        bmin[a] = (int32_t)floor((lo[a] - (double)f->vs) / edge);
+        bmax[a] = (int32_t)floor((hi[a] + (double)f->vs) / edge);
+    }
+    return 1;
+}
+
 static REAL *FN(dist_ptr)(ora_map *m) { return (REAL *)m->dist; }
 static REAL *FN(weight_ptr)(ora_map *m) { return (REAL *)m->weight; }
 
 /* One frame into the sparse map.  Every block of the scan box is evaluated
  * voxel by voxel; a block that has at least one updated voxel is looked up or
- * inserted in the block hash (§IV-A) and its updated voxels are fused. */
-static long long FN(integrate)(ora_map *m, const float *depth, int width, int height,
-                               const float K[4], const float T[16])
+ * inserted in the block hash (§IV-A) and its updated voxels are fused.
+ * model == NULL: pinhole depth image; otherwise a spherical range image. */
+static long long FN(integrate_any)(ora_map *m, const float *depth, int width, int height,
+                                   const float K[4], const float *model, const float T[16])
 {
     FN(frame) f;
-    FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    if (model)
+        FN(range_setup)(&f, &m->p, depth, width, height, model, T);
+    else
+        FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
     m->n_touched = 0;
     int32_t bmin[3], bmax[3];
-    if (!FN(scan_box)(&f, K, T, bmin, bmax)) {
+    const int any_valid = model ? FN(scan_box_range)(&f, model, T, bmin, bmax) : FN(scan_box)(&f, K, T, bmin, bmax);
+    if (!any_valid) {
         for (int a = 0; a < 3; ++a) { m->scan_min[a] = 0; m->scan_max[a] = -1; }
         return 0;
     }
@@ -190,8 +318,9 @@ static long long FN(integrate)(ora_map *m, const float *depth, int width, int he
                     for (int ly = 0; ly < 8; ++ly)
                         for (int lx = 0; lx < 8; ++lx) {
                             int k = lx + 8 * ly + 64 * lz;
-                            hit[k] = (unsigned char)FN(voxel_measure)(
-                                &f, 8 * bx + lx, 8 * by + ly, 8 * bz + lz, &xs[k], &ws[k]);
+                            hit[k] = (unsigned char)(model
+                                ? FN(voxel_measure_range)(&f, 8 * bx + lx, 8 * by + ly, 8 * bz + lz, &xs[k], &ws[k])
+                                : FN(voxel_measure)(&f, 8 * bx + lx, 8 * by + ly, 8 * bz + lz, &xs[k], &ws[k]));
                             any |= hit[k];
                         }
                 if (!any)
@@ -214,6 +343,12 @@ static long long FN(integrate)(ora_map *m, const float *depth, int width, int he
                     }
             }
     return updates;
+}
+
+static long long FN(integrate)(ora_map *m, const float *depth, int width, int height,
+                               const float K[4], const float T[16])
+{
+    return FN(integrate_any)(m, depth, width, height, K, NULL, T);
 }
 
 static void FN(export_voxels)(const ora_map *m, double *dist, double *weight)
@@ -240,6 +375,29 @@ static long long FN(dense)(const ora_params *p, const float *depth, int width, i
             for (int32_t x = 0; x < gdim[0]; ++x, ++k) {
                 REAL xv, wv;
                 if (!FN(voxel_measure)(&f, gmin[0] + x, gmin[1] + y, gmin[2] + z, &xv, &wv))
+                    continue;
+                REAL D = (REAL)dist[k], W = (REAL)weight[k];
+                FN(voxel_fuse)(&D, &W, xv, wv, f.w_max);
+                dist[k] = (double)D;
+                weight[k] = (double)W;
+                ++updates;
+            }
+    return updates;
+}
+
+static long long FN(dense_range)(const ora_params *p, const float *range, int width, int height,
+                                 const float model[6], const float T[16],
+                                 const int32_t gmin[3], const int32_t gdim[3], double *dist, double *weight)
+{
+    FN(frame) f;
+    FN(range_setup)(&f, p, range, width, height, model, T);
+    long long updates = 0;
+    size_t k = 0;
+    for (int32_t z = 0; z < gdim[2]; ++z)
+        for (int32_t y = 0; y < gdim[1]; ++y)
+            for (int32_t x = 0; x < gdim[0]; ++x, ++k) {
+                REAL xv, wv;
+                if (!FN(voxel_measure_range)(&f, gmin[0] + x, gmin[1] + y, gmin[2] + z, &xv, &wv))
                     continue;
                 REAL D = (REAL)dist[k], W = (REAL)weight[k];
                 FN(voxel_fuse)(&D, &W, xv, wv, f.w_max);

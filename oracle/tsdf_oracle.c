@@ -163,17 +163,63 @@ static int touched_push(ora_map *m, long long b)
     return 0;
 }
 
+/* atan on [0, 1]: the polynomial of Abramowitz & Stegun, Handbook of
+ * Mathematical Functions, formula 4.4.49 (|error| <= 2e-8), evaluated by
+ * Horner's rule in binary32. */
+static float atan_unit_f32(float t)
+{
+    const float t2 = t * t;
+    float p = 0.0028662257f;
+    p = p * t2 + -0.0161657367f;
+    p = p * t2 + 0.0429096138f;
+    p = p * t2 + -0.0752896400f;
+    p = p * t2 + 0.1065626393f;
+    p = p * t2 + -0.1420889944f;
+    p = p * t2 + 0.1999355085f;
+    p = p * t2 + -0.3333314528f;
+    p = p * t2 + 1.0f;
+    return p * t;
+}
+
+/* atan2 in binary32 from atan on [0, 1] by octant reduction; (0, 0) -> 0. */
+float ora_atan2_f32(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    if (ax == 0.0f && ay == 0.0f)
+        return 0.0f;
+    const int swap = ay > ax;
+    const float t = swap ? ax / ay : ay / ax;
+    float a = atan_unit_f32(t);
+    if (swap)
+        a = 1.57079637f - a;
+    if (x < 0.0f)
+        a = 3.14159274f - a;
+    return y < 0.0f ? -a : a;
+}
+
 #define REAL float
 #define SFX _f32
+#define SQRT sqrtf
+#define FLOOR floorf
+#define ATAN2 ora_atan2_f32
 #include "oracle_impl.h"
 #undef REAL
 #undef SFX
+#undef SQRT
+#undef FLOOR
+#undef ATAN2
 
 #define REAL double
 #define SFX _f64
+#define SQRT sqrt
+#define FLOOR floor
+#define ATAN2 atan2
 #include "oracle_impl.h"
 #undef REAL
 #undef SFX
+#undef SQRT
+#undef FLOOR
+#undef ATAN2
 
 static int params_ok(int precision, float vs, float tau, float wmax, float dmax, int weighting)
 {
@@ -250,6 +296,39 @@ long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, i
     const long long n = ora_integrate_depth(m, depth, width, height, K, T);
     m->p.max_range = saved;
     return n;
+}
+
+long long ora_integrate_range(ora_map *m, const float *range, int width, int height,
+                              const float model[6], const float T[16])
+{
+    if (!m || !range || !model || !T || width <= 1 || height <= 1)
+        return -1;
+    if (!(model[1] > 0 && model[3] > 0 && model[4] >= 0 && isfinite(model[0]) && isfinite(model[1]) &&
+          isfinite(model[2]) && isfinite(model[3]) && isfinite(model[4]) && model[5] >= 0 && isfinite(model[5])))
+        return -1;
+    for (int k = 0; k < 16; ++k)
+        if (!isfinite(T[k]))
+            return -1;
+    const float saved = m->p.max_range;
+    if (model[5] > 0)
+        m->p.max_range = model[5];
+    const long long n = m->precision == 32 ? integrate_any_f32(m, range, width, height, NULL, model, T)
+                                           : integrate_any_f64(m, range, width, height, NULL, model, T);
+    m->p.max_range = saved;
+    return n;
+}
+
+long long ora_dense_integrate_range(int precision, float voxel_size, float truncation_vox, float max_weight,
+                                    float max_range, int weighting, const float *range, int width, int height,
+                                    const float model[6], const float T[16], const int32_t gmin[3],
+                                    const int32_t gdim[3], double *dist, double *weight)
+{
+    if (!params_ok(precision, voxel_size, truncation_vox, max_weight, max_range, weighting) || !range ||
+        !model || !T || width <= 1 || height <= 1 || !gmin || !gdim || !dist || !weight)
+        return -1;
+    ora_params p = {voxel_size, truncation_vox, max_weight, model[5] > 0 ? model[5] : max_range, weighting};
+    return precision == 32 ? dense_range_f32(&p, range, width, height, model, T, gmin, gdim, dist, weight)
+                           : dense_range_f64(&p, range, width, height, model, T, gmin, gdim, dist, weight);
 }
 
 long long ora_num_blocks(const ora_map *m) { return m ? m->n_blocks : 0; }

@@ -66,6 +66,26 @@ long long ora_integrate_depth(ora_map *m, const float *depth, int width, int hei
 long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, int height,
                                     const float K[4], const float T_world_cam[16], float max_range);
 
+/* Integrates one spherical range image (Eq. (3); row-major float32,
+ * width columns of azimuth x height rows of polar angle, Euclidean range in
+ * metres) seen from T_world_sensor (sensor frame: x forward, y left, z up).
+ * model = {azimuth start, azimuth field of view, polar start (from +z),
+ * polar field of view, largest interpolated spread, max range (0: the
+ * map's)}, angles in radians.  Returns the number of voxel updates or -1. */
+long long ora_integrate_range(ora_map *m, const float *range, int width, int height,
+                              const float model[6], const float T_world_sensor[16]);
+
+/* Dense brute force of ora_integrate_range over the voxel box
+ * [gmin, gmin + gdim), as ora_dense_integrate. */
+long long ora_dense_integrate_range(int precision, float voxel_size, float truncation_vox, float max_weight,
+                                    float max_range, int weighting, const float *range, int width, int height,
+                                    const float model[6], const float T_world_sensor[16], const int32_t gmin[3],
+                                    const int32_t gdim[3], double *dist, double *weight);
+
+/* binary32 atan2 the binary32 oracle uses for Eq. (3) (Abramowitz & Stegun
+ * 4.4.49 with octant reduction). */
+float ora_atan2_f32(float y, float x);
+
 long long ora_num_blocks(const ora_map *m);
 /* Block indices (x, y, z), 3 int32 per block, in insertion order. */
 void ora_blocks(const ora_map *m, int32_t *xyz);

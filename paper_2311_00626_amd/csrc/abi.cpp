@@ -24,6 +24,7 @@ struct tsdf_map {
     int sticky;                           // host copy of an observed device error (TSDF_EFULL) or 0
     float eps, delta, span_inv;           // per-map constants in binary32
     int max_groups;                       // cap on integration workgroups per launch
+    tsdf_launch_config launch;            // explicit launch shape (0 fields = automatic)
     long long frames;                     // integrate calls launched so far (parity of the touched counters)
     // kernel timing
     bool profiling;
@@ -148,6 +149,7 @@ int camera_view(const tsdf_map *m, const float *depth, int width, int height, co
     cv.height_f = (float)height;
     cv.depth = depth;
     cv.d_max = max_range;
+    cv.model = kModelPinhole;
 
     // An updated voxel has 0 < z <= d + eps <= max_range + eps and projects
     // into the image: it lies in the pyramid of the camera centre and the
@@ -177,6 +179,59 @@ int camera_view(const tsdf_map *m, const float *depth, int width, int height, co
     cv.margin_u = (float)(e * ((double)K[0] + std::fabs((double)K[2]) + (double)width));
     cv.margin_v = (float)(e * ((double)K[1] + std::fabs((double)K[3]) + (double)height));
     return TSDF_OK;
+}
+
+// Per-view constants of a spherical range image (Eq. (3)); the pose as for a
+// camera.  Columns and rows per radian are binary32 divisions, as in the
+// oracle.  Every updated voxel lies within R = max_range + eps of the sensor
+// and inside the polar band, so inside the sensor-frame box
+// [-R, R]^2 x [min(0, R cos phi_end), max(0, R cos phi_start)].
+int spherical_view(const tsdf_map *m, const float *range, int width, int height, const float A[4], float interp,
+                   const float T[16], float max_range, CameraView &cv, double lo[3], double hi[3])
+{
+    const float K[4] = {1.0f, 1.0f, 0.0f, 0.0f};
+    camera_view(m, range, width, height, K, T, max_range, cv, lo, hi);
+    cv.model = kModelSpherical;
+    cv.az_start = A[0];
+    cv.alpha = (float)width / A[1];
+    cv.pol_start = A[2];
+    cv.beta = (float)height / A[3];
+    cv.interp_diff = interp;
+    cv.full_circle = A[1] >= 6.28318548f ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        cv.origin[a] = T[4 * a + 3];
+    cv.cos_pol_start = (float)std::cos((double)A[2]);
+    cv.cos_pol_end = (float)std::cos((double)A[2] + (double)A[3]);
+    const double R = (double)max_range + (double)m->eps;
+    cv.zfar = (float)R;
+    const double zlo = std::min(0.0, R * std::cos((double)A[2] + (double)A[3]));
+    const double zhi = std::max(0.0, R * std::cos((double)A[2]));
+    for (int a = 0; a < 3; ++a)
+        lo[a] = hi[a] = (double)T[4 * a + 3];
+    for (int c = 0; c < 8; ++c) {
+        const double pc[3] = {(c & 1) ? R : -R, (c & 2) ? R : -R, (c & 4) ? zhi : zlo};
+        for (int a = 0; a < 3; ++a) {
+            double w = (double)T[4 * a + 3];
+            for (int b = 0; b < 3; ++b)
+                w += (double)T[4 * a + b] * pc[b];
+            lo[a] = std::min(lo[a], w);
+            hi[a] = std::max(hi[a], w);
+        }
+    }
+    return TSDF_OK;
+}
+
+bool lidar_valid(int width, int height, const float A[4], float interp, float max_range)
+{
+    if (width < 2 || height < 2 || (long long)width * (long long)height > (1ll << 28))
+        return false;
+    if (!finite_all(A, 4) || !std::isfinite(interp) || !std::isfinite(max_range))
+        return false;
+    const double pi = 3.14159265358979323846;
+    if (!(A[1] > 0.0f && A[1] <= 6.28318548f && A[3] > 0.0f && A[2] >= 0.0f && A[2] < pi &&
+          (double)A[2] + (double)A[3] <= pi + 1e-6))
+        return false;
+    return interp >= 0.0f && max_range >= 0.0f;
 }
 
 void map_consts(const tsdf_map *m, double max_extent, double max_zfar, MapConsts &mc)
@@ -254,10 +309,36 @@ void timing_end(tsdf_map *m, hipStream_t s, bool timed)
         ++m->ev_used;
 }
 
-int groups_for(const tsdf_map *m, long long n_lat)
+// Makes the map's device current (a no-op when it already is).
+hipError_t use_device(const tsdf_map *m)
 {
-    long long groups = (n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
-    return (int)std::max(1ll, std::min(groups, (long long)m->max_groups));
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != m->device)
+        e = hipSetDevice(m->device);
+    return e;
+}
+
+// Launch shape (tuned on MI355X).  Small lattices (a few blocks per wave) are
+// latency-bound: one block per wave pass keeps every touched block on its own
+// wave.  Large lattices (fine voxels, long ranges) cull 8 blocks per wave pass.
+// Image-band ownership per XCD (partitions = 8) cuts L2 fills but measured
+// slower on both regimes, so it is only used when asked for.  Fields of the
+// map's launch configuration override these choices.
+int schedule(const tsdf_map *m, Lattice &lat)
+{
+    const tsdf_launch_config &lc = m->launch;
+    long long max_groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
+    max_groups = std::max<long long>(kPartitions, max_groups / kPartitions * kPartitions);
+    const long long full_waves = max_groups * kWavesPerGroup;
+    const int parts = lc.partitions > 0 ? lc.partitions : 1;
+    long long groups = (lat.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
+    groups = (groups + kPartitions - 1) / kPartitions * kPartitions;
+    groups = std::max<long long>(kPartitions, std::min<long long>(groups, max_groups));
+    const long long chunk = lc.chunk > 0 ? lc.chunk : (lat.n_lat > 4 * full_waves ? 8 : 1);
+    lat.chunk = (int)std::max(1ll, std::min<long long>(chunk, kMaxChunk));
+    lat.partitions = parts;
+    return (int)groups;
 }
 
 struct CounterSnapshot {
@@ -331,7 +412,8 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     m->eps = p->truncation_vox * p->voxel_size_m;
     m->delta = p->voxel_size_m;
     m->span_inv = m->eps > m->delta ? 1.0f / (m->eps - m->delta) : 0.0f;
-    m->max_groups = 512;
+    m->max_groups = 512;   // a multiple of kPartitions
+    m->launch = tsdf_launch_config{0, 0, 0, 0};
     m->frames = 0;
     m->profiling = false;
     m->ev_used = 0;
@@ -394,6 +476,7 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     if (m->sticky)
         return TSDF_ESTATE;
     FrameArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
     double lo[3], hi[3];
     int st = camera_view(m, depth_dev, width, height, K, T_world_cam, m->p.max_range_m, fa.cam, lo, hi);
     if (st == TSDF_OK)
@@ -403,11 +486,48 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     map_consts(m, box_extent(lo, hi), (double)fa.cam.zfar, fa.mc);
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = hipSetDevice(m->device);
+    hipError_t e = use_device(m);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
-    e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups_for(m, fa.lat.n_lat), s);
+    const int groups = schedule(m, fa.lat);
+    e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    timing_end(m, s, timed);
+    ++m->frames;
+    return TSDF_OK;
+}
+
+int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model *lidar,
+                    const float T_world_sensor[16], void *hip_stream)
+{
+    if (!m || !range_dev || !lidar || !T_world_sensor || !pose_valid(T_world_sensor))
+        return TSDF_EINVAL;
+    const float A[4] = {lidar->azimuth_start_rad, lidar->azimuth_fov_rad, lidar->polar_start_rad,
+                        lidar->polar_fov_rad};
+    if (!lidar_valid(lidar->width, lidar->height, A, lidar->interp_max_diff_m, lidar->max_range_m))
+        return TSDF_EINVAL;
+    if (m->sticky)
+        return TSDF_ESTATE;
+    const float range = lidar->max_range_m > 0.0f ? lidar->max_range_m : m->p.max_range_m;
+    FrameArgs fa;
+    std::memset(&fa, 0, sizeof(fa));
+    double lo[3], hi[3];
+    spherical_view(m, range_dev, lidar->width, lidar->height, A, lidar->interp_max_diff_m, T_world_sensor, range,
+                   fa.cam, lo, hi);
+    int st = lattice_of(m, lo, hi, fa.lat);
+    if (st != TSDF_OK)
+        return st;
+    map_consts(m, box_extent(lo, hi), (double)fa.cam.zfar, fa.mc);
+    fa.parity = (int)(m->frames & 1);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = use_device(m);
+    if (e != hipSuccess)
+        return hip_status(e);
+    const bool timed = timing_begin(m, s);
+    const int groups = schedule(m, fa.lat);
+    e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
     timing_end(m, s, timed);
@@ -421,12 +541,18 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
         return TSDF_EINVAL;
     for (int v = 0; v < n_views; ++v) {
         const tsdf_depth_view &w = views[v];
-        if (w.model != TSDF_MODEL_PINHOLE || w.reserved != 0.0f)
+        if (w.reserved != 0.0f || !(w.max_range_m >= 0.0f && std::isfinite(w.max_range_m)))
             return TSDF_EINVAL;
-        if (!(w.max_range_m >= 0.0f && std::isfinite(w.max_range_m)))
+        if (w.model == TSDF_MODEL_PINHOLE) {
+            if (w.interp_max_diff_m != 0.0f || !view_args_valid(w.depth_dev, w.width, w.height, w.K, w.T_world_cam))
+                return TSDF_EINVAL;
+        } else if (w.model == TSDF_MODEL_SPHERICAL) {
+            if (!w.depth_dev || !pose_valid(w.T_world_cam) ||
+                !lidar_valid(w.width, w.height, w.K, w.interp_max_diff_m, w.max_range_m))
+                return TSDF_EINVAL;
+        } else {
             return TSDF_EINVAL;
-        if (!view_args_valid(w.depth_dev, w.width, w.height, w.K, w.T_world_cam))
-            return TSDF_EINVAL;
+        }
     }
     if (m->sticky)
         return TSDF_ESTATE;
@@ -436,8 +562,12 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
     for (int v = 0; v < n_views; ++v) {
         double vlo[3], vhi[3];
         const float range = views[v].max_range_m > 0.0f ? views[v].max_range_m : m->p.max_range_m;
-        const int st = camera_view(m, views[v].depth_dev, views[v].width, views[v].height, views[v].K,
-                                   views[v].T_world_cam, range, va.cam[v], vlo, vhi);
+        const int st = views[v].model == TSDF_MODEL_SPHERICAL
+                           ? spherical_view(m, views[v].depth_dev, views[v].width, views[v].height, views[v].K,
+                                            views[v].interp_max_diff_m, views[v].T_world_cam, range, va.cam[v],
+                                            vlo, vhi)
+                           : camera_view(m, views[v].depth_dev, views[v].width, views[v].height, views[v].K,
+                                         views[v].T_world_cam, range, va.cam[v], vlo, vhi);
         max_zfar = std::max(max_zfar, (double)va.cam[v].zfar);
         if (st != TSDF_OK)
             return st;
@@ -453,11 +583,12 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
     map_consts(m, box_extent(lo, hi), max_zfar, va.mc);
     va.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = hipSetDevice(m->device);
+    hipError_t e = use_device(m);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
-    e = launch_integrate_views(m->dm, va, m->p.weighting, groups_for(m, va.lat.n_lat), s);
+    const int groups = schedule(m, va.lat);
+    e = launch_integrate_views(m->dm, va, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
     timing_end(m, s, timed);
@@ -613,6 +744,20 @@ const char *tsdf_strerror(int status)
     case TSDF_ESTATE: return "map is in a sticky error state";
     default: return "unknown status";
     }
+}
+
+int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *lc)
+{
+    if (!m)
+        return TSDF_EINVAL;
+    tsdf_launch_config c = {0, 0, 0, 0};
+    if (lc)
+        c = *lc;
+    if (c.max_groups < 0 || c.max_groups > 65536 || c.chunk < 0 || c.chunk > kMaxChunk || c.reserved != 0 ||
+        (c.partitions != 0 && c.partitions != 1 && c.partitions != kPartitions))
+        return TSDF_EINVAL;
+    m->launch = c;
+    return TSDF_OK;
 }
 
 int tsdf_profile(tsdf_map *m, int enable)

@@ -202,28 +202,201 @@ __device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long lon
     return kInvalidSlot;
 }
 
-// Block culling against a view's frustum.  Lane c (mod 8) evaluates corner c;
-// the block is dropped when all 8 corners are outside one plane by more than
-// the margin, which exceeds the binary32 error of any voxel's projection.
-__device__ __forceinline__ bool block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+// Lane-level culling of one block against a pinhole view.  Each frustum plane
+// is a linear function f of the camera-frame point; over the block (a box
+// with corner p0 and edges E R[:,k] in camera coordinates) its maximum is
+// f(p0) + sum_k max(0, f(E R[:,k])).  The block is dropped when that maximum is
+// below -margin for some plane; the margin exceeds the binary32 error of any
+// voxel's projection, so no block holding an updated voxel is ever dropped.
+__device__ __forceinline__ bool lane_block_in_pinhole(const CameraView &cv, const MapConsts &mc, int bx, int by,
+                                                      int bz)
 {
-    const int c = lane_id() & 7;
-    const float X = (float)(8 * bx + ((c & 1) ? 8 : 0)) * mc.vs;
-    const float Y = (float)(8 * by + ((c & 2) ? 8 : 0)) * mc.vs;
-    const float Z = (float)(8 * bz + ((c & 4) ? 8 : 0)) * mc.vs;
-    const float xc = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
-    const float yc = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
-    const float zc = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
-    const bool out_l = cv.fx * xc + cv.cx * zc < -cv.margin_u;
-    const bool out_r = (cv.width_f - cv.cx) * zc - cv.fx * xc < -cv.margin_u;
-    const bool out_t = cv.fy * yc + cv.cy * zc < -cv.margin_v;
-    const bool out_b = (cv.height_f - cv.cy) * zc - cv.fy * yc < -cv.margin_v;
-    const bool out_n = zc < -mc.margin_z;
-    const bool out_f = zc > cv.zfar + mc.margin_z;
-    const unsigned long long all = 0xFFull;
-    return !(((__ballot(out_l) & all) == all) || ((__ballot(out_r) & all) == all) ||
-             ((__ballot(out_t) & all) == all) || ((__ballot(out_b) & all) == all) ||
-             ((__ballot(out_n) & all) == all) || ((__ballot(out_f) & all) == all));
+    const float e = 8.0f * mc.vs;
+    const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
+    const float x0 = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
+    const float y0 = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
+    const float z0 = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
+    float ex[3], ey[3], ez[3];   // camera-frame edge vectors of the block
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ex[k] = e * cv.R[k];
+        ey[k] = e * cv.R[3 + k];
+        ez[k] = e * cv.R[6 + k];
+    }
+    auto box_max = [&](float a, float b, float c, float d) {   // max of a x + b y + c z + d
+        float m = a * x0 + b * y0 + c * z0 + d;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            m += fmaxf(0.0f, a * ex[k] + b * ey[k] + c * ez[k]);
+        return m;
+    };
+    if (box_max(cv.fx, 0.0f, cv.cx, 0.0f) < -cv.margin_u)                        // u >= 0
+        return false;
+    if (box_max(-cv.fx, 0.0f, cv.width_f - cv.cx, 0.0f) < -cv.margin_u)          // u <= W
+        return false;
+    if (box_max(0.0f, cv.fy, cv.cy, 0.0f) < -cv.margin_v)                        // v >= 0
+        return false;
+    if (box_max(0.0f, -cv.fy, cv.height_f - cv.cy, 0.0f) < -cv.margin_v)         // v <= H
+        return false;
+    if (box_max(0.0f, 0.0f, 1.0f, 0.0f) < -mc.margin_z)                          // z > 0
+        return false;
+    if (box_max(0.0f, 0.0f, -1.0f, cv.zfar) < -mc.margin_z)                      // z <= zfar
+        return false;
+    return true;
+}
+
+// Lane-level culling of one block against a spherical view.  Dropped when
+// the block's closest point is farther than the largest usable range, or when
+// all 8 corners lie strictly inside the cone above the polar band (or below
+// it): z - |p| cos(phi_start) and -z + |p| cos(phi_end) are concave, so their
+// minimum over the box is at a corner.
+__device__ __forceinline__ bool lane_block_in_spherical(const CameraView &cv, const MapConsts &mc, int bx, int by,
+                                                        int bz)
+{
+    const float e = 8.0f * mc.vs;
+    const float lo[3] = {(float)(8 * bx) * mc.vs, (float)(8 * by) * mc.vs, (float)(8 * bz) * mc.vs};
+    float d2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float below = lo[a] - cv.origin[a];
+        const float above = cv.origin[a] - (lo[a] + e);
+        const float g = fmaxf(0.0f, fmaxf(below, above));
+        d2 += g * g;
+    }
+    const float reach = cv.zfar + mc.margin_z;
+    if (d2 > reach * reach)
+        return false;
+    float min_up = 3.0e38f, min_down = 3.0e38f;
+    for (int c = 0; c < 8; ++c) {
+        const float X = lo[0] + ((c & 1) ? e : 0.0f), Y = lo[1] + ((c & 2) ? e : 0.0f),
+                    Z = lo[2] + ((c & 4) ? e : 0.0f);
+        const float x = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
+        const float y = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
+        const float z = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
+        const float r = sqrtf(x * x + y * y + z * z);
+        min_up = fminf(min_up, z - r * cv.cos_pol_start);
+        min_down = fminf(min_down, -z + r * cv.cos_pol_end);
+    }
+    if (cv.cos_pol_start > 0.0f && min_up > mc.margin_z)
+        return false;
+    if (cv.cos_pol_end < 0.0f && min_down > mc.margin_z)
+        return false;
+    return true;
+}
+
+__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+{
+    return cv.model == kModelSpherical ? lane_block_in_spherical(cv, mc, bx, by, bz)
+                                       : lane_block_in_pinhole(cv, mc, bx, by, bz);
+}
+
+// atan on [0, 1]: the polynomial of Abramowitz & Stegun, Handbook of
+// Mathematical Functions, formula 4.4.49 (|error| <= 2e-8), Horner's rule in
+// binary32; atan2 by octant reduction, (0, 0) -> 0.  The CPU oracle evaluates
+// the same operations, so column and row decisions agree bit for bit.
+__device__ __forceinline__ float atan_unit(float t)
+{
+    const float t2 = t * t;
+    float p = 0.0028662257f;
+    p = p * t2 + -0.0161657367f;
+    p = p * t2 + 0.0429096138f;
+    p = p * t2 + -0.0752896400f;
+    p = p * t2 + 0.1065626393f;
+    p = p * t2 + -0.1420889944f;
+    p = p * t2 + 0.1999355085f;
+    p = p * t2 + -0.3333314528f;
+    p = p * t2 + 1.0f;
+    return p * t;
+}
+
+__device__ __forceinline__ float atan2_as(float y, float x)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const bool swap = ay > ax;
+    const float t = swap ? ax / ay : ay / ax;
+    float a = atan_unit(t);
+    if (swap)
+        a = 1.57079637f - a;
+    if (x < 0.0f)
+        a = 3.14159274f - a;
+    a = y < 0.0f ? -a : a;
+    return (ax == 0.0f && ay == 0.0f) ? 0.0f : a;
+}
+
+// Ownership band of a block (one per XCD): the image-column band of the
+// block centre in the first view that sees the centre; the lattice index
+// otherwise.  Every wave computes the same band for a block, so exactly one
+// partition processes it, and a partition's waves touch about 1/kPartitions of
+// each image.
+__device__ __forceinline__ int block_band(const CameraView *cams, int n_views, const MapConsts &mc, int bx, int by,
+                                          int bz, uint32_t lb)
+{
+    const float X = ((float)(8 * bx) + 4.0f) * mc.vs, Y = ((float)(8 * by) + 4.0f) * mc.vs,
+                Z = ((float)(8 * bz) + 4.0f) * mc.vs;
+    for (int v = 0; v < n_views; ++v) {
+        const CameraView &cv = cams[v];
+        const float x = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
+        const float y = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
+        const float z = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
+        if (cv.model == kModelSpherical) {
+            const float u = (atan2_as(y, x) - cv.az_start) * cv.alpha;
+            if (u >= 0.0f && u < cv.width_f)
+                return min((int)(u * (float)kPartitions / cv.width_f), kPartitions - 1);
+            continue;
+        }
+        if (!(z > 0.0f))
+            continue;
+        const float u = cv.fx * (x / z) + cv.cx;
+        const float w = cv.fy * (y / z) + cv.cy;
+        if (u >= 0.0f && u < cv.width_f && w >= 0.0f && w < cv.height_f)
+            return min((int)(u * (float)kPartitions / cv.width_f), kPartitions - 1);
+    }
+    return (int)(lb % (uint32_t)kPartitions);
+}
+
+// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
+// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
+// P = 8) scans all chunks; each lane bands and culls one block, and the
+// surviving blocks of this partition are handed to body(bx, by, bz, view_mask)
+// one at a time (wave-uniform).
+template <class Body>
+__device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
+                                             const MapConsts &mc, Body &&body)
+{
+    const int lane = lane_id();
+    const uint32_t P = (uint32_t)lat.partitions;
+    const int part = (int)(blockIdx.x % P);
+    const uint32_t waves_pp = (gridDim.x / P) * (uint32_t)kWavesPerGroup;
+    const uint32_t wave_pp = (blockIdx.x / P) * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6);
+    const uint32_t n_lat = (uint32_t)lat.n_lat;
+    const uint32_t chunk = (uint32_t)lat.chunk;
+    const uint32_t n_chunks = (n_lat + chunk - 1) / chunk;
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    for (uint32_t c = wave_pp; c < n_chunks; c += waves_pp) {
+        const uint32_t lb = c * chunk + (uint32_t)lane;
+        uint32_t vmask = 0;
+        int bx = 0, by = 0, bz = 0;
+        if ((uint32_t)lane < chunk && lb < n_lat) {
+            const uint32_t rest = lb / dim_x;
+            bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+            by = lat.lat_min[1] + (int)(rest % dim_y);
+            bz = lat.lat_min[2] + (int)(rest / dim_y);
+            if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
+                for (int v = 0; v < n_views; ++v)
+                    if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                        vmask |= 1u << v;
+        }
+        unsigned long long todo = __ballot(vmask != 0);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int sbx = __builtin_amdgcn_readlane(bx, src);
+            const int sby = __builtin_amdgcn_readlane(by, src);
+            const int sbz = __builtin_amdgcn_readlane(bz, src);
+            const uint32_t svm = (uint32_t)__builtin_amdgcn_readlane((int)vmask, src);
+            body(sbx, sby, sbz, svm);
+        }
+    }
 }
 
 // Eq. (1)-(2) and the TSDF measurement (§IV-B) of the lane's 8 voxels
@@ -277,6 +450,90 @@ __device__ __forceinline__ uint32_t measure_pinhole(const CameraView &cv, const 
         hit |= (upd ? 1u : 0u) << s;
     }
     return hit;
+}
+
+// Eq. (3) and the TSDF measurement (§IV-B) of the lane's 8 voxels against a
+// spherical range image: azimuth theta = atan2(y, x), polar angle phi =
+// atan2(sqrt(x^2 + y^2), z) (the angle acos(z / r)), pixel coordinates
+// u = (theta - theta_start) alpha, v = (phi - phi_start) beta; the range is
+// interpolated bilinearly between the 4 beam centres around (u, v) only when
+// all 4 are valid and their spread is at most interp_diff; the voxel depth is
+// its Euclidean range.  Same operation order as the CPU oracle.
+template <int WEIGHTING>
+__device__ __forceinline__ uint32_t measure_spherical(const CameraView &cv, const MapConsts &mc, float px, float py,
+                                                      int bz, float xs[8], float ws[8])
+{
+    const uint32_t width = (uint32_t)cv.width;
+    const __amdgpu_buffer_rsrc_t range = make_rsrc(cv.depth, 4u * width * (uint32_t)cv.height);
+    const float ax = cv.R[0] * px + cv.R[1] * py;
+    const float ay = cv.R[3] * px + cv.R[4] * py;
+    const float az = cv.R[6] * px + cv.R[7] * py;
+    uint32_t hit = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const float pz = ((float)(8 * bz + s) + 0.5f) * mc.vs;
+        const float xc = (ax + cv.R[2] * pz) + cv.t[0];
+        const float yc = (ay + cv.R[5] * pz) + cv.t[1];
+        const float zc = (az + cv.R[8] * pz) + cv.t[2];
+        const float rv = sqrtf((xc * xc + yc * yc) + zc * zc);
+        const float theta = atan2_as(yc, xc);
+        const float phi = atan2_as(sqrtf(xc * xc + yc * yc), zc);
+        const float uc = (theta - cv.az_start) * cv.alpha - 0.5f;
+        const float vc = (phi - cv.pol_start) * cv.beta - 0.5f;
+        const float fi = floorf(uc), fj = floorf(vc);
+        const float fu = uc - fi, fv = vc - fj;
+        // rows never wrap; columns wrap for a full circle
+        const bool row_ok = rv > 0.0f && fj >= 0.0f && fj + 1.0f <= cv.height_f - 1.0f;
+        int i0 = row_ok ? (int)fi : 0;
+        int i1;
+        bool col_ok;
+        if (cv.full_circle) {
+            i0 = ((i0 % cv.width) + cv.width) % cv.width;
+            i1 = (i0 + 1) % cv.width;
+            col_ok = true;
+        } else {
+            col_ok = i0 >= 0 && i0 + 1 <= cv.width - 1;
+            i1 = i0 + 1;
+        }
+        const bool ok = row_ok && col_ok;
+        const uint32_t j0 = ok ? (uint32_t)fj : 0u;
+        const uint32_t o00 = ok ? 4u * (j0 * width + (uint32_t)i0) : kOutOfRange;
+        const uint32_t o10 = ok ? 4u * (j0 * width + (uint32_t)i1) : kOutOfRange;
+        const uint32_t o01 = ok ? o00 + 4u * width : kOutOfRange;
+        const uint32_t o11 = ok ? o10 + 4u * width : kOutOfRange;
+        const float r00 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(range, o00, 0, 0));
+        const float r10 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(range, o10, 0, 0));
+        const float r01 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(range, o01, 0, 0));
+        const float r11 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(range, o11, 0, 0));
+        const bool valid = r00 > 0.0f && r00 <= cv.d_max && r10 > 0.0f && r10 <= cv.d_max && r01 > 0.0f &&
+                           r01 <= cv.d_max && r11 > 0.0f && r11 <= cv.d_max;
+        float mn = r00 < r10 ? r00 : r10, mx = r00 < r10 ? r10 : r00;
+        mn = r01 < mn ? r01 : mn;
+        mx = r01 > mx ? r01 : mx;
+        mn = r11 < mn ? r11 : mn;
+        mx = r11 > mx ? r11 : mx;
+        const float d = (1.0f - fv) * ((1.0f - fu) * r00 + fu * r10) + fv * ((1.0f - fu) * r01 + fu * r11);
+        const float dp = d - rv;
+        float wm = 1.0f;
+        if (WEIGHTING == 1 && dp < -mc.delta)
+            wm = (mc.eps + dp) * mc.span_inv;
+        const bool upd = ok && valid && mx - mn <= cv.interp_diff && dp >= -mc.eps && wm > 0.0f;
+        xs[s] = dp < mc.eps ? dp : mc.eps;
+        ws[s] = wm;
+        hit |= (upd ? 1u : 0u) << s;
+    }
+    return hit;
+}
+
+// SPHERICAL: 0 = every view is a pinhole camera (the spherical code is not
+// compiled in), 1 = the view's model decides.
+template <int WEIGHTING, int SPHERICAL>
+__device__ __forceinline__ uint32_t measure_view(const CameraView &cv, const MapConsts &mc, float px, float py,
+                                                 int bz, float xs[8], float ws[8])
+{
+    if (SPHERICAL && cv.model == kModelSpherical)
+        return measure_spherical<WEIGHTING>(cv, mc, px, py, bz, xs, ws);
+    return measure_pinhole<WEIGHTING>(cv, mc, px, py, bz, xs, ws);
 }
 
 // Weighted average with capped weight (§IV-B):
@@ -371,16 +628,6 @@ __device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
         if (prev != 0)
             atomicAdd(&dm.totals[kTotalTouched], (unsigned long long)prev);
     }
-}
-
-// Block index of lattice entry lb (x fastest).
-__device__ __forceinline__ void lattice_block(const Lattice &lat, uint32_t lb, int &bx, int &by, int &bz)
-{
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    const uint32_t rest = lb / dim_x;
-    bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-    by = lat.lat_min[1] + (int)(rest % dim_y);
-    bz = lat.lat_min[2] + (int)(rest / dim_y);
 }
 
 }  // namespace dev

@@ -2,11 +2,11 @@
 // single gfx950 kernel.
 //
 // One wave64 owns one block of the frame's block lattice at a time:
-//   1. culling  -- the block's 8 corners are tested against the view frustum
-//                  (side planes, camera plane, far plane); a block whose
-//                  corners are all outside one plane cannot hold an updated
-//                  voxel.  The lattice enumerates every block index once, so
-//                  the candidate set has no duplicates to remove.
+//   1. culling  -- lanes test consecutive lattice blocks against the view
+//                  frustum (side planes, camera plane, far plane) and keep the
+//                  blocks of their workgroup's band (XCD-local image columns);
+//                  the lattice enumerates every block index once, so the
+//                  candidate set has no duplicates to remove.
 //   2. measure  -- lane (lx, ly) projects the 8 voxels of its column
 //                  (Eq. (1)-(2)), samples the nearest pixel and keeps the
 //                  truncated projective distance and weight in registers; the
@@ -27,15 +27,12 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING, int STORAGE>
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa)
 {
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
     const int lx = lane & 7;
     const int ly = lane >> 3;
-    const uint32_t stride = gridDim.x * kWavesPerGroup;
-    const uint32_t n_lat = (uint32_t)fa.lat.n_lat;
     const int parity = fa.parity;
     const int sub = (int)(blockIdx.x % kSubLists);
     begin_launch(dm, parity);
@@ -44,12 +41,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
     int n_pending = 0;                 // wave-uniform
     uint32_t n_updates = 0;            // wave-uniform
 
-    for (uint32_t lb = blockIdx.x * kWavesPerGroup + (uint32_t)wave; lb < n_lat; lb += stride) {
-        int bx, by, bz;
-        lattice_block(fa.lat, lb, bx, by, bz);
-        if (!block_in_view(fa.cam, fa.mc, bx, by, bz))
-            continue;
-
+    scan_lattice(fa.lat, &fa.cam, 1, fa.mc, [&](int bx, int by, int bz, uint32_t) {
         // first hash probe window, consumed only if the block is touched
         const unsigned long long key = pack_key(bx, by, bz);
         const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
@@ -59,13 +51,13 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
         const float px = ((float)(8 * bx + lx) + 0.5f) * fa.mc.vs;
         const float py = ((float)(8 * by + ly) + 0.5f) * fa.mc.vs;
         float xs[8], ws[8];
-        const uint32_t hit = measure_pinhole<WEIGHTING>(fa.cam, fa.mc, px, py, bz, xs, ws);
+        const uint32_t hit = measure_view<WEIGHTING, SPHERICAL>(fa.cam, fa.mc, px, py, bz, xs, ws);
         if (__ballot(hit != 0) == 0ull)
-            continue;
+            return;
 
         const uint32_t slot = find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
-            continue;
+            return;
 
         // lanes whose voxel is not updated use an out-of-range offset: no load, no store
         using IO = VoxelIO<STORAGE>;
@@ -86,25 +78,35 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
             IO::store(blk, off[s], dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
-    }
+    });
     // one write per update: a single view updates a voxel at most once
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates);
 }
 
 }  // namespace
 
+template <int SPHERICAL>
+static void launch_depth_model(const DeviceMap &dm, const FrameArgs &fa, int weighting, dim3 grid, dim3 block,
+                               hipStream_t stream)
+{
+    if (weighting == 1 && dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 1, SPHERICAL>), grid, block, 0, stream, dm, fa);
+    else if (weighting == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 0, SPHERICAL>), grid, block, 0, stream, dm, fa);
+    else if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 1, SPHERICAL>), grid, block, 0, stream, dm, fa);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 0, SPHERICAL>), grid, block, 0, stream, dm, fa);
+}
+
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
                                   hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (weighting == 1 && dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 1>), grid, block, 0, stream, dm, fa);
-    else if (weighting == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 0>), grid, block, 0, stream, dm, fa);
-    else if (dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 1>), grid, block, 0, stream, dm, fa);
+    if (fa.cam.model == kModelSpherical)
+        launch_depth_model<1>(dm, fa, weighting, grid, block, stream);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 0>), grid, block, 0, stream, dm, fa);
+        launch_depth_model<0>(dm, fa, weighting, grid, block, stream);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@
 // view, so the batch stays bit-identical to storing and reloading per view.
 //
 // Per block of the union lattice of all views:
-//   1. culling against every view's frustum -> view mask (wave-uniform);
+//   1. culling against every view's frustum -> view mask (wave-uniform), only
+//      for blocks of the workgroup's band (XCD-local image columns);
 //   2. view 0 of the mask is measured while the first hash window is in flight;
 //   3. the block is looked up; an existing block's 512 voxels are loaded while
 //      the next view is being measured (software pipeline of depth 2);
@@ -27,15 +28,12 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING, int STORAGE>
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
 {
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
     const int lx = lane & 7;
     const int ly = lane >> 3;
-    const uint32_t stride = gridDim.x * kWavesPerGroup;
-    const uint32_t n_lat = (uint32_t)va.lat.n_lat;
     const int parity = va.parity;
     const int sub = (int)(blockIdx.x % kSubLists);
     begin_launch(dm, parity);
@@ -45,16 +43,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
     uint32_t n_updates = 0;   // voxel updates, one per voxel per view
     uint32_t n_writes = 0;    // voxels stored, one per voxel per launch
 
-    for (uint32_t lb = blockIdx.x * kWavesPerGroup + (uint32_t)wave; lb < n_lat; lb += stride) {
-        int bx, by, bz;
-        lattice_block(va.lat, lb, bx, by, bz);
-        uint32_t vmask = 0;
-        for (int v = 0; v < va.n_views; ++v)
-            if (block_in_view(va.cam[v], va.mc, bx, by, bz))
-                vmask |= 1u << v;
-        if (vmask == 0)
-            continue;
-
+    scan_lattice(va.lat, va.cam, va.n_views, va.mc, [&](int bx, int by, int bz, uint32_t vmask) {
         const unsigned long long key = pack_key(bx, by, bz);
         const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
         const ProbeWindow w0 = load_window(dm, h, 0);
@@ -66,7 +55,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
         float xa[8], wa[8];
         int v = __builtin_ctz(vmask);
         uint32_t rest = vmask & (vmask - 1);
-        uint32_t ha = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xa, wa);
+        uint32_t ha = measure_view<WEIGHTING, SPHERICAL>(va.cam[v], va.mc, px, py, bz, xa, wa);
 
         // state of an existing block, loaded while the next view is measured
         using IO = VoxelIO<STORAGE>;
@@ -91,7 +80,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
             if (more) {
                 v = __builtin_ctz(rest);
                 rest &= rest - 1;
-                hb = measure_pinhole<WEIGHTING>(va.cam[v], va.mc, px, py, bz, xb, wb);
+                hb = measure_view<WEIGHTING, SPHERICAL>(va.cam[v], va.mc, px, py, bz, xb, wb);
             }
             // fuse the pending view, in view order; the state is rounded to the
             // storage precision after every view, exactly as a store and reload would
@@ -112,11 +101,11 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
             ha = hb;
         }
         if (__ballot(any != 0) == 0ull)
-            continue;
+            return;
 
         const uint32_t slot = found != kInvalidSlot ? found : find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
-            continue;
+            return;
         const __amdgpu_buffer_rsrc_t blk = block_rsrc<STORAGE>(dm, slot);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -124,24 +113,37 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
             IO::store(blk, ((any >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
-    }
+    });
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes);
 }
 
 }  // namespace
 
+template <int SPHERICAL>
+static void launch_views_model(const DeviceMap &dm, const ViewsArgs &va, int weighting, dim3 grid, dim3 block,
+                               hipStream_t stream)
+{
+    if (weighting == 1 && dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else if (weighting == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+}
+
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
                                   hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (weighting == 1 && dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 1>), grid, block, 0, stream, dm, va);
-    else if (weighting == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 0>), grid, block, 0, stream, dm, va);
-    else if (dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 1>), grid, block, 0, stream, dm, va);
+    bool spherical = false;
+    for (int v = 0; v < va.n_views; ++v)
+        spherical = spherical || va.cam[v].model == kModelSpherical;
+    if (spherical)
+        launch_views_model<1>(dm, va, weighting, grid, block, stream);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 0>), grid, block, 0, stream, dm, va);
+        launch_views_model<0>(dm, va, weighting, grid, block, stream);
     return hipGetLastError();
 }
 

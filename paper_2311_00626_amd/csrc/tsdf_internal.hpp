@@ -15,6 +15,8 @@ constexpr int kBlockCoordMax = (1 << 20) - 1;       // |block index| limit on ev
 constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of wave64
 constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
 constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
+constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
+constexpr int kMaxChunk = 64;                       // lattice blocks culled together by one wave
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
 // Counter words, one hot counter per 128-byte line so that atomics on
@@ -60,17 +62,28 @@ struct DeviceMap {
 
 constexpr uint32_t voxel_bytes(int storage) { return storage == 1 ? 4u : 8u; }
 
-// One pinhole depth image and its pose (host-computed, passed by value).
+constexpr int kModelPinhole = 0;                    // depth camera, Eq. (2)
+constexpr int kModelSpherical = 1;                  // rotating LiDAR range image, Eq. (3)
+
+// One depth view and its pose (host-computed, passed by value).
 struct CameraView {
-    float R[9];             // camera-from-world rotation, row-major (T_CL of Eq. (1))
-    float t[3];             // camera-from-world translation
+    float R[9];             // sensor-from-world rotation, row-major (T_CL of Eq. (1))
+    float t[3];             // sensor-from-world translation
     float fx, fy, cx, cy;   // pinhole intrinsics (Eq. (2))
     float width_f, height_f;
     int width, height;
-    const float *depth;     // device float32[height][width]
+    const float *depth;     // device float32[height][width]: z-depth or range
     float d_max;            // max valid measurement of this view
-    float zfar;             // no voxel beyond camera depth zfar can be updated
+    float zfar;             // pinhole: no voxel beyond this camera z is updated; spherical: range
     float margin_u, margin_v;   // conservative slack of the side culling planes
+    int model;              // kModelPinhole or kModelSpherical
+    // spherical model (Eq. (3)); sensor frame x forward, y left, z up
+    float az_start, alpha;  // azimuth of column 0's left edge, columns per radian
+    float pol_start, beta;  // polar angle (from +z) of row 0's top edge, rows per radian
+    float interp_diff;      // largest spread of the 4 interpolated ranges
+    int full_circle;        // columns wrap around
+    float origin[3];        // sensor centre in the world (range culling)
+    float cos_pol_start, cos_pol_end;   // polar band edges (cone culling)
 };
 
 // Per-map constants in binary32.
@@ -83,11 +96,14 @@ struct MapConsts {
     float margin_z;         // conservative slack of the near/far culling planes
 };
 
-// Block lattice scanned by one launch.
+// Block lattice scanned by one launch.  Waves cull `chunk` consecutive
+// lattice entries at a time, one per lane.
 struct Lattice {
     int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
+    int chunk;              // 1 .. kMaxChunk
+    int partitions;         // 1 or kPartitions ownership bands
 };
 
 // Arguments of a single-frame launch.

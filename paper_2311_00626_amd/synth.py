@@ -116,19 +116,9 @@ def _ray_dirs_cam(cam: PinholeCamera, dev, dtype=torch.float64):
     return torch.stack([dx, dy, dz], dim=-1)  # (H, W, 3); z component is 1
 
 
-def render_depth(scene: Scene, cam: PinholeCamera, T_world_cam: np.ndarray,
-                 device: str = "cpu", chunk: int = 1 << 16) -> np.ndarray:
-    """Ray-cast z-depth (float32, H x W) of ``scene`` seen from ``T_world_cam``.
-
-    Every object is intersected with every ray in float64 (spheres and boxes
-    vectorised over objects, rays processed in chunks); pixels whose ray hits
-    nothing get depth 0 (invalid).
-    """
-    dev = torch.device(device)
-    f64 = torch.float64
-    T = torch.as_tensor(np.asarray(T_world_cam, dtype=np.float64), device=dev)
-    R, o = T[:3, :3], T[:3, 3]
-    dirs = (_ray_dirs_cam(cam, dev) @ R.T).reshape(-1, 3)   # world directions; t == z-depth
+def _cast(scene: Scene, o, dirs, chunk: int = 1 << 16):
+    """Distance t along each direction (o + t d) to the first surface, inf if none."""
+    dev, f64 = dirs.device, torch.float64
     dirs = torch.where(dirs == 0, torch.full_like(dirs, 1e-300), dirs)
     inf = float("inf")
     room = torch.tensor(scene.room, device=dev, dtype=f64) if scene.room is not None else None
@@ -176,9 +166,82 @@ def render_depth(scene: Scene, cam: PinholeCamera, T_world_cam: np.ndarray,
             t = torch.where((denom > 0) & (t > 0), t, torch.full_like(t, inf))
             t_best = torch.minimum(t_best, t.min(dim=-1).values)
         out.append(t_best)
-    t_best = torch.cat(out).reshape(cam.height, cam.width)
-    depth = torch.where(torch.isfinite(t_best), t_best, torch.zeros_like(t_best))
+    return torch.cat(out)
+
+
+def render_depth(scene: Scene, cam: PinholeCamera, T_world_cam: np.ndarray,
+                 device: str = "cpu") -> np.ndarray:
+    """Ray-cast z-depth (float32, H x W) of ``scene`` seen from ``T_world_cam``.
+
+    Every object is intersected with every ray in float64 (spheres and boxes
+    vectorised over objects, rays processed in chunks); pixels whose ray hits
+    nothing get depth 0 (invalid).  Ray directions have camera-frame z = 1, so
+    the distance along them is the z-depth.
+    """
+    dev = torch.device(device)
+    T = torch.as_tensor(np.asarray(T_world_cam, dtype=np.float64), device=dev)
+    R, o = T[:3, :3], T[:3, 3]
+    dirs = (_ray_dirs_cam(cam, dev) @ R.T).reshape(-1, 3)
+    t = _cast(scene, o, dirs).reshape(cam.height, cam.width)
+    depth = torch.where(torch.isfinite(t), t, torch.zeros_like(t))
     return depth.to(torch.float32).cpu().numpy()
+
+
+@dataclass(frozen=True)
+class LidarModel:
+    """Spherical range image (rotating LiDAR).  Sensor frame: x forward, y left,
+    z up.  Column i spans azimuths (atan2(y, x)) azimuth_start + [i, i+1) *
+    azimuth_fov / width, row j polar angles (from +z) polar_start + [j, j+1) *
+    polar_fov / height; each beam points at the centre of its pixel."""
+    width: int = 1024
+    height: int = 64
+    azimuth_start: float = -math.pi
+    azimuth_fov: float = 2.0 * math.pi
+    polar_start: float = math.radians(74.0)
+    polar_fov: float = math.radians(32.0)
+    interp_max_diff: float = 0.2
+    max_range: float = 25.0
+
+    def params(self) -> np.ndarray:
+        """float32 [azimuth start, azimuth fov, polar start, polar fov, interp max diff, max range]."""
+        return np.array([self.azimuth_start, self.azimuth_fov, self.polar_start, self.polar_fov,
+                         self.interp_max_diff, self.max_range], dtype=np.float32)
+
+
+def render_range(scene: Scene, lidar: LidarModel, T_world_sensor: np.ndarray,
+                 device: str = "cpu") -> np.ndarray:
+    """Ray-cast Euclidean range (float32, height x width) along the beam of
+    every pixel centre; 0 where a beam hits nothing."""
+    dev = torch.device(device)
+    p = lidar.params().astype(np.float64)
+    j, i = torch.meshgrid(torch.arange(lidar.height, device=dev, dtype=torch.float64),
+                          torch.arange(lidar.width, device=dev, dtype=torch.float64), indexing="ij")
+    theta = p[0] + (i + 0.5) * (p[1] / lidar.width)
+    phi = p[2] + (j + 0.5) * (p[3] / lidar.height)
+    ds = torch.stack([torch.sin(phi) * torch.cos(theta), torch.sin(phi) * torch.sin(theta), torch.cos(phi)], -1)
+    T = torch.as_tensor(np.asarray(T_world_sensor, dtype=np.float64), device=dev)
+    dirs = (ds @ T[:3, :3].T).reshape(-1, 3)
+    t = _cast(scene, T[:3, 3], dirs).reshape(lidar.height, lidar.width)
+    rng = torch.where(torch.isfinite(t), t, torch.zeros_like(t))
+    return rng.to(torch.float32).cpu().numpy()
+
+
+def pose_lidar(position: Sequence[float], yaw: float) -> np.ndarray:
+    """Level LiDAR pose (float32 4x4): x forward at ``yaw``, y left, z up."""
+    c, s_ = math.cos(yaw), math.sin(yaw)
+    T = np.eye(4)
+    T[:3, 0] = (c, s_, 0.0)
+    T[:3, 1] = (-s_, c, 0.0)
+    T[:3, 2] = (0.0, 0.0, 1.0)
+    T[:3, 3] = np.asarray(position, dtype=np.float64)
+    return T.astype(np.float32)
+
+
+def add_range_noise(rng_img: np.ndarray, rng: np.random.Generator, sigma: float = 0.02) -> np.ndarray:
+    """Range noise N(0, sigma^2) on valid returns."""
+    r = rng_img.astype(np.float64)
+    out = np.where(r > 0, r + sigma * rng.standard_normal(r.shape), 0.0)
+    return out.astype(np.float32)
 
 
 def add_depth_noise(depth: np.ndarray, rng: np.random.Generator, sigma_a: float = 0.0012,
@@ -375,6 +438,7 @@ RIG_SIZES = ((640, 480), (848, 480), (424, 240), (1280, 720))
 class RigStep:
     cameras: List[PinholeCamera]
     poses: List[np.ndarray]
+    lidar_pose: Optional[np.ndarray] = None
 
 
 def rig_cameras() -> List[PinholeCamera]:
@@ -404,5 +468,6 @@ def rig_sequence(n_steps: int, room=(20.0, 15.0, 3.0), speed: float = 0.5, rate:
         Tb = T.astype(np.float64)
         yaw0 = math.atan2(Tb[1, 2], Tb[0, 2])
         poses = [pose_from_forward(Tb[:3, 3], yaw0 + dy, dp) for (dy, dp) in ext]
-        steps.append(RigStep(cams, poses))
+        lidar_pose = pose_lidar(Tb[:3, 3] + np.array([0.0, 0.0, 0.15]), yaw0)
+        steps.append(RigStep(cams, poses, lidar_pose))
     return Scene(room=room, spheres=spheres, boxes=boxes), steps

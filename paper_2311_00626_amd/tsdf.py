@@ -37,10 +37,31 @@ class tsdf_stats(C.Structure):
 class tsdf_depth_view(C.Structure):
     _fields_ = [("depth_dev", C.c_void_p), ("width", C.c_int), ("height", C.c_int),
                 ("model", C.c_int), ("max_range_m", C.c_float), ("K", C.c_float * 4),
-                ("reserved", C.c_float), ("reserved2", C.c_float), ("T_world_cam", C.c_float * 16)]
+                ("interp_max_diff_m", C.c_float), ("reserved", C.c_float), ("T_world_cam", C.c_float * 16)]
+
+
+class tsdf_lidar_model(C.Structure):
+    _fields_ = [("width", C.c_int), ("height", C.c_int), ("azimuth_start_rad", C.c_float),
+                ("azimuth_fov_rad", C.c_float), ("polar_start_rad", C.c_float), ("polar_fov_rad", C.c_float),
+                ("interp_max_diff_m", C.c_float), ("max_range_m", C.c_float)]
+
+
+MODEL_PINHOLE, MODEL_SPHERICAL = 0, 1
+
+
+def lidar_struct(lidar) -> tsdf_lidar_model:
+    """tsdf_lidar_model of an object with width, height and params() (see synth.LidarModel)."""
+    if isinstance(lidar, tsdf_lidar_model):
+        return lidar
+    p = [float(x) for x in np.asarray(lidar.params(), dtype=np.float32)]
+    return tsdf_lidar_model(int(lidar.width), int(lidar.height), *p)
 
 
 MAX_VIEWS = 16
+
+
+class tsdf_launch_config(C.Structure):
+    _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("reserved", C.c_int)]
 
 
 class tsdf_params(C.Structure):
@@ -61,21 +82,24 @@ def _load() -> C.CDLL:
     lib.create_map.argtypes = [C.c_float, C.c_float, C.POINTER(vp)]
     lib.create_map_ex.argtypes = [C.POINTER(tsdf_params), C.POINTER(vp)]
     lib.destroy_map.argtypes = [vp]
-    lib.integrate_depth.argtypes = [vp, vp, i, i, fp, fp, vp]
+    lib.integrate_depth.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
     lib.query_touched.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.map_stats.argtypes = [vp, C.POINTER(tsdf_stats), vp]
     lib.integrate_depth_views.argtypes = [vp, C.POINTER(tsdf_depth_view), i, vp]
+    lib.integrate_range.argtypes = [vp, vp, C.POINTER(tsdf_lidar_model), vp, vp]
     lib.map_status.argtypes = [vp]
     lib.tsdf_strerror.argtypes = [i]
     lib.tsdf_strerror.restype = C.c_char_p
     lib.tsdf_profile.argtypes = [vp, i]
+    lib.tsdf_set_launch_config.argtypes = [vp, C.POINTER(tsdf_launch_config)]
     lib.tsdf_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ll)]
     for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "integrate_depth_views",
+                 "integrate_range",
                  "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
-                 "tsdf_profile_read"):
+                 "tsdf_profile_read", "tsdf_set_launch_config"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -83,9 +107,9 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "integrate_depth",
-            "integrate_depth_views",
+            "integrate_depth_views", "integrate_range",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
-            "tsdf_strerror", "tsdf_profile", "tsdf_profile_read")
+            "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config")
 
 
 def strerror(status: int) -> str:
@@ -103,8 +127,9 @@ def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
 
 
 def _host_f32(a, n: int) -> np.ndarray:
-    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(n))
-    return arr
+    if type(a) is np.ndarray and a.dtype == np.float32 and a.size == n and a.flags.c_contiguous:
+        return a.reshape(n)
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(n))
 
 
 def default_params(voxel_size: float, truncation_vox: float) -> tsdf_params:
@@ -161,15 +186,27 @@ class TsdfMap:
         Kh = _host_f32(K, 4)
         Th = _host_f32(T_world_cam, 16)
         H, W = depth.shape
-        st = lib.integrate_depth(self._h, C.c_void_p(depth.data_ptr()), int(W), int(H),
-                                 Kh.ctypes.data_as(C.POINTER(C.c_float)),
-                                 Th.ctypes.data_as(C.POINTER(C.c_float)), C.c_void_p(_stream_ptr(stream)))
+        st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
+                                 _stream_ptr(stream))
         _check(st, "integrate_depth")
+
+    def integrate_range(self, rng: torch.Tensor, lidar, T_world_sensor,
+                        stream: Optional[torch.cuda.Stream] = None) -> None:
+        """One LiDAR range image; lidar is a LidarModel (or tsdf_lidar_model)."""
+        if not (rng.is_cuda and rng.dtype == torch.float32 and rng.dim() == 2 and rng.is_contiguous()):
+            raise ValueError("range must be a contiguous 2-D float32 CUDA tensor")
+        lm = lidar_struct(lidar)
+        if (lm.height, lm.width) != tuple(rng.shape):
+            raise ValueError("range image shape does not match the LiDAR model")
+        Th = _host_f32(T_world_sensor, 16)
+        _check(lib.integrate_range(self._h, rng.data_ptr(), C.byref(lm), Th.ctypes.data, _stream_ptr(stream)),
+               "integrate_range")
 
     def integrate_depth_views(self, depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None,
                               stream: Optional[torch.cuda.Stream] = None) -> None:
         """Fuses up to MAX_VIEWS views in one launch; bit-identical to calling
-        integrate_depth on each in order (per-view max range, 0 = map default)."""
+        integrate_depth / integrate_range on each in order (per-view max range,
+        0 = map default).  A view whose K is a LidarModel is a range image."""
         n = len(depths)
         max_ranges = [0.0] * n if max_ranges is None else list(max_ranges)
         if not 1 <= n <= MAX_VIEWS or len(Ks) != n or len(Ts) != n:
@@ -180,8 +217,15 @@ class TsdfMap:
                 raise ValueError("each depth must be a contiguous 2-D float32 CUDA tensor")
             arr[k].depth_dev = d.data_ptr()
             arr[k].height, arr[k].width = int(d.shape[0]), int(d.shape[1])
-            arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
-            arr[k].max_range_m = float(max_ranges[k])
+            if hasattr(K, "params"):
+                lm = lidar_struct(K)
+                arr[k].model = MODEL_SPHERICAL
+                arr[k].K[:] = [lm.azimuth_start_rad, lm.azimuth_fov_rad, lm.polar_start_rad, lm.polar_fov_rad]
+                arr[k].interp_max_diff_m = lm.interp_max_diff_m
+                arr[k].max_range_m = float(max_ranges[k]) or lm.max_range_m
+            else:
+                arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
+                arr[k].max_range_m = float(max_ranges[k])
             arr[k].T_world_cam[:] = [float(x) for x in _host_f32(T, 16)]
         _check(lib.integrate_depth_views(self._h, arr, n, C.c_void_p(_stream_ptr(stream))),
                "integrate_depth_views")
@@ -242,6 +286,11 @@ class TsdfMap:
         d, w = self.query_tsdf(b)
         torch.cuda.synchronize()
         return b.cpu().numpy(), d.cpu().numpy(), w.cpu().numpy()
+
+    def set_launch_config(self, max_groups: int = 0, partitions: int = 0, chunk: int = 0) -> None:
+        """Launch shape of the integration kernels (0 = automatic)."""
+        c = tsdf_launch_config(max_groups, partitions, chunk, 0)
+        _check(lib.tsdf_set_launch_config(self._h, C.byref(c)), "tsdf_set_launch_config")
 
     # -- kernel timing -------------------------------------------------------
     def profile(self, enable: bool) -> None:

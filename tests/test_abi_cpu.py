@@ -36,6 +36,7 @@ def test_every_declared_symbol_is_exported(t):
 
 def test_struct_layouts(t):
     assert C.sizeof(t.tsdf_depth_view) == 112
+    assert C.sizeof(t.tsdf_lidar_model) == 32
     assert C.sizeof(t.tsdf_stats) == 40
 
 

@@ -1,6 +1,6 @@
 """The pins must catch plausible mistakes in the oracle.  Each case plants one
 mistake in a temporary copy of the oracle sources (on the CPU), builds it, and
-runs the pin suite against it; the suite has to fail."""
+runs the pin suites (pinhole and LiDAR) against it; the suite has to fail."""
 import os
 import shutil
 import subprocess
@@ -40,6 +40,20 @@ MUTANTS = [
      "double zfar = zmax - (double)f->eps;"),
     ("binary16_rounds_toward_zero", "tsdf_oracle.c", "float r = nearbyintf(ax / q) * q;",
      "float r = truncf(ax / q) * q;"),
+    # spherical (LiDAR) path
+    ("atan_coefficient_wrong", "tsdf_oracle.c", "p = p * t2 + 0.1999355085f;", "p = p * t2 + 0.1899355085f;"),
+    ("atan2_arguments_swapped", "oracle_impl.h", "REAL theta = ATAN2(yc, xc);", "REAL theta = ATAN2(xc, yc);"),
+    ("polar_angle_from_minus_z", "oracle_impl.h", "REAL phi = ATAN2(SQRT(xc * xc + yc * yc), zc);",
+     "REAL phi = ATAN2(SQRT(xc * xc + yc * yc), -zc);"),
+    ("no_azimuth_wrap", "oracle_impl.h", "f->full_circle = (REAL)model[1] >= (REAL)6.28318548f;",
+     "f->full_circle = 0;"),
+    ("interpolation_weights_swapped", "oracle_impl.h",
+     "REAL d = (one - fv) * ((one - fu) * r00 + fu * r10) + fv * ((one - fu) * r01 + fu * r11);",
+     "REAL d = (one - fu) * ((one - fv) * r00 + fv * r10) + fu * ((one - fv) * r01 + fv * r11);"),
+    ("no_interpolation_guard", "oracle_impl.h", "if (!(mx - mn <= f->interp_diff))", "if (0)"),
+    ("lidar_depth_is_z", "oracle_impl.h", "REAL dp = d - rv;", "REAL dp = d - zc;"),
+    ("beam_at_pixel_edge", "oracle_impl.h",
+     "REAL uc = (theta - f->az_start) * f->alpha - half;", "REAL uc = (theta - f->az_start) * f->alpha;"),
 ]
 
 
@@ -57,6 +71,7 @@ def test_pins_catch_planted_mistake(name, fname, orig, mutant):
                         "-o", lib, os.path.join(tmp, "tsdf_oracle.c"), "-lm"], check=True, cwd=tmp)
         env = dict(os.environ, TSDF_ORACLE_LIB=lib)
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_lidar.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"pins did not catch the planted mistake '{name}'"
