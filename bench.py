@@ -82,6 +82,141 @@ def cpu_baseline(w, frames_host, budget_s: float):
                       f"{dt:.1f} s, {n / dt:.1f} frames/s"}
 
 
+def counters(m):
+    st = m.full_stats()
+    return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
+
+
+def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int) -> dict:
+    """One integrate_depth launch per frame over `steps` frames (cycling the
+    sequence) after `warmup` untimed ones; HIP events around each launch."""
+    import torch
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    n_frames = frames.shape[0]
+    H, W = frames.shape[1], frames.shape[2]
+    K = w.camera.K
+    m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity)
+    for k in range(warmup):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    torch.cuda.synchronize()
+    b0, u0, _, t0_ = counters(m)
+    m.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    kernel_ms, launches = m.profile_read()
+    m.profile(False)
+    b1, u1, _, t1_ = counters(m)
+    assert m.status() == 0, "map overflowed"
+    alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, steps, 4 if storage == "fp16" else 8) / steps
+    kern = kernel_ms / 1e3 / max(launches, 1)
+    return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
+            "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9}
+
+
+def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
+    """The 640x480 box-room sequence at a fine voxel size, binary32 and
+    binary16 storage: the configuration whose per-frame voxel traffic is
+    large enough for the HBM roofline to bind."""
+    import torch
+    from paper_2311_00626_amd import synth
+    w = synth.box_room_sequence(voxel_size, n_frames=300)
+    frames = torch.stack([torch.as_tensor(f) for f in w.frames(device="cuda")]).cuda().contiguous()
+    poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
+    out = {"workload": w.name, "voxel_size_m": voxel_size}
+    for storage in ("fp32", "fp16"):
+        r = timed_plain(w, frames, poses, storage, min(steps, 290), warmup, 1 << 17)
+        out[storage] = {"value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
+                        "frames_per_s": min(steps, 290) / r["elapsed"],
+                        "updates_per_frame": r["updates"] / min(steps, 290),
+                        "touched_blocks_per_frame": r["touched"] / min(steps, 290),
+                        "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
+                                     "kernel": f"integrate_depth_kernel<{storage}>",
+                                     "kernel_ms_mean": r["kernel_s"] * 1e3,
+                                     "algorithmic_bytes_per_launch": r["alg_per_launch"]}}
+    del frames
+    torch.cuda.empty_cache()
+    return out
+
+
+def rig_leg(n_steps: int, warmup: int):
+    """Multi-sensor steps: 4 pinhole cameras (640x480, 848x480, 424x240,
+    1280x720) and a 1024x64 spherical LiDAR (+-16 deg, 25 m, 2 cm range noise)
+    on a rig moving through a 20 x 15 x 3 m room at 10 Hz, 5 cm voxels.  Each
+    step is one replay of a captured hipGraph (argument upload + one batched
+    integration launch); the launch shape is autotuned on the first steps
+    before timing."""
+    import torch
+    from paper_2311_00626_amd import autotune, synth
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    t0 = time.perf_counter()
+    scene, steps = synth.rig_sequence(n_steps)
+    L = synth.LidarModel(width=1024, height=64, max_range=25.0, interp_max_diff=0.2)
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff", max_range=5.0)
+    rng = np.random.default_rng(11)
+    data, pixels = [], 0
+    for st in steps:
+        views = [torch.as_tensor(synth.add_depth_noise(synth.render_depth(scene, c, T, device="cuda"), rng),
+                                 device="cuda") for c, T in zip(st.cameras, st.poses)]
+        views.append(torch.as_tensor(synth.add_range_noise(synth.render_range(scene, L, st.lidar_pose,
+                                                                              device="cuda"), rng), device="cuda"))
+        pixels += sum(v.numel() for v in views)
+        data.append((views, [c.K for c in st.cameras] + [L], list(st.poses) + [st.lidar_pose]))
+    log(f"rig: rendered {n_steps} steps in {time.perf_counter() - t0:.1f} s")
+
+    def make_map():
+        return TsdfMap.from_params(params, block_capacity=1 << 16)
+
+    def make_runner(m):
+        s = m.step(with_spherical=True)
+        return (lambda k: s.run(*data[k])), s.close
+
+    t0 = time.perf_counter()
+    tune_steps = range(min(12, n_steps))
+    choice, trials = autotune.tune("rig-4cam-lidar-5cm", make_map, None, tune_steps, make_runner=make_runner,
+                                   rounds=2, refresh=True)
+    log(f"rig: tuned {len(trials)} launch shapes in {time.perf_counter() - t0:.1f} s -> {choice}")
+    m = make_map()
+    choice.apply(m)
+    step = m.step(with_spherical=True)
+    for k in range(min(warmup, n_steps)):
+        step.run(*data[k])
+    torch.cuda.synchronize()
+    st0 = m.full_stats()
+    m.profile(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    timed = range(min(warmup, n_steps), n_steps)
+    for k in timed:
+        step.run(*data[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t_start
+    kms, kl = m.profile_read()
+    m.profile(False)
+    st1 = m.full_stats()
+    step.close()
+    assert m.status() == 0, "map overflowed"
+    n = len(timed)
+    px = sum(sum(v.numel() for v in data[k][0]) for k in timed)
+    alg = algorithmic_bytes(st1["voxel_writes"] - st0["voxel_writes"], st1["touched_blocks"] - st0["touched_blocks"],
+                            st1["blocks"] - st0["blocks"], px, 1) / max(kl, 1)
+    ks = kms / 1e3 / max(kl, 1)
+    return {"steps": n, "views_per_step": 5, "pixels_per_step": pixels // n_steps,
+            "value": (st1["voxel_updates"] - st0["voxel_updates"]) / el, "unit": "voxel updates/s",
+            "steps_per_s": n / el, "ms_per_step": el / n * 1e3,
+            "launch_config": {"max_groups": choice.max_groups, "partitions": choice.partitions, "chunk": choice.chunk},
+            "tuning": [{"config": [t.config.max_groups, t.config.partitions, t.config.chunk],
+                        "kernel_ms": round(t.kernel_ms_per_launch, 4)} for t in trials[:5]],
+            "blocks": st1["blocks"],
+            "roofline": {"bound": "hbm", "achieved": alg / ks / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / ks / 1e9 / HBM_PEAK_GBS, "kernel": "integrate_views_kernel_dev (graph)",
+                         "kernel_ms_mean": ks * 1e3, "algorithmic_bytes_per_launch": alg}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +227,10 @@ def main():
     ap.add_argument("--batch", type=int, default=16, help="views per launch of the batched leg (1 = skip it)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (PMC scaling)")
+    ap.add_argument("--rig-steps", type=int, default=500,
+                    help="steps of the multi-sensor rig leg (4 cameras + LiDAR, graph-replayed; 0 = skip it)")
+    ap.add_argument("--legs", default="plain,fp16,batched,rig,precision",
+                    help="comma-separated legs to run (plain is always run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -113,33 +252,8 @@ def main():
     K = w.camera.K
     poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
 
-    def counters(m):
-        st = m.full_stats()
-        return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
-
     def plain_leg(storage: str):
-        """One integrate_depth launch per frame; HIP events around each launch."""
-        m = TsdfMap.from_params(w.params, storage=storage, block_capacity=1 << 16)
-        for k in range(args.warmup):
-            m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
-        torch.cuda.synchronize()
-        b0, u0, _, t0_ = counters(m)
-        m.profile(True)
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for k in range(args.warmup, args.warmup + args.steps):
-            m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
-        torch.cuda.synchronize()
-        t_end = time.perf_counter()
-        kernel_ms, launches = m.profile_read()
-        m.profile(False)
-        b1, u1, _, t1_ = counters(m)
-        assert m.status() == 0, "map overflowed"
-        alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, args.steps,
-                                4 if storage == "fp16" else 8) / args.steps
-        kern = kernel_ms / 1e3 / max(launches, 1)
-        return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
-                "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9}
+        return timed_plain(w, frames, poses, storage, args.steps, args.warmup, 1 << 16)
 
     # ---- plain path, binary32 storage: the headline value ------------------
     p32 = plain_leg("fp32")
@@ -148,9 +262,13 @@ def main():
     alg_per_launch, mean_kernel_s, achieved = p32["alg_per_launch"], p32["kernel_s"], p32["achieved"]
     launches = p32["launches"]
 
+    legs = set(args.legs.split(","))
+
     # ---- plain path, binary16 storage ---------------------------------------
-    p16 = plain_leg("fp16")
-    fp16 = {"storage": "binary16 distance + binary16 weight, binary32 update arithmetic",
+    fp16 = None
+    p16 = plain_leg("fp16") if "fp16" in legs else None
+    if p16 is not None:
+      fp16 = {"storage": "binary16 distance + binary16 weight, binary32 update arithmetic",
             "value": p16["updates"] / p16["elapsed"], "unit": "voxel updates/s",
             "frames_per_s": args.steps / p16["elapsed"], "ms_per_step": p16["elapsed"] / args.steps * 1e3,
             "roofline": {"bound": "hbm", "achieved": p16["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -160,7 +278,7 @@ def main():
 
     # ---- batched path: integrate_depth_views, several frames per launch ------
     batched = None
-    if args.batch > 1:
+    if args.batch > 1 and "batched" in legs:
         B = args.batch
         mb = TsdfMap.from_params(w.params, block_capacity=1 << 16)
         first = n_frames % B or B           # warm-up batch, so that the rest splits evenly
@@ -191,6 +309,10 @@ def main():
                                 "kernel": "integrate_views_kernel", "kernel_ms_mean": kb * 1e3,
                                 "algorithmic_bytes_per_launch": alg_b}}
         del mb
+
+    rig = rig_leg(args.rig_steps, args.warmup) if args.rig_steps > 0 and "rig" in legs else None
+    precision = ([precision_leg(vs, args.steps, args.warmup) for vs in (0.01, 0.02)]
+                 if "precision" in legs else None)
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
@@ -225,7 +347,12 @@ def main():
                      "kernel": "integrate_depth_kernel", "kernel_ms_mean": mean_kernel_s * 1e3,
                      "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches},
     }
-    result["fp16"] = fp16
+    if fp16 is not None:
+        result["fp16"] = fp16
+    if rig is not None:
+        result["rig"] = rig
+    if precision is not None:
+        result["precision"] = precision
     if batched is not None:
         result["batched"] = batched
     if not args.skip_cpu_baseline:

@@ -166,6 +166,21 @@ typedef struct {
  * the views.  Only enqueues work; errors as integrate_depth. */
 TSDF_API int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream);
 
+/* A batched step replayed from a hipGraph.  tsdf_step_create captures, once,
+ * [a copy of the step's launch arguments from pinned host memory to device
+ * memory] + [the integrate_depth_views kernel reading them] into two
+ * instantiated graphs used alternately.  tsdf_step_run validates the views,
+ * writes the arguments and launches one graph on hip_stream: the same result
+ * as integrate_depth_views, with one graph launch as the only per-step
+ * submission.  with_spherical must be nonzero for steps holding range images.
+ * A step belongs to its map and must be destroyed before it; runs on one map
+ * must be ordered on one stream.  tsdf_step_run may wait for the replay before
+ * last to finish (it reuses that one's staging slot). */
+typedef struct tsdf_step tsdf_step;
+TSDF_API int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out);
+TSDF_API int tsdf_step_run(tsdf_step *step, const tsdf_depth_view *views, int n_views, void *hip_stream);
+TSDF_API int tsdf_step_destroy(tsdf_step *step);
+
 /* Writes the indices of all allocated blocks, sorted ascending by (x, y, z),
  * as int32 triples to out_xyz_dev (room for `capacity` blocks; min(count,
  * capacity) are written) and the total count to *out_count (host).

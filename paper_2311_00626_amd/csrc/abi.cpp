@@ -535,9 +535,14 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
     return TSDF_OK;
 }
 
-int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream)
+} // extern "C"
+
+namespace {
+
+// Validates a batch of views and fills the launch arguments (not the parity).
+int build_views_args(tsdf_map *m, const tsdf_depth_view *views, int n_views, ViewsArgs &va, bool &spherical)
 {
-    if (!m || !views || n_views < 1 || n_views > TSDF_MAX_VIEWS)
+    if (!views || n_views < 1 || n_views > TSDF_MAX_VIEWS)
         return TSDF_EINVAL;
     for (int v = 0; v < n_views; ++v) {
         const tsdf_depth_view &w = views[v];
@@ -554,10 +559,8 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
             return TSDF_EINVAL;
         }
     }
-    if (m->sticky)
-        return TSDF_ESTATE;
-    ViewsArgs va;
     std::memset(&va, 0, sizeof(va));
+    spherical = false;
     double lo[3], hi[3], max_zfar = 0;
     for (int v = 0; v < n_views; ++v) {
         double vlo[3], vhi[3];
@@ -568,19 +571,72 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
                                             vlo, vhi)
                            : camera_view(m, views[v].depth_dev, views[v].width, views[v].height, views[v].K,
                                          views[v].T_world_cam, range, va.cam[v], vlo, vhi);
-        max_zfar = std::max(max_zfar, (double)va.cam[v].zfar);
         if (st != TSDF_OK)
             return st;
+        spherical = spherical || views[v].model == TSDF_MODEL_SPHERICAL;
+        max_zfar = std::max(max_zfar, (double)va.cam[v].zfar);
         for (int a = 0; a < 3; ++a) {
             lo[a] = v == 0 ? vlo[a] : std::min(lo[a], vlo[a]);
             hi[a] = v == 0 ? vhi[a] : std::max(hi[a], vhi[a]);
         }
     }
-    int st = lattice_of(m, lo, hi, va.lat);
+    const int st = lattice_of(m, lo, hi, va.lat);
     if (st != TSDF_OK)
         return st;
     va.n_views = n_views;
     map_consts(m, box_extent(lo, hi), max_zfar, va.mc);
+    return TSDF_OK;
+}
+
+}  // namespace
+
+// A replayable batched step: two instantiated hipGraphs, each [copy of the
+// step's launch arguments from a pinned staging slot to device memory] +
+// [the batched integration kernel reading them], used alternately so that a
+// slot is rewritten only after its previous replay has finished.
+struct tsdf_step {
+    tsdf_map *m;
+    bool spherical;
+    int groups;
+    ViewsArgs *pinned[2];
+    ViewsArgs *dev[2];
+    hipGraph_t graph[2];
+    hipGraphExec_t exec[2];
+    hipEvent_t done[2];
+    bool pending[2];
+    int next;
+};
+
+static void step_free(tsdf_step *st)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (st->exec[k])
+            (void)hipGraphExecDestroy(st->exec[k]);
+        if (st->graph[k])
+            (void)hipGraphDestroy(st->graph[k]);
+        if (st->done[k])
+            (void)hipEventDestroy(st->done[k]);
+        if (st->pinned[k])
+            (void)hipHostFree(st->pinned[k]);
+        if (st->dev[k])
+            (void)hipFree(st->dev[k]);
+    }
+    delete st;
+}
+
+extern "C" {
+
+int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream)
+{
+    if (!m)
+        return TSDF_EINVAL;
+    ViewsArgs va;
+    bool spherical = false;
+    int st = build_views_args(m, views, n_views, va, spherical);
+    if (st != TSDF_OK)
+        return st;
+    if (m->sticky)
+        return TSDF_ESTATE;
     va.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
@@ -593,6 +649,106 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
         return hip_status(e);
     timing_end(m, s, timed);
     ++m->frames;
+    return TSDF_OK;
+}
+
+int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
+{
+    if (!m || !out)
+        return TSDF_EINVAL;
+    *out = nullptr;
+    tsdf_step *st = new (std::nothrow) tsdf_step();
+    if (!st)
+        return TSDF_ENOMEM;
+    st->m = m;
+    st->spherical = with_spherical != 0;
+    const tsdf_launch_config &lc = m->launch;
+    long long groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
+    st->groups = (int)std::max<long long>(kPartitions, groups / kPartitions * kPartitions);
+    hipError_t e = use_device(m);
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc((void **)&st->pinned[k], sizeof(ViewsArgs), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&st->dev[k], sizeof(ViewsArgs));
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&st->done[k], hipEventDisableTiming);
+        if (e == hipSuccess) {
+            std::memset(st->pinned[k], 0, sizeof(ViewsArgs));
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        }
+        if (e == hipSuccess) {
+            hipError_t e1 = hipMemcpyAsync(st->dev[k], st->pinned[k], sizeof(ViewsArgs), hipMemcpyHostToDevice, cs);
+            hipError_t e2 = e1 == hipSuccess ? launch_integrate_views_dev(m->dm, st->dev[k], st->spherical,
+                                                                          m->p.weighting, st->groups, cs)
+                                             : e1;
+            hipError_t e3 = hipStreamEndCapture(cs, &st->graph[k]);
+            e = e2 != hipSuccess ? e2 : e3;
+        }
+        if (e == hipSuccess)
+            e = hipGraphInstantiate(&st->exec[k], st->graph[k], nullptr, nullptr, 0);
+    }
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        step_free(st);
+        return hip_status(e);
+    }
+    *out = st;
+    return TSDF_OK;
+}
+
+int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void *hip_stream)
+{
+    if (!st)
+        return TSDF_EINVAL;
+    tsdf_map *m = st->m;
+    ViewsArgs va;
+    bool spherical = false;
+    int rc = build_views_args(m, views, n_views, va, spherical);
+    if (rc != TSDF_OK)
+        return rc;
+    if (spherical && !st->spherical)
+        return TSDF_EINVAL;
+    if (m->sticky)
+        return TSDF_ESTATE;
+    va.parity = (int)(m->frames & 1);
+    Lattice lat = va.lat;
+    (void)schedule(m, lat);      // chunk and partitions for this lattice; the grid is fixed
+    va.lat.chunk = lat.chunk;
+    va.lat.partitions = lat.partitions;
+    hipError_t e = use_device(m);
+    if (e != hipSuccess)
+        return hip_status(e);
+    const int k = st->next;
+    if (st->pending[k] && (e = hipEventSynchronize(st->done[k])) != hipSuccess)
+        return hip_status(e);
+    *st->pinned[k] = va;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const bool timed = timing_begin(m, s);
+    e = hipGraphLaunch(st->exec[k], s);
+    if (e == hipSuccess)
+        e = hipEventRecord(st->done[k], s);
+    if (e != hipSuccess)
+        return hip_status(e);
+    timing_end(m, s, timed);
+    st->pending[k] = true;
+    st->next = k ^ 1;
+    ++m->frames;
+    return TSDF_OK;
+}
+
+int tsdf_step_destroy(tsdf_step *st)
+{
+    if (!st)
+        return TSDF_OK;
+    (void)use_device(st->m);
+    for (int k = 0; k < 2; ++k)
+        if (st->pending[k])
+            (void)hipEventSynchronize(st->done[k]);
+    step_free(st);
     return TSDF_OK;
 }
 

@@ -29,7 +29,7 @@ namespace {
 using namespace dev;
 
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
-__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
+__device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const ViewsArgs &va)
 {
     const int lane = lane_id();
     const int lx = lane & 7;
@@ -117,6 +117,22 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes);
 }
 
+// Arguments passed by value (eager launches).
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
+{
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, va);
+}
+
+// Arguments read from device memory (graph replays: the host rewrites them
+// between replays through a captured copy).
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel_dev(DeviceMap dm,
+                                                                                  const ViewsArgs *__restrict__ va)
+{
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, *va);
+}
+
 }  // namespace
 
 template <int SPHERICAL>
@@ -144,6 +160,31 @@ hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int 
         launch_views_model<1>(dm, va, weighting, grid, block, stream);
     else
         launch_views_model<0>(dm, va, weighting, grid, block, stream);
+    return hipGetLastError();
+}
+
+template <int SPHERICAL>
+static void launch_views_dev_model(const DeviceMap &dm, const ViewsArgs *va, int weighting, dim3 grid, dim3 block,
+                                   hipStream_t stream)
+{
+    if (weighting == 1 && dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<1, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else if (weighting == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<1, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<0, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<0, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+}
+
+hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,
+                                      int groups, hipStream_t stream)
+{
+    const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
+    if (spherical)
+        launch_views_dev_model<1>(dm, va_dev, weighting, grid, block, stream);
+    else
+        launch_views_dev_model<0>(dm, va_dev, weighting, grid, block, stream);
     return hipGetLastError();
 }
 

@@ -155,6 +155,8 @@ hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int 
                                   hipStream_t stream);
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
                                   hipStream_t stream);
+hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,
+                                      int groups, hipStream_t stream);
 hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,

@@ -95,11 +95,15 @@ def _load() -> C.CDLL:
     lib.tsdf_profile.argtypes = [vp, i]
     lib.tsdf_set_launch_config.argtypes = [vp, C.POINTER(tsdf_launch_config)]
     lib.tsdf_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(ll)]
+    lib.tsdf_step_create.argtypes = [vp, i, C.POINTER(vp)]
+    lib.tsdf_step_run.argtypes = [vp, C.POINTER(tsdf_depth_view), i, vp]
+    lib.tsdf_step_destroy.argtypes = [vp]
     for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "integrate_depth_views",
                  "integrate_range",
                  "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
-                 "tsdf_profile_read", "tsdf_set_launch_config"):
+                 "tsdf_profile_read", "tsdf_set_launch_config", "tsdf_step_create", "tsdf_step_run",
+                 "tsdf_step_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -109,7 +113,8 @@ lib = _load()
 EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "integrate_depth",
             "integrate_depth_views", "integrate_range",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
-            "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config")
+            "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config",
+            "tsdf_step_create", "tsdf_step_run", "tsdf_step_destroy")
 
 
 def strerror(status: int) -> str:
@@ -136,6 +141,31 @@ def default_params(voxel_size: float, truncation_vox: float) -> tsdf_params:
     p = tsdf_params()
     lib.tsdf_default_params(C.byref(p), voxel_size, truncation_vox)
     return p
+
+
+def views_array(depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None):
+    """(tsdf_depth_view array, n) of a batch of depth / range images."""
+    n = len(depths)
+    max_ranges = [0.0] * n if max_ranges is None else list(max_ranges)
+    if not 1 <= n <= MAX_VIEWS or len(Ks) != n or len(Ts) != n:
+        raise ValueError(f"need 1..{MAX_VIEWS} views with matching K and T")
+    arr = (tsdf_depth_view * n)()
+    for k, (d, K, T) in enumerate(zip(depths, Ks, Ts)):
+        if not (d.is_cuda and d.dtype == torch.float32 and d.dim() == 2 and d.is_contiguous()):
+            raise ValueError("each depth must be a contiguous 2-D float32 CUDA tensor")
+        arr[k].depth_dev = d.data_ptr()
+        arr[k].height, arr[k].width = int(d.shape[0]), int(d.shape[1])
+        if hasattr(K, "params"):
+            lm = lidar_struct(K)
+            arr[k].model = MODEL_SPHERICAL
+            arr[k].K[:] = [lm.azimuth_start_rad, lm.azimuth_fov_rad, lm.polar_start_rad, lm.polar_fov_rad]
+            arr[k].interp_max_diff_m = lm.interp_max_diff_m
+            arr[k].max_range_m = float(max_ranges[k]) or lm.max_range_m
+        else:
+            arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
+            arr[k].max_range_m = float(max_ranges[k])
+        arr[k].T_world_cam[:] = [float(x) for x in _host_f32(T, 16)]
+    return arr, n
 
 
 class TsdfMap:
@@ -207,28 +237,13 @@ class TsdfMap:
         """Fuses up to MAX_VIEWS views in one launch; bit-identical to calling
         integrate_depth / integrate_range on each in order (per-view max range,
         0 = map default).  A view whose K is a LidarModel is a range image."""
-        n = len(depths)
-        max_ranges = [0.0] * n if max_ranges is None else list(max_ranges)
-        if not 1 <= n <= MAX_VIEWS or len(Ks) != n or len(Ts) != n:
-            raise ValueError(f"need 1..{MAX_VIEWS} views with matching K and T")
-        arr = (tsdf_depth_view * n)()
-        for k, (d, K, T) in enumerate(zip(depths, Ks, Ts)):
-            if not (d.is_cuda and d.dtype == torch.float32 and d.dim() == 2 and d.is_contiguous()):
-                raise ValueError("each depth must be a contiguous 2-D float32 CUDA tensor")
-            arr[k].depth_dev = d.data_ptr()
-            arr[k].height, arr[k].width = int(d.shape[0]), int(d.shape[1])
-            if hasattr(K, "params"):
-                lm = lidar_struct(K)
-                arr[k].model = MODEL_SPHERICAL
-                arr[k].K[:] = [lm.azimuth_start_rad, lm.azimuth_fov_rad, lm.polar_start_rad, lm.polar_fov_rad]
-                arr[k].interp_max_diff_m = lm.interp_max_diff_m
-                arr[k].max_range_m = float(max_ranges[k]) or lm.max_range_m
-            else:
-                arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
-                arr[k].max_range_m = float(max_ranges[k])
-            arr[k].T_world_cam[:] = [float(x) for x in _host_f32(T, 16)]
+        arr, n = views_array(depths, Ks, Ts, max_ranges)
         _check(lib.integrate_depth_views(self._h, arr, n, C.c_void_p(_stream_ptr(stream))),
                "integrate_depth_views")
+
+    def step(self, with_spherical: bool = False) -> "TsdfStep":
+        """A graph-replayed batched step on this map (see TsdfStep)."""
+        return TsdfStep(self, with_spherical)
 
     # -- queries --------------------------------------------------------------
     def query_blocks(self, stream=None) -> torch.Tensor:
@@ -300,3 +315,31 @@ class TsdfMap:
         ms, n = C.c_double(), C.c_longlong()
         _check(lib.tsdf_profile_read(self._h, C.byref(ms), C.byref(n)), "tsdf_profile_read")
         return ms.value, n.value
+
+
+class TsdfStep:
+    """A batched step replayed from a captured hipGraph (tsdf_step_* in the C
+    ABI): run() has the effect of TsdfMap.integrate_depth_views, with one
+    graph launch per step.  Close it (or let it go) before its map."""
+
+    def __init__(self, m: TsdfMap, with_spherical: bool = False):
+        h = C.c_void_p()
+        _check(lib.tsdf_step_create(m.handle, 1 if with_spherical else 0, C.byref(h)), "tsdf_step_create")
+        self._h = h
+        self.map = m
+
+    def run(self, depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None,
+            stream: Optional[torch.cuda.Stream] = None) -> None:
+        arr, n = views_array(depths, Ks, Ts, max_ranges)
+        _check(lib.tsdf_step_run(self._h, arr, n, C.c_void_p(_stream_ptr(stream))), "tsdf_step_run")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib.tsdf_step_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

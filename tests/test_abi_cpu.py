@@ -86,3 +86,7 @@ def test_null_map_rejected(t):
     assert t.lib.integrate_depth_views(None, views, 1, None) == t.EINVAL
     assert t.lib.map_status(None) == t.EINVAL
     assert t.lib.destroy_map(None) == t.OK
+    step = C.c_void_p()
+    assert t.lib.tsdf_step_create(None, 0, C.byref(step)) == t.EINVAL and not step.value
+    assert t.lib.tsdf_step_run(None, views, 1, None) == t.EINVAL
+    assert t.lib.tsdf_step_destroy(None) == t.OK

@@ -6,6 +6,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -32,8 +33,9 @@ MUTANTS = [
      "if (dp < -f->eps)\n        dp = -f->eps;"),
     ("weight_not_capped", "oracle_impl.h", "*W = s < w_max ? s : w_max;", "*W = s;"),
     ("average_drops_old_weight", "oracle_impl.h", "REAL n = *D * *W + x * wm;", "REAL n = *D + x * wm;"),
-    ("voxel_centre_missing_half", "oracle_impl.h", "REAL px = ((REAL)gx + half) * f->vs;",
-     "REAL px = ((REAL)gx) * f->vs;"),
+    ("voxel_centre_missing_half", "oracle_impl.h",
+     "/* voxel centre p_L */\n    REAL px = ((REAL)gx + half) * f->vs;",
+     "/* voxel centre p_L */\n    REAL px = ((REAL)gx) * f->vs;"),
     ("dropoff_sign", "oracle_impl.h", "w = (f->eps + dp) * f->span_inv;", "w = (f->eps - dp) * f->span_inv;"),
     ("max_range_exclusive", "oracle_impl.h", "if (!(d > 0 && d <= f->d_max))", "if (!(d > 0 && d < f->d_max))"),
     ("scan_box_misses_truncation_band", "oracle_impl.h", "double zfar = zmax + (double)f->eps;",
@@ -52,26 +54,46 @@ MUTANTS = [
      "REAL d = (one - fu) * ((one - fv) * r00 + fv * r10) + fu * ((one - fv) * r01 + fv * r11);"),
     ("no_interpolation_guard", "oracle_impl.h", "if (!(mx - mn <= f->interp_diff))", "if (0)"),
     ("lidar_depth_is_z", "oracle_impl.h", "REAL dp = d - rv;", "REAL dp = d - zc;"),
+    ("lidar_voxel_centre_missing_half", "oracle_impl.h",
+     "one = (REAL)1;\n    REAL px = ((REAL)gx + half) * f->vs;", "one = (REAL)1;\n    REAL px = ((REAL)gx) * f->vs;"),
     ("beam_at_pixel_edge", "oracle_impl.h",
      "REAL uc = (theta - f->az_start) * f->alpha - half;", "REAL uc = (theta - f->az_start) * f->alpha;"),
 ]
 
 
-@pytest.mark.parametrize("name,fname,orig,mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_planted_mistake(name, fname, orig, mutant):
+def run_mutant(fname, orig, mutant):
+    """Builds the oracle with one planted mistake and runs the pin suites
+    against it; returns (anchor count, pytest return code)."""
     with tempfile.TemporaryDirectory() as tmp:
         for f in ("tsdf_oracle.c", "tsdf_oracle.h", "oracle_impl.h"):
             shutil.copy(os.path.join(ORACLE, f), tmp)
         path = os.path.join(tmp, fname)
         text = open(path).read()
-        assert text.count(orig) == 1, f"mutation anchor not found once: {orig}"
+        if text.count(orig) != 1:
+            return text.count(orig), None
         open(path, "w").write(text.replace(orig, mutant))
         lib = os.path.join(tmp, "libmutant.so")
         subprocess.run(["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
                         "-o", lib, os.path.join(tmp, "tsdf_oracle.c"), "-lm"], check=True, cwd=tmp)
-        env = dict(os.environ, TSDF_ORACLE_LIB=lib)
+        env = dict(os.environ, TSDF_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                             os.path.join(ROOT, "tests", "test_oracle_lidar.py")],
-                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-        assert r.returncode != 0, f"pins did not catch the planted mistake '{name}'"
+                           cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+        return 1, r.returncode
+
+
+@pytest.fixture(scope="module")
+def mutant_results():
+    """All mutants, run concurrently (each is its own process)."""
+    workers = max(1, min(8, (os.cpu_count() or 2) - 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {m[0]: ex.submit(run_mutant, m[1], m[2], m[3]) for m in MUTANTS}
+        return {k: f.result() for k, f in futs.items()}
+
+
+@pytest.mark.parametrize("name,fname,orig,mutant", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(mutant_results, name, fname, orig, mutant):
+    count, rc = mutant_results[name]
+    assert count == 1, f"mutation anchor not found once: {orig}"
+    assert rc != 0, f"pins did not catch the planted mistake '{name}'"
