@@ -61,6 +61,8 @@ extern "C" {
 
 #define TSDF_WEIGHT_CONSTANT 0        /* f_w(d_p) = 1 */
 #define TSDF_WEIGHT_LINEAR_DROPOFF 1  /* 1 for d_p >= -voxel_size, then linear to 0 at -epsilon */
+#define TSDF_WEIGHT_LEARNED 2         /* per-pixel weight and truncation from the learned sensor
+                                         model (tsdf_set_sensor_model); pinhole views only */
 
 #define TSDF_STORAGE_FP32 0   /* (distance, weight) as two binary32: 8 B per voxel, 4 KiB per block */
 #define TSDF_STORAGE_FP16 1   /* two binary16, rounded to nearest-even after each binary32 update:
@@ -227,10 +229,20 @@ TSDF_API const char *tsdf_strerror(int status);
  *               multiple of 8), 1 .. 65536;
  *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
  *               each XCD reads about 1/8 of every depth image;
- *   chunk       lattice blocks a wave culls per pass, 1 .. 64.
+ *   chunk       lattice blocks a wave culls per pass, 1 .. 64;
+ *   footprint   footprint culling: a pre-pass reduces every view to the
+ *               largest valid measurement per 8/16/32/64-pixel tile, and a
+ *               block is skipped when its nearest point lies beyond the
+ *               largest measurement under its image footprint plus epsilon
+ *               (no voxel of it can be updated).  TSDF_FOOTPRINT_AUTO uses it
+ *               for launches whose block lattice has at least 65536 blocks;
+ *               views larger than 4096 pixels a side are never culled this way.
  * NULL restores the automatic choice.  Errors: TSDF_EINVAL. */
+#define TSDF_FOOTPRINT_AUTO 0
+#define TSDF_FOOTPRINT_NEVER 1
+#define TSDF_FOOTPRINT_ALWAYS 2
 typedef struct {
-    int max_groups, partitions, chunk, reserved;
+    int max_groups, partitions, chunk, footprint;
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);
 
@@ -241,6 +253,71 @@ TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *confi
  * then clears them.  At most 65536 launches are kept. */
 TSDF_API int tsdf_profile(tsdf_map *m, int enable);
 TSDF_API int tsdf_profile_read(tsdf_map *m, double *total_ms, long long *launches);
+
+/* ---- Learned sensor model --------------------------------------------------
+ *
+ * §IV-B lets the measurement weight follow the sensor's error model.  The
+ * learned model is a per-pixel perceptron 27 -> 32 -> 32 -> 2 on the pixel's
+ * depth neighbourhood: inputs are the 5 x 5 patch of depth differences q - d
+ * (clipped to +-0.5 m, 0 outside the image or for invalid q), the depth d and
+ * the incidence angle between the pixel's ray and the normal of the
+ * back-projected depth (pi/2 without all four neighbours); outputs o give the
+ * weight w = (o0 + sqrt(o0^2 + 4)) / 2 and the truncation distance
+ * eps = voxel_size (1 + 7 s), s = (1 + o1 / sqrt(1 + o1^2)) / 2.  With weighting
+ * TSDF_WEIGHT_LEARNED a voxel with projective distance d_p is updated when
+ * d_p >= -eps and w > 0, with x = min(d_p, eps) and weight w, in place of the
+ * map's epsilon and weighting function.
+ *
+ * Parameters: TSDF_SM_NPARAM binary32 values that are bfloat16 numbers (low
+ * 16 bits zero), in the order W1[32][27], b1[32], W2[32][32], b2[32],
+ * W3[2][32], b3[2] (row-major, output index first).  Inference rounds inputs
+ * and hidden activations to bfloat16 and accumulates each dot product in
+ * binary32, one fused multiply-add per term in index order from the bias. */
+#define TSDF_SM_NPARAM 2018
+#define TSDF_SM_MAX_FRAMES 16
+
+/* Copies the parameters (host memory) to the map; needed before any
+ * integration of a TSDF_WEIGHT_LEARNED map, which otherwise fails with
+ * TSDF_EINVAL.  Waits for the device.  Errors: TSDF_EINVAL (NULL, a value that
+ * is not a finite bfloat16 number), TSDF_ENOMEM, TSDF_EDEVICE.  Learned maps
+ * reject range images and graph steps (TSDF_EINVAL). */
+TSDF_API int tsdf_set_sensor_model(tsdf_map *m, const float *params);
+
+/* The per-pixel (weight, truncation) pairs of one depth image: maps_dev
+ * receives 2 floats per pixel, row-major; (0, 0) for invalid pixels
+ * (outside 0 < d <= max_range).  params_dev: TSDF_SM_NPARAM floats in device
+ * memory.  Enqueued on hip_stream.  Errors: TSDF_EINVAL, TSDF_EDEVICE. */
+TSDF_API int tsdf_sensor_maps(const float *depth_dev, int width, int height, const float K[4], float max_range,
+                              float voxel_size, const float *params_dev, float *maps_dev, void *hip_stream);
+
+/* Training.  For a window of n_frames depth images (device pointers, all
+ * width x height, poses T_world_cam: n_frames x 16 floats in host memory) and
+ * n_vox target voxels (vox_dev: 3 int32 global voxel indices each, target_dev:
+ * one float target distance each, device memory), the loss is
+ *   L = (1/N) sum_v (D(v) - D*(v))^2,  D(v) = sum_f w_f x_f / sum_f w_f,
+ * over the N target voxels that some frame updates under the model, x_f and w_f
+ * as in integration with the pixel frame f projects v into (the fused distance
+ * before any weight cap).  tsdf_sm_loss_grad writes dL/dparams to grad_dev
+ * (TSDF_SM_NPARAM floats, overwritten) and, when loss_host is not NULL, waits
+ * for the stream and stores {L, N} there.  The band test d_p >= -eps carries no
+ * gradient; rounding to bfloat16 is differentiated as the identity.  A
+ * trainer holds the per-pixel work buffers of windows of up to max_frames
+ * (<= TSDF_SM_MAX_FRAMES) images of one size; calls on one trainer must be
+ * ordered on one stream. */
+typedef struct tsdf_sm_trainer tsdf_sm_trainer;
+TSDF_API int tsdf_sm_trainer_create(int width, int height, int max_frames, tsdf_sm_trainer **out);
+TSDF_API int tsdf_sm_trainer_destroy(tsdf_sm_trainer *t);
+TSDF_API int tsdf_sm_loss_grad(tsdf_sm_trainer *t, const float *params_dev, int n_frames,
+                               const float *const *depth_dev, const float K[4], const float *T_world_cam,
+                               float voxel_size, float max_range, long long n_vox, const int *vox_dev,
+                               const float *target_dev, float *grad_dev, double *loss_host, void *hip_stream);
+
+/* One Adam step on n parameters (device memory): moments m1, m2 and the
+ * binary32 master copy are updated in place, params_dev receives the master
+ * rounded to bfloat16 (the inference parameters).  step >= 1 is the step count
+ * used for the bias corrections. */
+TSDF_API int tsdf_sm_adam(float *master_dev, float *m1_dev, float *m2_dev, const float *grad_dev, float *params_dev,
+                          int n, float lr, float beta1, float beta2, float eps, int step, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -63,6 +63,17 @@ def _load():
     lib.ora_dense_integrate.restype = C.c_longlong
     lib.ora_dense_integrate.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                         f32p, C.c_int, C.c_int, f32p, f32p, i32p, i32p, f64p, f64p]
+    lib.ora_round_bf16.restype = C.c_float
+    lib.ora_round_bf16.argtypes = [C.c_float]
+    lib.ora_sm_features.restype = None
+    lib.ora_sm_features.argtypes = [f32p, C.c_int, C.c_int, f32p, C.c_float, f32p]
+    lib.ora_sm_maps.restype = C.c_int
+    lib.ora_sm_maps.argtypes = [f32p, C.c_int, C.c_int, f32p, C.c_float, C.c_float, f32p, f32p, f32p]
+    lib.ora_integrate_learned.restype = C.c_longlong
+    lib.ora_integrate_learned.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p, f32p, f32p]
+    lib.ora_sm_loss_grad.restype = C.c_double
+    lib.ora_sm_loss_grad.argtypes = [f32p, C.c_int, f32p, C.c_int, C.c_int, f32p, f32p, C.c_float, C.c_float,
+                                     C.c_longlong, i32p, f64p, C.c_int, f64p, C.POINTER(C.c_longlong)]
     _lib = lib
     return lib
 
@@ -124,6 +135,16 @@ class OracleMap:
         n = _lib.ora_integrate_range(self._h, rng, W, H, _f32(lidar.params(), 6), _f32(T_world_sensor, 16))
         if n < 0:
             raise ValueError("oracle rejected the range image")
+        return int(n)
+
+    def integrate_learned(self, depth: np.ndarray, K, T_world_cam, w_map, eps_map) -> int:
+        """One pinhole frame with per-pixel weight and truncation maps."""
+        depth = _f32(depth)
+        H, W = depth.shape
+        n = _lib.ora_integrate_learned(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16),
+                                       _f32(w_map).reshape(H, W), _f32(eps_map).reshape(H, W))
+        if n < 0:
+            raise ValueError("oracle rejected the frame")
         return int(n)
 
     def num_blocks(self) -> int:
@@ -224,3 +245,52 @@ def dense_integrate(params, frames, K, poses, gmin, gdim, precision: int = 32):
             raise ValueError("oracle rejected the frame")
     shape = (int(gdim[2]), int(gdim[1]), int(gdim[0]))
     return dist.reshape(shape), weight.reshape(shape)
+
+
+SM_NPARAM = 2018
+
+
+def round_bf16(x: float) -> float:
+    return float(_load().ora_round_bf16(x))
+
+
+def sm_features(depth, K, max_range: float) -> np.ndarray:
+    """(H, W, 27) binary32 input features of the learned sensor model."""
+    lib = _load()
+    depth = _f32(depth)
+    H, W = depth.shape
+    out = np.empty((H, W, 27), np.float32)
+    lib.ora_sm_features(depth, W, H, _f32(K, 4), max_range, out)
+    return out
+
+
+def sm_maps(depth, K, max_range: float, voxel_size: float, params) -> Tuple[np.ndarray, np.ndarray]:
+    """Per-pixel (weight, truncation) maps of the bfloat16-emulating forward."""
+    lib = _load()
+    depth = _f32(depth)
+    H, W = depth.shape
+    w = np.empty((H, W), np.float32)
+    e = np.empty((H, W), np.float32)
+    if lib.ora_sm_maps(depth, W, H, _f32(K, 4), max_range, voxel_size, _f32(params, SM_NPARAM), w, e) != 0:
+        raise ValueError("oracle rejected the sensor-model inputs")
+    return w, e
+
+
+def sm_loss_grad(params, frames, K, poses, voxel_size: float, max_range: float, vox, target,
+                 emulate_bf16: bool = True):
+    """(loss, gradient (2018,), voxels used) of the learned sensor model's
+    training loss in binary64 (see sensor_model_impl.h)."""
+    lib = _load()
+    frames = np.ascontiguousarray(np.stack([_f32(f) for f in frames]))
+    n, H, W = frames.shape
+    T = np.ascontiguousarray(np.stack([_f32(t, 16) for t in poses]))
+    vox = np.ascontiguousarray(np.asarray(vox, np.int32).reshape(-1, 3))
+    target = np.ascontiguousarray(np.asarray(target, np.float64).reshape(-1))
+    grad = np.zeros(SM_NPARAM, np.float64)
+    used = C.c_longlong()
+    loss = lib.ora_sm_loss_grad(_f32(params, SM_NPARAM), n, frames.reshape(-1), W, H, _f32(K, 4), T.reshape(-1),
+                                voxel_size, max_range, len(vox), vox.reshape(-1), target, int(emulate_bf16),
+                                grad, C.byref(used))
+    if loss < 0:
+        raise MemoryError("oracle out of memory")
+    return float(loss), grad, int(used.value)

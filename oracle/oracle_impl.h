@@ -34,6 +34,8 @@ typedef struct {
     REAL pol_start, beta;     /* polar angle (from +z) of row 0's top edge; rows per radian */
     REAL interp_diff;         /* largest spread of the 4 interpolated ranges */
     int full_circle;          /* columns wrap around (azimuth field of view >= 2 pi) */
+    /* learned sensor model: per-pixel weight and truncation distance (NULL otherwise) */
+    const float *w_map, *eps_map;
 } FN(frame);
 
 /* Frame set-up.  The inverse of a rigid pose is (R^T, -R^T t).  R^T is exact;
@@ -69,6 +71,8 @@ static void FN(frame_setup)(FN(frame) *f, const ora_params *p, const float *dept
     f->d_max = (REAL)p->max_range;
     f->weighting = p->weighting;
     f->depth = depth;
+    f->w_map = 0;
+    f->eps_map = 0;
 }
 
 /* The TSDF functor after sampling (§IV-B): truncation band, weight, clamp.
@@ -114,12 +118,26 @@ static int FN(voxel_measure)(const FN(frame) *f, int32_t gx, int32_t gy, int32_t
         return 0;
     int32_t i = (int32_t)u;
     int32_t j = (int32_t)v;
-    REAL d = (REAL)f->depth[(size_t)j * (size_t)f->width + (size_t)i];
+    const size_t idx = (size_t)j * (size_t)f->width + (size_t)i;
+    REAL d = (REAL)f->depth[idx];
     /* a measurement is valid iff 0 < d <= max range (NaN, Inf, <= 0 fail) */
     if (!(d > 0 && d <= f->d_max))
         return 0;
     /* projective distance; voxel depth d_v is the camera-frame z for a depth image */
     REAL dp = d - zc;
+    if (f->w_map) {
+        /* learned sensor model: the pixel's own truncation distance and weight
+         * replace epsilon and the weighting function */
+        REAL e = (REAL)f->eps_map[idx];
+        if (!(dp >= -e))
+            return 0;
+        REAL w = (REAL)f->w_map[idx];
+        if (!(w > 0))
+            return 0;
+        *x = dp < e ? dp : e;
+        *wm = w;
+        return 1;
+    }
     return FN(measure_tail)(f, dp, x, wm);
 }
 
@@ -291,6 +309,9 @@ static REAL *FN(weight_ptr)(ora_map *m) { return (REAL *)m->weight; }
  * voxel by voxel; a block that has at least one updated voxel is looked up or
  * inserted in the block hash (§IV-A) and its updated voxels are fused.
  * model == NULL: pinhole depth image; otherwise a spherical range image. */
+static long long FN(integrate_prepared)(ora_map *m, FN(frame) *fp, const float K[4], const float *model,
+                                        const float T[16]);
+
 static long long FN(integrate_any)(ora_map *m, const float *depth, int width, int height,
                                    const float K[4], const float *model, const float T[16])
 {
@@ -299,6 +320,33 @@ static long long FN(integrate_any)(ora_map *m, const float *depth, int width, in
         FN(range_setup)(&f, &m->p, depth, width, height, model, T);
     else
         FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    return FN(integrate_prepared)(m, &f, K, model, T);
+}
+
+/* A pinhole frame with the learned sensor model's per-pixel weight and
+ * truncation maps.  The scan box reaches the largest truncation of any valid
+ * pixel behind the farthest measurement. */
+static long long FN(integrate_learned)(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                       const float T[16], const float *w_map, const float *eps_map)
+{
+    FN(frame) f;
+    FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    f.w_map = w_map;
+    f.eps_map = eps_map;
+    REAL emax = 0;
+    for (size_t k = 0; k < (size_t)width * (size_t)height; ++k) {
+        const float d = depth[k];
+        if (d > 0 && d <= (float)f.d_max && (REAL)eps_map[k] > emax)
+            emax = (REAL)eps_map[k];
+    }
+    f.eps = emax;
+    return FN(integrate_prepared)(m, &f, K, NULL, T);
+}
+
+static long long FN(integrate_prepared)(ora_map *m, FN(frame) *fp, const float K[4], const float *model,
+                                        const float T[16])
+{
+    FN(frame) f = *fp;
     m->n_touched = 0;
     int32_t bmin[3], bmax[3];
     const int any_valid = model ? FN(scan_box_range)(&f, model, T, bmin, bmax) : FN(scan_box)(&f, K, T, bmin, bmax);

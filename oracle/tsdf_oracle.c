@@ -390,3 +390,5 @@ long long ora_dense_integrate(int precision, float voxel_size, float truncation_
     return precision == 32 ? dense_f32(&p, depth, width, height, K, T, gmin, gdim, dist, weight)
                            : dense_f64(&p, depth, width, height, K, T, gmin, gdim, dist, weight);
 }
+
+#include "sensor_model_impl.h"

@@ -114,6 +114,41 @@ long long ora_dense_integrate(int precision, float voxel_size, float truncation_
                               const int32_t gmin[3], const int32_t gdim[3],
                               double *dist, double *weight);
 
+
+/* ---- learned sensor model (see sensor_model_impl.h for the definition) ---- */
+
+/* Number of parameters of the 27 -> 32 -> 32 -> 2 perceptron. */
+#define ORA_SM_NPARAM 2018
+
+/* The bfloat16 value nearest to x (ties to even), as a binary32. */
+float ora_round_bf16(float x);
+
+/* The 27 binary32 input features of every pixel (H x W x 27, zeros for
+ * invalid pixels). */
+void ora_sm_features(const float *depth, int width, int height, const float K[4], float max_range, float *feat);
+
+/* Per-pixel weight and truncation maps of a depth frame under the
+ * bfloat16-emulating binary32 forward (0 for invalid pixels).  params holds
+ * ORA_SM_NPARAM bfloat16-representable values.  Returns 0 or -1. */
+int ora_sm_maps(const float *depth, int width, int height, const float K[4], float max_range, float voxel_size,
+                const float *params, float *w_map, float *eps_map);
+
+/* Integrates a pinhole frame with per-pixel weights and truncation distances
+ * in place of the map's weighting and epsilon.  Returns updates or -1. */
+long long ora_integrate_learned(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                const float T_world_cam[16], const float *w_map, const float *eps_map);
+
+/* Training loss of the sensor model over a window of frames (n_frames depth
+ * images, row-major, and poses) against target distances of n_vox voxels
+ * (global voxel indices, 3 int32 each), in binary64; writes dL/dparams
+ * (ORA_SM_NPARAM doubles) and the number of voxels the prediction reaches.
+ * emulate_bf16 rounds inputs and hidden activations to bfloat16.  Returns the
+ * loss, or -1 when out of memory. */
+double ora_sm_loss_grad(const float *params, int n_frames, const float *depths, int width, int height,
+                        const float K[4], const float *T_world_cam, float voxel_size, float max_range,
+                        long long n_vox, const int32_t *vox, const double *target, int emulate_bf16,
+                        double *grad, long long *n_used);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,10 +1,11 @@
 """Launch-shape autotuner for the integration kernels.
 
 The kernels walk the block lattice of a frame (or of a batch of views) with a
-persistent grid.  Three knobs shape that walk (tsdf_set_launch_config in the C
+persistent grid.  Four knobs shape that walk (tsdf_set_launch_config in the C
 ABI): the number of workgroups per launch, the number of consecutive lattice
-blocks a lane culls before the wave compacts the survivors (the chunk), and
-whether workgroups are banded over image columns (partitions).  None of them
+blocks a wave culls at once, one per lane (the chunk), whether workgroups are
+banded over image columns (partitions), and whether blocks are also culled
+against a per-view pyramid of tile depth maxima (footprint).  None of them
 changes a result: every configuration leaves a bit-identical map.  Which one
 is fastest depends on the sensor sizes, the voxel size and the batch, so the
 tuner measures the candidates on a few steps of the caller's own workload,
@@ -24,6 +25,7 @@ import torch
 GROUPS = (256, 512, 1024, 2048)
 CHUNKS = (0, 1, 4, 8)
 PARTITIONS = (1, 8)
+FOOTPRINTS = ("never", "always")
 
 
 @dataclass(frozen=True)
@@ -31,13 +33,14 @@ class LaunchConfig:
     max_groups: int = 0      # 0 = library default
     partitions: int = 0      # 0 = library default (1)
     chunk: int = 0           # 0 = automatic from the lattice size
+    footprint: str = "auto"  # footprint culling: auto, never, always
 
     def apply(self, m) -> None:
-        m.set_launch_config(self.max_groups, self.partitions, self.chunk)
+        m.set_launch_config(self.max_groups, self.partitions, self.chunk, self.footprint)
 
 
 def default_candidates() -> List[LaunchConfig]:
-    return [LaunchConfig(g, p, c) for g in GROUPS for p in PARTITIONS for c in CHUNKS]
+    return [LaunchConfig(g, p, c, f) for g in GROUPS for p in PARTITIONS for c in CHUNKS for f in FOOTPRINTS]
 
 
 @dataclass

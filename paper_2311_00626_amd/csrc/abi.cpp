@@ -3,6 +3,7 @@
 // map memory management and kernel launches.  No exception leaves this file.
 #include "tsdf.h"
 #include "tsdf_internal.hpp"
+#include "sensor_model.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -26,6 +27,10 @@ struct tsdf_map {
     int max_groups;                       // cap on integration workgroups per launch
     tsdf_launch_config launch;            // explicit launch shape (0 fields = automatic)
     long long frames;                     // integrate calls launched so far (parity of the touched counters)
+    float *tiles = nullptr;               // footprint pyramids, kMaxViews slots (allocated on first use)
+    float *sm_params = nullptr;           // learned sensor model parameters (kSmParams)
+    float2 *sm_maps = nullptr;            // per-pixel (weight, truncation), kMaxViews slots
+    long long sm_slot = 0;                // pixels per slot of sm_maps
     // kernel timing
     bool profiling;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -57,7 +62,8 @@ bool params_valid(const tsdf_params *p)
         return false;
     if (!(p->max_range_m > 0 && std::isfinite(p->max_range_m)))
         return false;
-    if (p->weighting != TSDF_WEIGHT_CONSTANT && p->weighting != TSDF_WEIGHT_LINEAR_DROPOFF)
+    if (p->weighting != TSDF_WEIGHT_CONSTANT && p->weighting != TSDF_WEIGHT_LINEAR_DROPOFF &&
+        p->weighting != TSDF_WEIGHT_LEARNED)
         return false;
     if (p->storage != TSDF_STORAGE_FP32 && p->storage != TSDF_STORAGE_FP16)
         return false;
@@ -111,6 +117,13 @@ void free_device(tsdf_map *m)
     (void)hipFree(d.counters);
     (void)hipFree(d.totals);
     d = DeviceMap{};
+    (void)hipFree(m->tiles);
+    m->tiles = nullptr;
+    (void)hipFree(m->sm_params);
+    m->sm_params = nullptr;
+    (void)hipFree(m->sm_maps);
+    m->sm_maps = nullptr;
+    m->sm_slot = 0;
 }
 
 void free_events(tsdf_map *m)
@@ -341,6 +354,119 @@ int schedule(const tsdf_map *m, Lattice &lat)
     return (int)groups;
 }
 
+// Footprint culling policy for one launch: explicit, or automatic when the
+// lattice is large enough for the culled measurement work to outweigh the
+// pyramid pass.
+constexpr long long kFootprintAutoLattice = 1ll << 16;
+
+bool use_footprint(const tsdf_map *m, const Lattice &lat)
+{
+    if (m->launch.footprint == TSDF_FOOTPRINT_NEVER)
+        return false;
+    if (m->launch.footprint == TSDF_FOOTPRINT_ALWAYS)
+        return true;
+    return lat.n_lat >= kFootprintAutoLattice;
+}
+
+hipError_t ensure_tiles(tsdf_map *m)
+{
+    if (m->tiles)
+        return hipSuccess;
+    return hipMalloc((void **)&m->tiles, sizeof(float) * (size_t)kMaxViews * (size_t)kTileFloatsPerView);
+}
+
+// Points the view at pyramid slot `slot` (nothing for images beyond the
+// pyramid's largest side).
+void attach_tiles(const tsdf_map *m, CameraView &cv, int slot)
+{
+    cv.tiles = nullptr;
+    if (!m->tiles || cv.width > kTileMaxSide || cv.height > kTileMaxSide)
+        return;
+    int off = 0;
+    for (int l = 0; l < kTileLevels; ++l) {
+        const int ts = 1 << (kTileBaseShift + l);
+        cv.tile_cols[l] = (cv.width + ts - 1) / ts;
+        cv.tile_rows[l] = (cv.height + ts - 1) / ts;
+        cv.tile_off[l] = off;
+        off += cv.tile_cols[l] * cv.tile_rows[l];
+    }
+    cv.tiles = m->tiles + (size_t)slot * (size_t)kTileFloatsPerView;
+}
+
+// Builds the pyramid of a single-view launch when the policy asks for it.
+hipError_t prepare_footprint(tsdf_map *m, FrameArgs &fa, hipStream_t s)
+{
+    if (!use_footprint(m, fa.lat))
+        return hipSuccess;
+    hipError_t e = ensure_tiles(m);
+    if (e != hipSuccess)
+        return e;
+    attach_tiles(m, fa.cam, 0);
+    ViewsArgs va;
+    std::memset(&va, 0, sizeof(va));
+    va.cam[0] = fa.cam;
+    va.n_views = 1;
+    return launch_footprint_tiles(va, s);
+}
+
+hipError_t prepare_footprint(tsdf_map *m, ViewsArgs &va, hipStream_t s, bool launch)
+{
+    if (!use_footprint(m, va.lat))
+        return hipSuccess;
+    hipError_t e = ensure_tiles(m);
+    if (e != hipSuccess)
+        return e;
+    for (int v = 0; v < va.n_views; ++v)
+        attach_tiles(m, va.cam[v], v);
+    return launch ? launch_footprint_tiles(va, s) : hipSuccess;
+}
+
+// Learned weighting: per-pixel (weight, truncation) maps of the views,
+// slot v for view v, evaluated from the map's sensor-model parameters.
+hipError_t ensure_sm_maps(tsdf_map *m, long long pixels)
+{
+    if (m->sm_maps && m->sm_slot >= pixels)
+        return hipSuccess;
+    long long slot = std::max<long long>(pixels, 640ll * 480ll);
+    (void)hipFree(m->sm_maps);
+    m->sm_maps = nullptr;
+    m->sm_slot = 0;
+    hipError_t e = hipMalloc((void **)&m->sm_maps, sizeof(float2) * (size_t)slot * kMaxViews);
+    if (e == hipSuccess)
+        m->sm_slot = slot;
+    return e;
+}
+
+SmView sm_view_of(const CameraView &cv)
+{
+    SmView v;
+    v.depth = cv.depth;
+    v.width = cv.width;
+    v.height = cv.height;
+    v.fx = cv.fx;
+    v.fy = cv.fy;
+    v.cx = cv.cx;
+    v.cy = cv.cy;
+    v.d_max = cv.d_max;
+    return v;
+}
+
+hipError_t prepare_learned(tsdf_map *m, CameraView *cams, int n_views, hipStream_t s)
+{
+    if (m->p.weighting != TSDF_WEIGHT_LEARNED)
+        return hipSuccess;
+    long long px = 0;
+    for (int v = 0; v < n_views; ++v)
+        px = std::max<long long>(px, (long long)cams[v].width * cams[v].height);
+    hipError_t e = ensure_sm_maps(m, px);
+    for (int v = 0; v < n_views && e == hipSuccess; ++v) {
+        float2 *out = m->sm_maps + (size_t)v * (size_t)m->sm_slot;
+        e = launch_sm_maps(sm_view_of(cams[v]), m->p.voxel_size_m, m->sm_params, out, s);
+        cams[v].sm_maps = out;
+    }
+    return e;
+}
+
 struct CounterSnapshot {
     uint32_t c[kNumCounterWords];
     unsigned long long t[kNumTotalWords];
@@ -412,6 +538,8 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     m->eps = p->truncation_vox * p->voxel_size_m;
     m->delta = p->voxel_size_m;
     m->span_inv = m->eps > m->delta ? 1.0f / (m->eps - m->delta) : 0.0f;
+    if (p->weighting == TSDF_WEIGHT_LEARNED)
+        m->eps = 8.0f * p->voxel_size_m;    // bound of every per-pixel truncation (culling only)
     m->max_groups = 512;   // a multiple of kPartitions
     m->launch = tsdf_launch_config{0, 0, 0, 0};
     m->frames = 0;
@@ -473,6 +601,8 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
 {
     if (!m || !view_args_valid(depth_dev, width, height, K, T_world_cam))
         return TSDF_EINVAL;
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED && !m->sm_params)
+        return TSDF_EINVAL;
     if (m->sticky)
         return TSDF_ESTATE;
     FrameArgs fa;
@@ -487,6 +617,10 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    if (e == hipSuccess)
+        e = prepare_footprint(m, fa, s);
+    if (e == hipSuccess)
+        e = prepare_learned(m, &fa.cam, 1, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -508,6 +642,8 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
                         lidar->polar_fov_rad};
     if (!lidar_valid(lidar->width, lidar->height, A, lidar->interp_max_diff_m, lidar->max_range_m))
         return TSDF_EINVAL;
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED)
+        return TSDF_EINVAL;    // the learned model is defined on pinhole depth images
     if (m->sticky)
         return TSDF_ESTATE;
     const float range = lidar->max_range_m > 0.0f ? lidar->max_range_m : m->p.max_range_m;
@@ -523,6 +659,10 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    if (e == hipSuccess)
+        e = prepare_footprint(m, fa, s);
+    if (e == hipSuccess)
+        e = prepare_learned(m, &fa.cam, 1, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -635,11 +775,17 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
     int st = build_views_args(m, views, n_views, va, spherical);
     if (st != TSDF_OK)
         return st;
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED && (spherical || !m->sm_params))
+        return TSDF_EINVAL;
     if (m->sticky)
         return TSDF_ESTATE;
     va.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    if (e == hipSuccess)
+        e = prepare_footprint(m, va, s, true);
+    if (e == hipSuccess)
+        e = prepare_learned(m, va.cam, va.n_views, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -657,6 +803,8 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
     if (!m || !out)
         return TSDF_EINVAL;
     *out = nullptr;
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED)
+        return TSDF_EINVAL;
     tsdf_step *st = new (std::nothrow) tsdf_step();
     if (!st)
         return TSDF_ENOMEM;
@@ -681,6 +829,8 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
         }
         if (e == hipSuccess) {
             hipError_t e1 = hipMemcpyAsync(st->dev[k], st->pinned[k], sizeof(ViewsArgs), hipMemcpyHostToDevice, cs);
+            if (e1 == hipSuccess)
+                e1 = launch_footprint_tiles_dev(st->dev[k], cs);
             hipError_t e2 = e1 == hipSuccess ? launch_integrate_views_dev(m->dm, st->dev[k], st->spherical,
                                                                           m->p.weighting, st->groups, cs)
                                              : e1;
@@ -720,6 +870,8 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
     va.lat.chunk = lat.chunk;
     va.lat.partitions = lat.partitions;
     hipError_t e = use_device(m);
+    if (e == hipSuccess)
+        e = prepare_footprint(m, va, nullptr, false);   // the graph builds the pyramids
     if (e != hipSuccess)
         return hip_status(e);
     const int k = st->next;
@@ -909,7 +1061,9 @@ int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *lc)
     tsdf_launch_config c = {0, 0, 0, 0};
     if (lc)
         c = *lc;
-    if (c.max_groups < 0 || c.max_groups > 65536 || c.chunk < 0 || c.chunk > kMaxChunk || c.reserved != 0 ||
+    if (c.max_groups < 0 || c.max_groups > 65536 || c.chunk < 0 || c.chunk > kMaxChunk ||
+        (c.footprint != TSDF_FOOTPRINT_AUTO && c.footprint != TSDF_FOOTPRINT_NEVER &&
+         c.footprint != TSDF_FOOTPRINT_ALWAYS) ||
         (c.partitions != 0 && c.partitions != 1 && c.partitions != kPartitions))
         return TSDF_EINVAL;
     m->launch = c;
@@ -942,6 +1096,202 @@ int tsdf_profile_read(tsdf_map *m, double *total_ms, long long *launches)
     *launches = (long long)m->ev_used;
     m->ev_used = 0;
     return TSDF_OK;
+}
+
+}  // extern "C"
+
+// ---- learned sensor model ------------------------------------------------
+
+struct tsdf_sm_trainer {
+    int width, height, max_frames;
+    int device;
+    float2 *maps;      // max_frames x H x W (weight, truncation)
+    float *gw, *ge;    // max_frames x H x W gradients with respect to weight and truncation
+    double *acc;       // [0] sum of squared errors, [1] voxels reached
+};
+
+namespace {
+
+bool bf16_params_valid(const float *p, int n)
+{
+    for (int k = 0; k < n; ++k) {
+        uint32_t u;
+        std::memcpy(&u, &p[k], 4);
+        if (!std::isfinite(p[k]) || (u & 0xFFFFu) != 0)
+            return false;
+    }
+    return true;
+}
+
+// Camera-from-world of a rigid pose, as for integration: R^T exactly, -R^T t
+// accumulated in binary64 and rounded once.
+void pose_inverse(const float T[16], float R[9], float t[3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            R[3 * i + j] = T[4 * j + i];
+    for (int i = 0; i < 3; ++i) {
+        const double acc = ((double)T[0 * 4 + i] * (double)T[3] + (double)T[1 * 4 + i] * (double)T[7]) +
+                           (double)T[2 * 4 + i] * (double)T[11];
+        t[i] = (float)(-acc);
+    }
+}
+
+void trainer_free(tsdf_sm_trainer *t)
+{
+    (void)hipFree(t->maps);
+    (void)hipFree(t->gw);
+    (void)hipFree(t->ge);
+    (void)hipFree(t->acc);
+    delete t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsdf_set_sensor_model(tsdf_map *m, const float *params)
+{
+    if (!m || !params || !bf16_params_valid(params, kSmParams))
+        return TSDF_EINVAL;
+    hipError_t e = use_device(m);
+    if (e == hipSuccess && !m->sm_params)
+        e = hipMalloc((void **)&m->sm_params, sizeof(float) * kSmParams);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();   // no launch may still read the previous parameters
+    if (e == hipSuccess)
+        e = hipMemcpy(m->sm_params, params, sizeof(float) * kSmParams, hipMemcpyHostToDevice);
+    return hip_status(e);
+}
+
+int tsdf_sensor_maps(const float *depth_dev, int width, int height, const float K[4], float max_range,
+                     float voxel_size, const float *params_dev, float *maps_dev, void *hip_stream)
+{
+    if (!depth_dev || !params_dev || !maps_dev || !K || width <= 0 || height <= 0 ||
+        (long long)width * height > (1ll << 28) || !finite_all(K, 4) || !(K[0] > 0.0f && K[1] > 0.0f) ||
+        !(max_range > 0.0f && std::isfinite(max_range)) || !(voxel_size > 0.0f && std::isfinite(voxel_size)))
+        return TSDF_EINVAL;
+    SmView v{depth_dev, width, height, K[0], K[1], K[2], K[3], max_range};
+    return hip_status(launch_sm_maps(v, voxel_size, params_dev, (float2 *)maps_dev, (hipStream_t)hip_stream));
+}
+
+int tsdf_sm_trainer_create(int width, int height, int max_frames, tsdf_sm_trainer **out)
+{
+    if (!out)
+        return TSDF_EINVAL;
+    *out = nullptr;
+    if (width <= 0 || height <= 0 || (long long)width * height > (1ll << 26) || max_frames < 1 ||
+        max_frames > kSmMaxFrames)
+        return TSDF_EINVAL;
+    tsdf_sm_trainer *t = new (std::nothrow) tsdf_sm_trainer();
+    if (!t)
+        return TSDF_ENOMEM;
+    t->width = width;
+    t->height = height;
+    t->max_frames = max_frames;
+    const size_t px = (size_t)width * height * (size_t)max_frames;
+    hipError_t e = hipGetDevice(&t->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->maps, sizeof(float2) * px);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->gw, sizeof(float) * px);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->ge, sizeof(float) * px);
+    if (e == hipSuccess) e = hipMalloc((void **)&t->acc, sizeof(double) * 2);
+    if (e != hipSuccess) {
+        trainer_free(t);
+        return hip_status(e);
+    }
+    *out = t;
+    return TSDF_OK;
+}
+
+int tsdf_sm_trainer_destroy(tsdf_sm_trainer *t)
+{
+    if (!t)
+        return TSDF_OK;
+    (void)hipSetDevice(t->device);
+    (void)hipDeviceSynchronize();
+    trainer_free(t);
+    return TSDF_OK;
+}
+
+int tsdf_sm_loss_grad(tsdf_sm_trainer *t, const float *params_dev, int n_frames, const float *const *depth_dev,
+                      const float K[4], const float *T_world_cam, float voxel_size, float max_range, long long n_vox,
+                      const int *vox_dev, const float *target_dev, float *grad_dev, double *loss_host,
+                      void *hip_stream)
+{
+    if (!t || !params_dev || !depth_dev || !K || !T_world_cam || !grad_dev || n_frames < 1 ||
+        n_frames > t->max_frames || n_vox < 0 || (n_vox > 0 && (!vox_dev || !target_dev)) || !finite_all(K, 4) ||
+        !(K[0] > 0.0f && K[1] > 0.0f) || !(max_range > 0.0f && std::isfinite(max_range)) ||
+        !(voxel_size > 0.0f && std::isfinite(voxel_size)))
+        return TSDF_EINVAL;
+    for (int f = 0; f < n_frames; ++f)
+        if (!depth_dev[f] || !pose_valid(T_world_cam + 16 * f))
+            return TSDF_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = hipSetDevice(t->device);
+    const long long wh = (long long)t->width * t->height;
+    SmLossArgs la;
+    std::memset(&la, 0, sizeof(la));
+    SmBackArgs ba;
+    std::memset(&ba, 0, sizeof(ba));
+    for (int f = 0; f < n_frames && e == hipSuccess; ++f) {
+        SmView v{depth_dev[f], t->width, t->height, K[0], K[1], K[2], K[3], max_range};
+        float2 *maps = t->maps + (size_t)f * (size_t)wh;
+        e = launch_sm_maps(v, voxel_size, params_dev, maps, s);
+        SmFrame &fr = la.frames[f];
+        pose_inverse(T_world_cam + 16 * f, fr.R, fr.t);
+        fr.depth = depth_dev[f];
+        fr.maps = maps;
+        fr.gw = t->gw + (size_t)f * (size_t)wh;
+        fr.ge = t->ge + (size_t)f * (size_t)wh;
+        ba.views[f] = v;
+    }
+    if (e == hipSuccess) e = launch_sm_fill(t->gw, wh * n_frames, 0.0f, s);
+    if (e == hipSuccess) e = launch_sm_fill(t->ge, wh * n_frames, 0.0f, s);
+    if (e == hipSuccess) e = launch_sm_fill(grad_dev, kSmParams, 0.0f, s);
+    la.n_frames = n_frames;
+    la.width = t->width;
+    la.height = t->height;
+    la.fx = K[0];
+    la.fy = K[1];
+    la.cx = K[2];
+    la.cy = K[3];
+    la.d_max = max_range;
+    la.vs = voxel_size;
+    la.n_vox = n_vox;
+    la.vox = vox_dev;
+    la.target = target_dev;
+    la.acc = t->acc;
+    if (e == hipSuccess) e = launch_sm_loss(la, s);
+    ba.n_frames = n_frames;
+    ba.width = t->width;
+    ba.height = t->height;
+    ba.vs = voxel_size;
+    ba.params = params_dev;
+    ba.gw = t->gw;
+    ba.ge = t->ge;
+    ba.acc = t->acc;
+    ba.grad = grad_dev;
+    if (e == hipSuccess) e = launch_sm_backward(ba, s);
+    if (e == hipSuccess && loss_host) {
+        double acc[2];
+        e = hipMemcpyAsync(acc, t->acc, sizeof(acc), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            loss_host[0] = acc[1] > 0.0 ? acc[0] / acc[1] : 0.0;
+            loss_host[1] = acc[1];
+        }
+    }
+    return hip_status(e);
+}
+
+int tsdf_sm_adam(float *master_dev, float *m1_dev, float *m2_dev, const float *grad_dev, float *params_dev, int n,
+                 float lr, float beta1, float beta2, float eps, int step, void *hip_stream)
+{
+    if (!master_dev || !m1_dev || !m2_dev || !grad_dev || !params_dev || n <= 0 || step < 1 ||
+        !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return TSDF_EINVAL;
+    return hip_status(launch_sm_adam(master_dev, m1_dev, m2_dev, grad_dev, params_dev, n, lr, beta1, beta2, eps, step,
+                                     (hipStream_t)hip_stream));
 }
 
 }  // extern "C"

@@ -284,11 +284,6 @@ __device__ __forceinline__ bool lane_block_in_spherical(const CameraView &cv, co
     return true;
 }
 
-__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
-{
-    return cv.model == kModelSpherical ? lane_block_in_spherical(cv, mc, bx, by, bz)
-                                       : lane_block_in_pinhole(cv, mc, bx, by, bz);
-}
 
 // atan on [0, 1]: the polynomial of Abramowitz & Stegun, Handbook of
 // Mathematical Functions, formula 4.4.49 (|error| <= 2e-8), Horner's rule in
@@ -321,6 +316,162 @@ __device__ __forceinline__ float atan2_as(float y, float x)
         a = 3.14159274f - a;
     a = y < 0.0f ? -a : a;
     return (ax == 0.0f && ay == 0.0f) ? 0.0f : a;
+}
+
+// Largest valid measurement over the pixel rectangle [i0, i1] x [j0, j1]
+// (inside the image) from the view's footprint pyramid, at the finest level
+// where the rectangle spans at most 3 x 3 tiles; `ok` is false when even the
+// coarsest level needs more.
+__device__ __forceinline__ float footprint_max(const CameraView &cv, int i0, int i1, int j0, int j1, bool &ok)
+{
+    int l = 0;
+    while (l < kTileLevels - 1 && (((i1 >> (kTileBaseShift + l)) - (i0 >> (kTileBaseShift + l))) > 2 ||
+                                   ((j1 >> (kTileBaseShift + l)) - (j0 >> (kTileBaseShift + l))) > 2))
+        ++l;
+    const int sh = kTileBaseShift + l;
+    const int a0 = i0 >> sh, a1 = i1 >> sh, b0 = j0 >> sh, b1 = j1 >> sh;
+    ok = a1 - a0 <= 2 && b1 - b0 <= 2;
+    const int off = l == 0 ? cv.tile_off[0] : l == 1 ? cv.tile_off[1] : l == 2 ? cv.tile_off[2] : cv.tile_off[3];
+    const int cols = l == 0 ? cv.tile_cols[0] : l == 1 ? cv.tile_cols[1] : l == 2 ? cv.tile_cols[2] : cv.tile_cols[3];
+    const float *T = cv.tiles + off;
+    float m = 0.0f;
+    if (ok) {
+        // a fixed 3 x 3 window, repeated indices clamped into [a0, a1] x [b0, b1]
+#pragma unroll
+        for (int db = 0; db < 3; ++db) {
+            const int b = min(b0 + db, b1);
+#pragma unroll
+            for (int da = 0; da < 3; ++da)
+                m = fmaxf(m, T[b * cols + min(a0 + da, a1)]);
+        }
+    }
+    return m;
+}
+
+// Footprint culling against a pinhole view.  The voxels of a block project
+// inside the rectangle of its 8 projected corners (the projection of a box in
+// front of the camera is the convex hull of its corners' projections) and
+// have depth at least the corners' minimum z.  An updated voxel has z <= d + eps
+// for the valid measurement d of its pixel, so the block is dropped when its
+// minimum z exceeds the footprint's largest measurement + eps (+ the rounding
+// slack margin_z).  Corners are projected with a fast reciprocal and the
+// rectangle is widened by 2 pixels, far beyond the binary32 error of either
+// projection.  Blocks reaching within 1 mm of the camera plane are kept.
+__device__ __forceinline__ bool lane_block_footprint_pinhole(const CameraView &cv, const MapConsts &mc, int bx,
+                                                             int by, int bz)
+{
+    const float e = 8.0f * mc.vs;
+    const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
+    float zmin = 3.0e38f, umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float px = X + ((c & 1) ? e : 0.0f), py = Y + ((c & 2) ? e : 0.0f), pz = Z + ((c & 4) ? e : 0.0f);
+        const float x = cv.R[0] * px + cv.R[1] * py + cv.R[2] * pz + cv.t[0];
+        const float y = cv.R[3] * px + cv.R[4] * py + cv.R[5] * pz + cv.t[1];
+        const float z = cv.R[6] * px + cv.R[7] * py + cv.R[8] * pz + cv.t[2];
+        const float r = __builtin_amdgcn_rcpf(fmaxf(z, 1e-3f));
+        const float u = cv.fx * (x * r) + cv.cx;
+        const float v = cv.fy * (y * r) + cv.cy;
+        zmin = fminf(zmin, z);
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+    }
+    if (!(zmin > 1e-3f))
+        return true;
+    const float lo_u = fmaxf(umin - 2.0f, 0.0f), hi_u = fminf(umax + 2.0f, cv.width_f - 1.0f);
+    const float lo_v = fmaxf(vmin - 2.0f, 0.0f), hi_v = fminf(vmax + 2.0f, cv.height_f - 1.0f);
+    if (hi_u < lo_u || hi_v < lo_v)
+        return false;
+    bool ok;
+    const float dm = footprint_max(cv, (int)lo_u, (int)hi_u, (int)lo_v, (int)hi_v, ok);
+    return !ok || zmin <= dm + mc.eps + mc.margin_z;
+}
+
+// Footprint culling against a spherical view.  Every voxel centre lies in
+// the block's bounding sphere (centre c, radius rho), so its range is at least
+// |c| - rho and its azimuth and polar angle lie within the half-angle
+// asin(rho / distance) of the sphere's (taken about the z axis for the
+// azimuth); the columns and rows it interpolates from follow, with one of
+// slack on each side.  The block is dropped when |c| - rho exceeds the
+// largest valid range over those pixels + eps.  Blocks whose sphere nearly
+// reaches the sensor are kept; so are those nearly reaching the z axis (all
+// azimuths), and, for a partial-circle sensor, those straddling azimuth +-pi.
+__device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView &cv, const MapConsts &mc, int bx,
+                                                               int by, int bz)
+{
+    const float e = 8.0f * mc.vs;
+    const float X = ((float)(8 * bx) + 4.0f) * mc.vs, Y = ((float)(8 * by) + 4.0f) * mc.vs,
+                Z = ((float)(8 * bz) + 4.0f) * mc.vs;
+    const float x = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
+    const float y = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
+    const float z = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
+    const float rad = 0.866026f * e * 1.001f + mc.margin_z;
+    const float R2 = x * x + y * y + z * z;
+    const float Rc = sqrtf(R2);
+    if (!(Rc > 1.05f * rad + 1e-3f))
+        return true;
+    // rows
+    const float phi_c = atan2_as(sqrtf(x * x + y * y), z);
+    const float hp = atan2_as(rad, sqrtf(R2 - rad * rad));
+    const float v_lo = (phi_c - hp - cv.pol_start) * cv.beta, v_hi = (phi_c + hp - cv.pol_start) * cv.beta;
+    const float r_lo = fmaxf(floorf(v_lo - 0.5f) - 1.0f, 0.0f);
+    const float r_hi = fminf(floorf(v_hi - 0.5f) + 2.0f, cv.height_f - 1.0f);
+    if (r_hi < r_lo)
+        return false;
+    const int j0 = (int)r_lo, j1 = (int)r_hi;
+    // columns
+    const float rho2 = x * x + y * y;
+    if (!(sqrtf(rho2) > 1.05f * rad + 1e-3f))
+        return true;
+    const float theta_c = atan2_as(y, x);
+    const float ha = atan2_as(rad, sqrtf(rho2 - rad * rad));
+    const float W = cv.width_f;
+    float c_lo = floorf((theta_c - ha - cv.az_start) * cv.alpha - 0.5f) - 1.0f;
+    float c_hi = floorf((theta_c + ha - cv.az_start) * cv.alpha - 0.5f) + 2.0f;
+    float dm;
+    bool ok = true;
+    if (cv.full_circle) {
+        if (c_hi - c_lo + 1.0f >= W)
+            return true;
+        // columns wrap modulo W: shift c_lo into [0, W); c_hi < c_lo + W - 1
+        const float k = floorf(c_lo / W);
+        c_lo = fminf(fmaxf(c_lo - k * W, 0.0f), W - 1.0f);
+        c_hi = c_hi - k * W;
+        if (c_hi >= W) {
+            // [c_lo, W - 1] and [0, c_hi - W]
+            bool ok2;
+            dm = fmaxf(footprint_max(cv, (int)c_lo, cv.width - 1, j0, j1, ok),
+                       footprint_max(cv, 0, (int)fminf(c_hi - W, W - 1.0f), j0, j1, ok2));
+            ok = ok && ok2;
+        } else {
+            if (!(c_hi >= c_lo))
+                return true;
+            dm = footprint_max(cv, (int)c_lo, (int)c_hi, j0, j1, ok);
+        }
+    } else {
+        if (theta_c - ha < -3.14159265f || theta_c + ha > 3.14159265f)
+            return true;
+        c_lo = fmaxf(c_lo, 0.0f);
+        c_hi = fminf(c_hi, W - 1.0f);
+        if (c_hi < c_lo)
+            return false;
+        dm = footprint_max(cv, (int)c_lo, (int)c_hi, j0, j1, ok);
+    }
+    return !ok || Rc - rad <= dm + mc.eps + mc.margin_z;
+}
+
+__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+{
+    if (cv.model == kModelSpherical) {
+        if (!lane_block_in_spherical(cv, mc, bx, by, bz))
+            return false;
+        return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz);
+    }
+    if (!lane_block_in_pinhole(cv, mc, bx, by, bz))
+        return false;
+    return !cv.tiles || lane_block_footprint_pinhole(cv, mc, bx, by, bz);
 }
 
 // Ownership band of a block (one per XCD): the image-column band of the
@@ -437,6 +588,24 @@ __device__ __forceinline__ uint32_t measure_pinhole(const CameraView &cv, const 
     for (int s = 0; s < 8; ++s)
         d[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(depth, pix_off[s], 0, 0));
     uint32_t hit = 0;
+    if constexpr (WEIGHTING == kWeightLearned) {
+        // learned sensor model: the pixel's own (weight, truncation) pair
+        const __amdgpu_buffer_rsrc_t maps = make_rsrc(cv.sm_maps, 8u * width * (uint32_t)cv.height);
+        float2 we[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            we[s] = load_f2(maps, pix_off[s] == kOutOfRange ? kOutOfRange : 2u * pix_off[s]);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const float dp = d[s] - zc[s];
+            const float e = we[s].y;
+            const bool upd = d[s] > 0.0f && d[s] <= cv.d_max && dp >= -e && we[s].x > 0.0f;
+            xs[s] = dp < e ? dp : e;
+            ws[s] = we[s].x;
+            hit |= (upd ? 1u : 0u) << s;
+        }
+        return hit;
+    }
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         // valid measurement, truncation band (skip below -eps), weight > 0

@@ -85,28 +85,37 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
 
 }  // namespace
 
-template <int SPHERICAL>
-static void launch_depth_model(const DeviceMap &dm, const FrameArgs &fa, int weighting, dim3 grid, dim3 block,
-                               hipStream_t stream)
+template <int WEIGHTING, int SPHERICAL>
+static void launch_depth_storage(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
 {
-    if (weighting == 1 && dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 1, SPHERICAL>), grid, block, 0, stream, dm, fa);
-    else if (weighting == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<1, 0, SPHERICAL>), grid, block, 0, stream, dm, fa);
-    else if (dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 1, SPHERICAL>), grid, block, 0, stream, dm, fa);
+    if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0, stream,
+                           dm, fa);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<0, 0, SPHERICAL>), grid, block, 0, stream, dm, fa);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0, stream,
+                           dm, fa);
 }
 
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
                                   hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (fa.cam.model == kModelSpherical)
-        launch_depth_model<1>(dm, fa, weighting, grid, block, stream);
-    else
-        launch_depth_model<0>(dm, fa, weighting, grid, block, stream);
+    const bool spherical = fa.cam.model == kModelSpherical;
+    if (weighting == kWeightLearned) {
+        if (spherical || !fa.cam.sm_maps)
+            return hipErrorInvalidValue;
+        launch_depth_storage<kWeightLearned, 0>(dm, fa, grid, block, stream);
+    } else if (weighting == kWeightDropoff) {
+        if (spherical)
+            launch_depth_storage<kWeightDropoff, 1>(dm, fa, grid, block, stream);
+        else
+            launch_depth_storage<kWeightDropoff, 0>(dm, fa, grid, block, stream);
+    } else {
+        if (spherical)
+            launch_depth_storage<kWeightConstant, 1>(dm, fa, grid, block, stream);
+        else
+            launch_depth_storage<kWeightConstant, 0>(dm, fa, grid, block, stream);
+    }
     return hipGetLastError();
 }
 

@@ -135,18 +135,15 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel_de
 
 }  // namespace
 
-template <int SPHERICAL>
-static void launch_views_model(const DeviceMap &dm, const ViewsArgs &va, int weighting, dim3 grid, dim3 block,
-                               hipStream_t stream)
+template <int WEIGHTING, int SPHERICAL>
+static void launch_views_storage(const DeviceMap &dm, const ViewsArgs &va, dim3 grid, dim3 block, hipStream_t stream)
 {
-    if (weighting == 1 && dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
-    else if (weighting == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<1, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
-    else if (dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0, stream,
+                           dm, va);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<0, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0, stream,
+                           dm, va);
 }
 
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
@@ -156,35 +153,53 @@ hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int 
     bool spherical = false;
     for (int v = 0; v < va.n_views; ++v)
         spherical = spherical || va.cam[v].model == kModelSpherical;
-    if (spherical)
-        launch_views_model<1>(dm, va, weighting, grid, block, stream);
-    else
-        launch_views_model<0>(dm, va, weighting, grid, block, stream);
+    if (weighting == kWeightLearned) {
+        if (spherical)
+            return hipErrorInvalidValue;
+        launch_views_storage<kWeightLearned, 0>(dm, va, grid, block, stream);
+    } else if (weighting == kWeightDropoff) {
+        if (spherical)
+            launch_views_storage<kWeightDropoff, 1>(dm, va, grid, block, stream);
+        else
+            launch_views_storage<kWeightDropoff, 0>(dm, va, grid, block, stream);
+    } else {
+        if (spherical)
+            launch_views_storage<kWeightConstant, 1>(dm, va, grid, block, stream);
+        else
+            launch_views_storage<kWeightConstant, 0>(dm, va, grid, block, stream);
+    }
     return hipGetLastError();
 }
 
-template <int SPHERICAL>
-static void launch_views_dev_model(const DeviceMap &dm, const ViewsArgs *va, int weighting, dim3 grid, dim3 block,
-                                   hipStream_t stream)
+template <int WEIGHTING, int SPHERICAL>
+static void launch_views_dev_storage(const DeviceMap &dm, const ViewsArgs *va, dim3 grid, dim3 block,
+                                     hipStream_t stream)
 {
-    if (weighting == 1 && dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<1, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
-    else if (weighting == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<1, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
-    else if (dm.storage == 1)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<0, 1, SPHERICAL>), grid, block, 0, stream, dm, va);
+    if (dm.storage == 1)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
+                           stream, dm, va);
     else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<0, 0, SPHERICAL>), grid, block, 0, stream, dm, va);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
+                           stream, dm, va);
 }
 
 hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,
                                       int groups, hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
-    if (spherical)
-        launch_views_dev_model<1>(dm, va_dev, weighting, grid, block, stream);
-    else
-        launch_views_dev_model<0>(dm, va_dev, weighting, grid, block, stream);
+    if (weighting == kWeightLearned)
+        return hipErrorInvalidValue;
+    if (weighting == kWeightDropoff) {
+        if (spherical)
+            launch_views_dev_storage<kWeightDropoff, 1>(dm, va_dev, grid, block, stream);
+        else
+            launch_views_dev_storage<kWeightDropoff, 0>(dm, va_dev, grid, block, stream);
+    } else {
+        if (spherical)
+            launch_views_dev_storage<kWeightConstant, 1>(dm, va_dev, grid, block, stream);
+        else
+            launch_views_dev_storage<kWeightConstant, 0>(dm, va_dev, grid, block, stream);
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,434 @@
+// Learned sensor model: per-pixel measurement weight and truncation distance
+// from a 27 -> 32 -> 32 -> 2 perceptron on the pixel's depth neighbourhood,
+// in place of a fixed weighting function (§IV-B lets the weight follow the
+// sensor's error model).
+//
+// Inputs of pixel (i, j) with valid depth d: the 5 x 5 patch of differences
+// q - d clipped to [-0.5, 0.5] m (0 outside the image or for invalid q), d,
+// and the incidence angle between the pixel's ray and the normal of the
+// back-projected depth (central differences; pi/2 without all 4 neighbours).
+// Outputs o: weight w = (o0 + sqrt(o0^2 + 4)) / 2 and truncation
+// eps = vs (1 + 7 s) with s = (1 + o1 / sqrt(1 + o1^2)) / 2.
+//
+// Inference (sm_maps_kernel) rounds inputs and hidden activations to
+// bfloat16 and accumulates every dot product in binary32, one fused
+// multiply-add per term in index order from the bias; with parameters that
+// are bfloat16 values this reproduces the CPU reference bit for bit.
+//
+// Training computes the gradient of
+//   L = (1/N) sum_v (D(v) - D*(v))^2,  D(v) = sum_f w_f x_f / sum_f w_f,
+// over target voxels v of a window of frames (x_f = min(d_p, eps_f) of the
+// pixel frame f projects v into): sm_fuse_loss_kernel evaluates D(v) and
+// scatters dL/dw and dL/deps onto the pixels, sm_backward_kernel
+// back-propagates them through the perceptron and reduces the parameter
+// gradient over 64-pixel tiles staged in LDS, and sm_adam_kernel updates a
+// binary32 master copy and its bfloat16 rounding.
+#include "device_common.hpp"
+
+#include "sensor_model.hpp"
+
+namespace tsdf {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ float round_bf16(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7f800000u) == 0x7f800000u)
+        return x;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(float, u & 0xffff0000u);
+}
+
+__device__ __forceinline__ bool sm_valid(float d, float d_max) { return d > 0.0f && d <= d_max; }
+
+__device__ __forceinline__ float sm_depth(const SmView &v, int i, int j) { return v.depth[(size_t)j * v.width + i]; }
+
+__device__ float sm_incidence(const SmView &v, int i, int j, float d)
+{
+    const float half_pi = 1.57079637f;
+    if (i < 1 || i > v.width - 2 || j < 1 || j > v.height - 2)
+        return half_pi;
+    const float dl = sm_depth(v, i - 1, j), dr = sm_depth(v, i + 1, j);
+    const float du = sm_depth(v, i, j - 1), dd = sm_depth(v, i, j + 1);
+    if (!(sm_valid(dl, v.d_max) && sm_valid(dr, v.d_max) && sm_valid(du, v.d_max) && sm_valid(dd, v.d_max)))
+        return half_pi;
+    const float rxl = (((float)(i - 1) + 0.5f) - v.cx) / v.fx, rxc = (((float)i + 0.5f) - v.cx) / v.fx;
+    const float rxr = (((float)(i + 1) + 0.5f) - v.cx) / v.fx;
+    const float ryu = (((float)(j - 1) + 0.5f) - v.cy) / v.fy, ryc = (((float)j + 0.5f) - v.cy) / v.fy;
+    const float ryd = (((float)(j + 1) + 0.5f) - v.cy) / v.fy;
+    const float ax = dr * rxr - dl * rxl, ay = dr * ryc - dl * ryc, az = dr - dl;
+    const float bx = dd * rxc - du * rxc, by = dd * ryd - du * ryu, bz = dd - du;
+    const float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+    const float px = d * rxc, py = d * ryc, pz = d;
+    const float dot = (nx * px + ny * py) + nz * pz;
+    const float cx = ny * pz - nz * py, cy = nz * px - nx * pz, cz = nx * py - ny * px;
+    const float cr = sqrtf((cx * cx + cy * cy) + cz * cz);
+    return atan2_as(cr, fabsf(dot));
+}
+
+// The 27 inputs, already rounded to bfloat16.
+__device__ __forceinline__ void sm_inputs(const SmView &v, int i, int j, float d, float x[kSmIn])
+{
+#pragma unroll
+    for (int dj = -2; dj <= 2; ++dj)
+#pragma unroll
+        for (int di = -2; di <= 2; ++di) {
+            const int ii = i + di, jj = j + dj;
+            float q = 0.0f;
+            if (ii >= 0 && ii < v.width && jj >= 0 && jj < v.height) {
+                const float dq = sm_depth(v, ii, jj);
+                if (sm_valid(dq, v.d_max)) {
+                    q = dq - d;
+                    q = q < -0.5f ? -0.5f : (q > 0.5f ? 0.5f : q);
+                }
+            }
+            x[(dj + 2) * 5 + (di + 2)] = round_bf16(q);
+        }
+    x[25] = round_bf16(d);
+    x[26] = round_bf16(sm_incidence(v, i, j, d));
+}
+
+// Forward through the hidden layers with parameters P (LDS); h1, h2 are the
+// bfloat16 activations, o the binary32 outputs.
+__device__ __forceinline__ void sm_forward(const float *P, const float x[kSmIn], float h1[kSmHidden],
+                                           float h2[kSmHidden], float o[kSmOut])
+{
+#pragma unroll 4
+    for (int k = 0; k < kSmHidden; ++k) {
+        float a = P[kSmB1 + k];
+#pragma unroll
+        for (int m = 0; m < kSmIn; ++m)
+            a = __builtin_fmaf(P[kSmW1 + kSmIn * k + m], x[m], a);
+        h1[k] = round_bf16(a > 0.0f ? a : 0.0f);
+    }
+#pragma unroll 4
+    for (int k = 0; k < kSmHidden; ++k) {
+        float a = P[kSmB2 + k];
+#pragma unroll
+        for (int m = 0; m < kSmHidden; ++m)
+            a = __builtin_fmaf(P[kSmW2 + kSmHidden * k + m], h1[m], a);
+        h2[k] = round_bf16(a > 0.0f ? a : 0.0f);
+    }
+#pragma unroll
+    for (int c = 0; c < kSmOut; ++c) {
+        float a = P[kSmB3 + c];
+#pragma unroll
+        for (int m = 0; m < kSmHidden; ++m)
+            a = __builtin_fmaf(P[kSmW3 + kSmHidden * c + m], h2[m], a);
+        o[c] = a;
+    }
+}
+
+__device__ __forceinline__ float2 sm_outputs(const float o[kSmOut], float vs)
+{
+    const float w = 0.5f * (o[0] + sqrtf(o[0] * o[0] + 4.0f));
+    const float s = 0.5f + 0.5f * (o[1] / sqrtf(1.0f + o[1] * o[1]));
+    return make_float2(w, vs * (1.0f + 7.0f * s));
+}
+
+constexpr int kMapThreads = 256;
+
+__global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs, const float *__restrict__ params,
+                                                              float2 *__restrict__ out)
+{
+    __shared__ float P[kSmParams];
+    for (int k = (int)threadIdx.x; k < kSmParams; k += kMapThreads)
+        P[k] = params[k];
+    __syncthreads();
+    const int n = v.width * v.height;
+    for (int p = (int)(blockIdx.x * kMapThreads + threadIdx.x); p < n; p += (int)(gridDim.x * kMapThreads)) {
+        const int j = p / v.width, i = p - j * v.width;
+        const float d = v.depth[p];
+        if (!sm_valid(d, v.d_max)) {
+            out[p] = make_float2(0.0f, 0.0f);
+            continue;
+        }
+        float x[kSmIn], h1[kSmHidden], h2[kSmHidden], o[kSmOut];
+        sm_inputs(v, i, j, d, x);
+        sm_forward(P, x, h1, h2, o);
+        out[p] = sm_outputs(o, vs);
+    }
+}
+
+// ---- training ------------------------------------------------------------
+
+constexpr int kLossThreads = 256;
+
+__global__ __launch_bounds__(kLossThreads) void sm_fuse_loss_kernel(SmLossArgs a)
+{
+    __shared__ double red[2][kLossThreads / 64];
+    double loss = 0.0, used = 0.0;
+    const long long stride = (long long)gridDim.x * kLossThreads;
+    for (long long v = (long long)blockIdx.x * kLossThreads + threadIdx.x; v < a.n_vox; v += stride) {
+        const float px = ((float)a.vox[3 * v] + 0.5f) * a.vs;
+        const float py = ((float)a.vox[3 * v + 1] + 0.5f) * a.vs;
+        const float pz = ((float)a.vox[3 * v + 2] + 0.5f) * a.vs;
+        float sw = 0.0f, swx = 0.0f, D = 0.0f, gD = 0.0f;
+        for (int stage = 0; stage < 2; ++stage) {
+            for (int f = 0; f < a.n_frames; ++f) {
+                const SmFrame &fr = a.frames[f];
+                const float xc = ((fr.R[0] * px + fr.R[1] * py) + fr.R[2] * pz) + fr.t[0];
+                const float yc = ((fr.R[3] * px + fr.R[4] * py) + fr.R[5] * pz) + fr.t[1];
+                const float zc = ((fr.R[6] * px + fr.R[7] * py) + fr.R[8] * pz) + fr.t[2];
+                if (!(zc > 0.0f))
+                    continue;
+                const float r = 1.0f / zc;
+                const float u = a.fx * (xc * r) + a.cx;
+                const float w_ = a.fy * (yc * r) + a.cy;
+                if (!(u >= 0.0f && u < (float)a.width && w_ >= 0.0f && w_ < (float)a.height))
+                    continue;
+                const size_t k = (size_t)(int)w_ * (size_t)a.width + (size_t)(int)u;
+                const float d = fr.depth[k];
+                if (!sm_valid(d, a.d_max))
+                    continue;
+                const float2 we = fr.maps[k];
+                const float dp = d - zc;
+                if (!(dp >= -we.y) || !(we.x > 0.0f))
+                    continue;
+                const float x = dp < we.y ? dp : we.y;
+                if (stage == 0) {
+                    sw += we.x;
+                    swx += we.x * x;
+                } else {
+                    atomicAdd(&fr.gw[k], gD * (x - D) / sw);
+                    if (dp > we.y)
+                        atomicAdd(&fr.ge[k], gD * we.x / sw);
+                }
+            }
+            if (stage == 0) {
+                if (!(sw > 0.0f))
+                    break;
+                D = swx / sw;
+                const float diff = D - a.target[v];
+                gD = 2.0f * diff;
+                loss += (double)diff * (double)diff;
+                used += 1.0;
+            }
+        }
+    }
+    // workgroup sums, one double atomic per workgroup and quantity
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        loss += __shfl_xor(loss, off);
+        used += __shfl_xor(used, off);
+    }
+    const int wave = (int)threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wave] = loss;
+        red[1][wave] = used;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double l = 0.0, u = 0.0;
+        for (int k = 0; k < kLossThreads / 64; ++k) {
+            l += red[0][k];
+            u += red[1][k];
+        }
+        if (u > 0.0) {
+            atomicAdd(&a.acc[0], l);
+            atomicAdd(&a.acc[1], u);
+        }
+    }
+}
+
+constexpr int kTile = 64;            // pixels per LDS tile; one wave per workgroup
+constexpr int kParamsPerLane = (kSmParams + 63) / 64;
+
+__global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
+{
+    __shared__ float P[kSmParams];
+    __shared__ float X[kTile][kSmIn + 1];
+    __shared__ float H1[kTile][kSmHidden + 1], H2[kTile][kSmHidden + 1];
+    __shared__ float G1[kTile][kSmHidden + 1], G2[kTile][kSmHidden + 1];
+    __shared__ float GO[kTile][kSmOut];
+    const int lane = (int)threadIdx.x;
+    for (int k = lane; k < kSmParams; k += 64)
+        P[k] = a.params[k];
+    const double n_used = a.acc[1];
+    const float scale = n_used > 0.0 ? (float)(1.0 / n_used) : 0.0f;
+    float acc[kParamsPerLane];
+#pragma unroll
+    for (int r = 0; r < kParamsPerLane; ++r)
+        acc[r] = 0.0f;
+    __syncthreads();
+    const long long per_frame = (long long)a.width * a.height;
+    const long long total = per_frame * a.n_frames;
+    for (long long base = (long long)blockIdx.x * kTile; base < total; base += (long long)gridDim.x * kTile) {
+        const long long p = base + lane;
+        float x[kSmIn], h1[kSmHidden], h2[kSmHidden], o[kSmOut];
+        float go0 = 0.0f, go1 = 0.0f;
+        bool active = false;
+        if (p < total) {
+            const int f = (int)(p / per_frame);
+            const int k = (int)(p - (long long)f * per_frame);
+            const float gw = a.gw[p], ge = a.ge[p];
+            const SmView v = a.views[f];
+            const float d = v.depth[k];
+            if ((gw != 0.0f || ge != 0.0f) && sm_valid(d, v.d_max)) {
+                const int j = k / v.width, i = k - j * v.width;
+                sm_inputs(v, i, j, d, x);
+                sm_forward(P, x, h1, h2, o);
+                go0 = scale * gw * 0.5f * (1.0f + o[0] / sqrtf(o[0] * o[0] + 4.0f));
+                const float q = 1.0f + o[1] * o[1];
+                go1 = scale * ge * a.vs * 7.0f * 0.5f / (q * sqrtf(q));
+                active = true;
+            }
+        }
+        if (!active) {
+#pragma unroll
+            for (int m = 0; m < kSmIn; ++m)
+                x[m] = 0.0f;
+#pragma unroll
+            for (int m = 0; m < kSmHidden; ++m)
+                h1[m] = h2[m] = 0.0f;
+        }
+        // back-propagation through the hidden layers (ReLU masks from the activations)
+        float g2[kSmHidden], g1[kSmHidden];
+#pragma unroll
+        for (int m = 0; m < kSmHidden; ++m) {
+            const float gh = P[kSmW3 + m] * go0 + P[kSmW3 + kSmHidden + m] * go1;
+            g2[m] = h2[m] > 0.0f ? gh : 0.0f;
+        }
+#pragma unroll 4
+        for (int m = 0; m < kSmHidden; ++m) {
+            float gh = 0.0f;
+#pragma unroll
+            for (int k2 = 0; k2 < kSmHidden; ++k2)
+                gh += P[kSmW2 + kSmHidden * k2 + m] * g2[k2];
+            g1[m] = h1[m] > 0.0f ? gh : 0.0f;
+        }
+#pragma unroll
+        for (int m = 0; m < kSmIn; ++m)
+            X[lane][m] = x[m];
+#pragma unroll
+        for (int m = 0; m < kSmHidden; ++m) {
+            H1[lane][m] = h1[m];
+            H2[lane][m] = h2[m];
+            G1[lane][m] = g1[m];
+            G2[lane][m] = g2[m];
+        }
+        GO[lane][0] = go0;
+        GO[lane][1] = go1;
+        __syncthreads();
+        // lane owns parameters q = lane + 64 r: sum over the tile's pixels
+#pragma unroll
+        for (int r = 0; r < kParamsPerLane; ++r) {
+            const int q = lane + 64 * r;
+            float s = 0.0f;
+            if (q < kSmB1) {
+                const int k2 = q / kSmIn, m = q - k2 * kSmIn;
+                for (int t = 0; t < kTile; ++t)
+                    s += G1[t][k2] * X[t][m];
+            } else if (q < kSmW2) {
+                const int k2 = q - kSmB1;
+                for (int t = 0; t < kTile; ++t)
+                    s += G1[t][k2];
+            } else if (q < kSmB2) {
+                const int k2 = (q - kSmW2) / kSmHidden, m = (q - kSmW2) - k2 * kSmHidden;
+                for (int t = 0; t < kTile; ++t)
+                    s += G2[t][k2] * H1[t][m];
+            } else if (q < kSmW3) {
+                const int k2 = q - kSmB2;
+                for (int t = 0; t < kTile; ++t)
+                    s += G2[t][k2];
+            } else if (q < kSmB3) {
+                const int c = (q - kSmW3) / kSmHidden, m = (q - kSmW3) - c * kSmHidden;
+                for (int t = 0; t < kTile; ++t)
+                    s += GO[t][c] * H2[t][m];
+            } else if (q < kSmParams) {
+                const int c = q - kSmB3;
+                for (int t = 0; t < kTile; ++t)
+                    s += GO[t][c];
+            }
+            acc[r] += s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < kParamsPerLane; ++r) {
+        const int q = lane + 64 * r;
+        if (q < kSmParams && acc[r] != 0.0f)
+            atomicAdd(&a.grad[q], acc[r]);
+    }
+}
+
+__global__ void sm_fill_kernel(float *p, long long n, float v)
+{
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+        p[k] = v;
+}
+
+__global__ void sm_zero_acc_kernel(double *acc)
+{
+    if (threadIdx.x < 2)
+        acc[threadIdx.x] = 0.0;
+}
+
+__global__ void sm_adam_kernel(float *master, float *m1, float *m2, const float *grad, float *params, int n, float lr,
+                               float beta1, float beta2, float eps, float corr1, float corr2)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n)
+        return;
+    const float g = grad[k];
+    const float a = beta1 * m1[k] + (1.0f - beta1) * g;
+    const float b = beta2 * m2[k] + (1.0f - beta2) * g * g;
+    m1[k] = a;
+    m2[k] = b;
+    const float w = master[k] - lr * (a / corr1) / (sqrtf(b / corr2) + eps);
+    master[k] = w;
+    params[k] = round_bf16(w);
+}
+
+}  // namespace
+
+hipError_t launch_sm_maps(const SmView &v, float vs, const float *params, float2 *out, hipStream_t stream)
+{
+    const long long n = (long long)v.width * v.height;
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((n + kMapThreads - 1) / kMapThreads,
+                                                                                  2048));
+    hipLaunchKernelGGL(sm_maps_kernel, dim3(groups), dim3(kMapThreads), 0, stream, v, vs, params, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_fill(float *p, long long n, float value, hipStream_t stream)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const unsigned groups = (unsigned)std::min<long long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(sm_fill_kernel, dim3(groups), dim3(256), 0, stream, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_loss(const SmLossArgs &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(sm_zero_acc_kernel, dim3(1), dim3(64), 0, stream, a.acc);
+    if (a.n_vox > 0) {
+        const unsigned groups =
+            (unsigned)std::min<long long>((a.n_vox + kLossThreads - 1) / kLossThreads, 4096);
+        hipLaunchKernelGGL(sm_fuse_loss_kernel, dim3(groups), dim3(kLossThreads), 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_backward(const SmBackArgs &a, hipStream_t stream)
+{
+    const long long total = (long long)a.width * a.height * a.n_frames;
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((total + kTile - 1) / kTile, 1024));
+    hipLaunchKernelGGL(sm_backward_kernel, dim3(groups), dim3(64), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_adam(float *master, float *m1, float *m2, const float *grad, float *params, int n, float lr,
+                          float beta1, float beta2, float eps, int step, hipStream_t stream)
+{
+    const float corr1 = 1.0f - (float)std::pow((double)beta1, (double)step);
+    const float corr2 = 1.0f - (float)std::pow((double)beta2, (double)step);
+    hipLaunchKernelGGL(sm_adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, master, m1, m2, grad,
+                       params, n, lr, beta1, beta2, eps, corr1, corr2);
+    return hipGetLastError();
+}
+
+}  // namespace tsdf

@@ -19,6 +19,26 @@ constexpr int kPartitions = 8;                      // XCDs: block ownership ban
 constexpr int kMaxChunk = 64;                       // lattice blocks culled together by one wave
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
+// Weighting functions (the tsdf_params weighting codes).
+constexpr int kWeightConstant = 0;
+constexpr int kWeightDropoff = 1;
+constexpr int kWeightLearned = 2;
+
+// Learned sensor model: a per-pixel perceptron 27 -> 32 -> 32 -> 2 with
+// parameters W1[32][27], b1[32], W2[32][32], b2[32], W3[2][32], b3[2].
+constexpr int kSmIn = 27, kSmHidden = 32, kSmOut = 2;
+constexpr int kSmW1 = 0, kSmB1 = kSmW1 + kSmHidden * kSmIn, kSmW2 = kSmB1 + kSmHidden,
+              kSmB2 = kSmW2 + kSmHidden * kSmHidden, kSmW3 = kSmB2 + kSmHidden, kSmB3 = kSmW3 + kSmOut * kSmHidden,
+              kSmParams = kSmB3 + kSmOut;
+
+// Depth footprint pyramid: per view, the largest valid measurement of every
+// tile of 8, 16, 32 and 64 pixels; images up to kTileMaxSide pixels a side.
+constexpr int kTileLevels = 4;
+constexpr int kTileBaseShift = 3;                    // level l tiles are 8 << l pixels wide
+constexpr int kTileMaxSide = 4096;
+constexpr long long kTileFloatsPerView = 348160;     // sum over levels of (4096 / (8 << l))^2
+constexpr int kTileSuper = 64;                       // pixels a side of one pyramid workgroup
+
 // Counter words, one hot counter per 128-byte line so that atomics on
 // different counters never share a line.
 enum Counter : int {
@@ -84,6 +104,13 @@ struct CameraView {
     int full_circle;        // columns wrap around
     float origin[3];        // sensor centre in the world (range culling)
     float cos_pol_start, cos_pol_end;   // polar band edges (cone culling)
+    // learned sensor model: per-pixel (weight, truncation) pairs (pinhole views)
+    const float2 *sm_maps;
+    // depth footprint pyramid of this view (nullptr: no footprint culling)
+    float *tiles;
+    int tile_cols[kTileLevels];         // tiles per row at each level
+    int tile_rows[kTileLevels];
+    int tile_off[kTileLevels];          // float offset of each level from `tiles`
 };
 
 // Per-map constants in binary32.
@@ -161,6 +188,9 @@ hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long 
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
                               hipStream_t stream);
+// Builds the footprint pyramids of the views whose `tiles` is set.
+hipError_t launch_footprint_tiles(const ViewsArgs &va, hipStream_t stream);
+hipError_t launch_footprint_tiles_dev(const ViewsArgs *va_dev, hipStream_t stream);
 hipError_t launch_gather_touched(const DeviceMap &dm, int sub, long long n, int32_t *xyz, hipStream_t stream);
 hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n,
                      hipStream_t stream);

@@ -417,6 +417,79 @@ def box_room_sequence(voxel_size: float, n_frames: int = 300) -> Workload:
                     MapParams(voxel_size, 4.0, "constant"))
 
 
+def depth_edge_range(depth: np.ndarray) -> np.ndarray:
+    """max - min of the valid depths in each pixel's 3x3 neighbourhood (0 where
+    fewer than two are valid)."""
+    d = np.asarray(depth, dtype=np.float64)
+    valid = d > 0
+    big = np.where(valid, d, -np.inf)
+    small = np.where(valid, d, np.inf)
+    H, W = d.shape
+    pad_hi = np.pad(big, 1, constant_values=-np.inf)
+    pad_lo = np.pad(small, 1, constant_values=np.inf)
+    mx = np.full((H, W), -np.inf)
+    mn = np.full((H, W), np.inf)
+    for dj in range(3):
+        for di in range(3):
+            mx = np.maximum(mx, pad_hi[dj:dj + H, di:di + W])
+            mn = np.minimum(mn, pad_lo[dj:dj + H, di:di + W])
+    r = mx - mn
+    return np.where(np.isfinite(r), r, 0.0), np.where(np.isfinite(mn), mn, 0.0), np.where(np.isfinite(mx), mx, 0.0)
+
+
+def add_flying_pixels(noisy: np.ndarray, clean: np.ndarray, rng: np.random.Generator, frac: float = 0.03,
+                      edge_range: float = 0.1) -> np.ndarray:
+    """Flying pixels at depth edges: pixels whose 3x3 neighbourhood (in the clean
+    render) spans more than `edge_range` metres are candidates; `frac` of all
+    pixels (at most every candidate) take a value between the neighbourhood's
+    nearest and farthest depth, d_fg + u (d_bg - d_fg) with u ~ U(0, 1)."""
+    r, mn, mx = depth_edge_range(clean)
+    cand = np.flatnonzero((r > edge_range) & (np.asarray(clean) > 0))
+    k = min(len(cand), int(round(frac * clean.size)))
+    out = np.array(noisy, dtype=np.float32, copy=True)
+    if k == 0:
+        return out
+    pick = rng.choice(cand, size=k, replace=False)
+    u = rng.uniform(0.0, 1.0, k)
+    flat = out.reshape(-1)
+    flat[pick] = (mn.reshape(-1)[pick] + u * (mx.reshape(-1)[pick] - mn.reshape(-1)[pick])).astype(np.float32)
+    return out
+
+
+@dataclass
+class LearningRoom:
+    """One room of the learned-sensor-model data: clean renders and their
+    corrupted versions (axial noise sigma = 0.0012 z^2, then flying pixels)
+    from the same poses."""
+    seed: int
+    camera: PinholeCamera
+    scene: Scene
+    poses: List[np.ndarray]
+
+    def frames(self, device: str = "cpu", count: Optional[int] = None):
+        n = len(self.poses) if count is None else min(count, len(self.poses))
+        rng = np.random.default_rng(self.seed + 20000)
+        clean, noisy = [], []
+        for k in range(n):
+            c = render_depth(self.scene, self.camera, self.poses[k], device=device)
+            nz = add_depth_noise(c, rng, dropout=0.0)
+            noisy.append(add_flying_pixels(nz, c, rng))
+            clean.append(c)
+        return clean, noisy
+
+
+def learning_room(seed: int, n_frames: int = 100, camera: Optional[PinholeCamera] = None) -> LearningRoom:
+    """The cluttered-room generator (8 x 6 x 3 m, 40 spheres, 20 boxes, spline
+    path at 0.5 m/s and 30 fps) with scene seed `seed` and path seed
+    seed + 10000.  Rooms 1000-1019 are the training set."""
+    camera = camera or CAM_640
+    room = (8.0, 6.0, 3.0)
+    poses = spline_trajectory(room, n_frames, np.random.default_rng(seed + 10000), margin=1.0)
+    spheres, boxes = random_objects(room, np.random.default_rng(seed), 40, 20, _path_positions(poses),
+                                    clearance=0.6)
+    return LearningRoom(seed, camera, Scene(room=room, spheres=spheres, boxes=boxes), poses)
+
+
 def random_frame(cam: PinholeCamera, rng: np.random.Generator, lo: float = 0.3, hi: float = 6.0,
                  invalid_frac: float = 0.1) -> np.ndarray:
     """Unstructured depth (uniform in [lo, hi]) with a fraction of invalid

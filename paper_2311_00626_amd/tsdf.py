@@ -18,7 +18,9 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libtsdf.so")
 
 OK, EINVAL, ENOMEM, EFULL, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
-WEIGHTINGS = {"constant": 0, "linear_dropoff": 1}
+WEIGHTINGS = {"constant": 0, "linear_dropoff": 1, "learned": 2}
+SM_NPARAM = 2018
+SM_MAX_FRAMES = 16
 STORAGES = {"fp32": 0, "fp16": 1}
 
 
@@ -58,10 +60,11 @@ def lidar_struct(lidar) -> tsdf_lidar_model:
 
 
 MAX_VIEWS = 16
+FOOTPRINT = {"auto": 0, "never": 1, "always": 2}
 
 
 class tsdf_launch_config(C.Structure):
-    _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("reserved", C.c_int)]
+    _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("footprint", C.c_int)]
 
 
 class tsdf_params(C.Structure):
@@ -98,12 +101,19 @@ def _load() -> C.CDLL:
     lib.tsdf_step_create.argtypes = [vp, i, C.POINTER(vp)]
     lib.tsdf_step_run.argtypes = [vp, C.POINTER(tsdf_depth_view), i, vp]
     lib.tsdf_step_destroy.argtypes = [vp]
+    lib.tsdf_set_sensor_model.argtypes = [vp, vp]
+    lib.tsdf_sensor_maps.argtypes = [vp, i, i, vp, C.c_float, C.c_float, vp, vp, vp]
+    lib.tsdf_sm_trainer_create.argtypes = [i, i, i, C.POINTER(vp)]
+    lib.tsdf_sm_trainer_destroy.argtypes = [vp]
+    lib.tsdf_sm_loss_grad.argtypes = [vp, vp, i, vp, vp, vp, C.c_float, C.c_float, ll, vp, vp, vp, vp, vp]
+    lib.tsdf_sm_adam.argtypes = [vp, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float, i, vp]
     for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "integrate_depth_views",
                  "integrate_range",
                  "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
                  "tsdf_profile_read", "tsdf_set_launch_config", "tsdf_step_create", "tsdf_step_run",
-                 "tsdf_step_destroy"):
+                 "tsdf_step_destroy", "tsdf_set_sensor_model", "tsdf_sensor_maps", "tsdf_sm_trainer_create",
+                 "tsdf_sm_trainer_destroy", "tsdf_sm_loss_grad", "tsdf_sm_adam"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -114,7 +124,8 @@ EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map",
             "integrate_depth_views", "integrate_range",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
             "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config",
-            "tsdf_step_create", "tsdf_step_run", "tsdf_step_destroy")
+            "tsdf_step_create", "tsdf_step_run", "tsdf_step_destroy", "tsdf_set_sensor_model", "tsdf_sensor_maps",
+            "tsdf_sm_trainer_create", "tsdf_sm_trainer_destroy", "tsdf_sm_loss_grad", "tsdf_sm_adam")
 
 
 def strerror(status: int) -> str:
@@ -241,6 +252,11 @@ class TsdfMap:
         _check(lib.integrate_depth_views(self._h, arr, n, C.c_void_p(_stream_ptr(stream))),
                "integrate_depth_views")
 
+    def set_sensor_model(self, params) -> None:
+        """Parameters of the learned sensor model (TSDF_SM_NPARAM bfloat16 values)."""
+        h = _host_f32(params.detach().cpu().numpy() if isinstance(params, torch.Tensor) else params, SM_NPARAM)
+        _check(lib.tsdf_set_sensor_model(self._h, h.ctypes.data), "tsdf_set_sensor_model")
+
     def step(self, with_spherical: bool = False) -> "TsdfStep":
         """A graph-replayed batched step on this map (see TsdfStep)."""
         return TsdfStep(self, with_spherical)
@@ -302,9 +318,11 @@ class TsdfMap:
         torch.cuda.synchronize()
         return b.cpu().numpy(), d.cpu().numpy(), w.cpu().numpy()
 
-    def set_launch_config(self, max_groups: int = 0, partitions: int = 0, chunk: int = 0) -> None:
-        """Launch shape of the integration kernels (0 = automatic)."""
-        c = tsdf_launch_config(max_groups, partitions, chunk, 0)
+    def set_launch_config(self, max_groups: int = 0, partitions: int = 0, chunk: int = 0,
+                          footprint: str = "auto") -> None:
+        """Launch shape of the integration kernels (0 = automatic); footprint
+        culling "auto", "never" or "always"."""
+        c = tsdf_launch_config(max_groups, partitions, chunk, FOOTPRINT[footprint])
         _check(lib.tsdf_set_launch_config(self._h, C.byref(c)), "tsdf_set_launch_config")
 
     # -- kernel timing -------------------------------------------------------
@@ -343,3 +361,74 @@ class TsdfStep:
             self.close()
         except Exception:
             pass
+
+
+def _dev_f32(t: torch.Tensor, name: str, n: Optional[int] = None) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must hold {n} values")
+    return t
+
+
+def sensor_maps(depth: torch.Tensor, K, max_range: float, voxel_size: float, params: torch.Tensor,
+                stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """(H, W, 2) per-pixel (weight, truncation) of the learned sensor model."""
+    _dev_f32(depth, "depth")
+    _dev_f32(params, "params", SM_NPARAM)
+    H, W = depth.shape
+    out = torch.empty((H, W, 2), dtype=torch.float32, device=depth.device)
+    Kh = _host_f32(K, 4)
+    _check(lib.tsdf_sensor_maps(depth.data_ptr(), W, H, Kh.ctypes.data, max_range, voxel_size, params.data_ptr(),
+                                out.data_ptr(), C.c_void_p(_stream_ptr(stream))), "tsdf_sensor_maps")
+    return out
+
+
+class SmTrainer:
+    """Work buffers for loss/gradient evaluations of the learned sensor model
+    on windows of up to max_frames depth images of one size."""
+
+    def __init__(self, width: int, height: int, max_frames: int = SM_MAX_FRAMES):
+        h = C.c_void_p()
+        _check(lib.tsdf_sm_trainer_create(width, height, max_frames, C.byref(h)), "tsdf_sm_trainer_create")
+        self._h = h
+        self.width, self.height, self.max_frames = width, height, max_frames
+
+    def loss_grad(self, params: torch.Tensor, depths: Sequence[torch.Tensor], K, poses, voxel_size: float,
+                  max_range: float, vox: torch.Tensor, target: torch.Tensor, grad: torch.Tensor,
+                  want_loss: bool = True, stream=None):
+        """Writes dL/dparams into grad; returns (L, voxels reached) if want_loss."""
+        _dev_f32(params, "params", SM_NPARAM)
+        _dev_f32(grad, "grad", SM_NPARAM)
+        _dev_f32(target, "target")
+        if not (vox.is_cuda and vox.dtype == torch.int32 and vox.is_contiguous() and vox.numel() == 3 * target.numel()):
+            raise ValueError("vox must be a contiguous int32 CUDA tensor of shape (n, 3)")
+        n = len(depths)
+        ptrs = (C.c_void_p * n)(*[_dev_f32(d, "depth").data_ptr() for d in depths])
+        T = np.ascontiguousarray(np.stack([_host_f32(t, 16) for t in poses]).reshape(-1))
+        Kh = _host_f32(K, 4)
+        out = (C.c_double * 2)()
+        _check(lib.tsdf_sm_loss_grad(self._h, params.data_ptr(), n, ptrs, Kh.ctypes.data, T.ctypes.data, voxel_size,
+                                     max_range, target.numel(), vox.data_ptr(), target.data_ptr(), grad.data_ptr(),
+                                     out if want_loss else None, C.c_void_p(_stream_ptr(stream))),
+               "tsdf_sm_loss_grad")
+        return (out[0], int(out[1])) if want_loss else None
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib.tsdf_sm_trainer_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sm_adam(master, m1, m2, grad, params, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+            eps: float = 1e-8, stream=None) -> None:
+    for t, name in ((master, "master"), (m1, "m1"), (m2, "m2"), (grad, "grad"), (params, "params")):
+        _dev_f32(t, name, SM_NPARAM)
+    _check(lib.tsdf_sm_adam(master.data_ptr(), m1.data_ptr(), m2.data_ptr(), grad.data_ptr(), params.data_ptr(),
+                            SM_NPARAM, lr, beta1, beta2, eps, step, C.c_void_p(_stream_ptr(stream))), "tsdf_sm_adam")

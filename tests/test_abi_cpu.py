@@ -90,3 +90,23 @@ def test_null_map_rejected(t):
     assert t.lib.tsdf_step_create(None, 0, C.byref(step)) == t.EINVAL and not step.value
     assert t.lib.tsdf_step_run(None, views, 1, None) == t.EINVAL
     assert t.lib.tsdf_step_destroy(None) == t.OK
+    P = (C.c_float * 2018)()
+    assert t.lib.tsdf_set_sensor_model(None, P) == t.EINVAL
+
+
+def test_sensor_model_arguments_rejected_before_device(t):
+    K = (C.c_float * 4)(1, 1, 0, 0)
+    tr = C.c_void_p()
+    for w, h, n in ((0, 10, 1), (10, 0, 1), (10, 10, 0), (10, 10, 17)):
+        assert t.lib.tsdf_sm_trainer_create(w, h, n, C.byref(tr)) == t.EINVAL and not tr.value
+    assert t.lib.tsdf_sm_trainer_create(10, 10, 1, None) == t.EINVAL
+    assert t.lib.tsdf_sm_trainer_destroy(None) == t.OK
+    assert t.lib.tsdf_sm_loss_grad(None, None, 1, None, K, None, 0.05, 5.0, 0, None, None, None, None, None) == t.EINVAL
+    assert t.lib.tsdf_sensor_maps(None, 4, 4, K, 5.0, 0.05, None, None, None) == t.EINVAL
+    assert t.lib.tsdf_sensor_maps(C.c_void_p(16), 0, 4, K, 5.0, 0.05, C.c_void_p(16), C.c_void_p(16), None) == t.EINVAL
+    assert t.lib.tsdf_sm_adam(None, None, None, None, None, 2018, 1e-3, 0.9, 0.999, 1e-8, 1, None) == t.EINVAL
+    # learned weighting is a valid map parameter, other codes are not
+    q = t.default_params(0.05, 4.0)
+    q.weighting = 3
+    h = C.c_void_p()
+    assert t.lib.create_map_ex(C.byref(q), C.byref(h)) == t.EINVAL

@@ -13,15 +13,15 @@ class FakeMap:
         self.cfg = None
         self.n = 0
 
-    def set_launch_config(self, g, p, c):
-        self.cfg = (g, p, c)
+    def set_launch_config(self, g, p, c, f="auto"):
+        self.cfg = (g, p, c, f)
 
     def profile(self, on):
         self.n = 0
 
     def profile_read(self):
-        g, p, c = self.cfg
-        ms = 1.0 + abs(g - 1024) / 1024 + (p == 8) * 0.5 + abs(c - 4) * 0.01
+        g, p, c, f = self.cfg
+        ms = 1.0 + abs(g - 1024) / 1024 + (p == 8) * 0.5 + abs(c - 4) * 0.01 + (f == "never") * 0.2
         return ms * self.n, self.n
 
     def status(self):
@@ -33,7 +33,8 @@ class FakeMap:
 
 def test_candidates_cover_the_grid():
     c = at.default_candidates()
-    assert len(c) == len(at.GROUPS) * len(at.CHUNKS) * len(at.PARTITIONS) and len(set(c)) == len(c)
+    assert len(c) == len(at.GROUPS) * len(at.CHUNKS) * len(at.PARTITIONS) * len(at.FOOTPRINTS)
+    assert len(set(c)) == len(c)
     assert all(x.partitions in (1, 8) and 0 <= x.chunk <= 64 for x in c)
 
 
@@ -46,10 +47,11 @@ def test_tune_picks_fastest_and_caches(tmp_path, monkeypatch):
         m.n += 1
 
     choice, trials = at.tune("w1", FakeMap, run_step, range(6), cache_path=cache, device="devA")
-    assert choice == at.LaunchConfig(1024, 1, 4)
+    assert choice == at.LaunchConfig(1024, 1, 4, "always")
     assert [t.kernel_ms_per_launch for t in trials] == sorted(t.kernel_ms_per_launch for t in trials)
     assert trials[0].launches == 4
-    assert json.load(open(cache)) == {"devA|w1": {"max_groups": 1024, "partitions": 1, "chunk": 4}}
+    assert json.load(open(cache)) == {"devA|w1": {"max_groups": 1024, "partitions": 1, "chunk": 4,
+                                                  "footprint": "always"}}
     # memoised, then from the file in a fresh process (memo cleared): no trials run
     FakeMap.log.clear()
     assert at.tune("w1", FakeMap, run_step, range(6), cache_path=cache, device="devA") == (choice, [])

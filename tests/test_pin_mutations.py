@@ -1,6 +1,7 @@
 """The pins must catch plausible mistakes in the oracle.  Each case plants one
 mistake in a temporary copy of the oracle sources (on the CPU), builds it, and
-runs the pin suites (pinhole and LiDAR) against it; the suite has to fail."""
+runs the pin suites (pinhole, LiDAR and learned sensor model) against it; the
+suite has to fail."""
 import os
 import shutil
 import subprocess
@@ -28,7 +29,8 @@ MUTANTS = [
     ("fx_fy_swapped", "oracle_impl.h", "REAL u = f->fx * (xc * r) + f->cx;",
      "REAL u = f->fy * (xc * r) + f->cx;"),
     ("image_indexed_transposed", "oracle_impl.h",
-     "f->depth[(size_t)j * (size_t)f->width + (size_t)i]", "f->depth[(size_t)i * (size_t)f->height + (size_t)j]"),
+     "const size_t idx = (size_t)j * (size_t)f->width + (size_t)i;",
+     "const size_t idx = (size_t)i * (size_t)f->height + (size_t)j;"),
     ("clamp_instead_of_skip_behind_surface", "oracle_impl.h", "if (!(dp >= -f->eps))\n        return 0;",
      "if (dp < -f->eps)\n        dp = -f->eps;"),
     ("weight_not_capped", "oracle_impl.h", "*W = s < w_max ? s : w_max;", "*W = s;"),
@@ -56,6 +58,23 @@ MUTANTS = [
     ("lidar_depth_is_z", "oracle_impl.h", "REAL dp = d - rv;", "REAL dp = d - zc;"),
     ("lidar_voxel_centre_missing_half", "oracle_impl.h",
      "one = (REAL)1;\n    REAL px = ((REAL)gx + half) * f->vs;", "one = (REAL)1;\n    REAL px = ((REAL)gx) * f->vs;"),
+    # learned sensor model
+    ("sm_relu_missing", "sensor_model_impl.h", "h1[k] = ora_round_bf16(a > 0.0f ? a : 0.0f);",
+     "h1[k] = ora_round_bf16(a);"),
+    ("sm_w1_transposed", "sensor_model_impl.h", "a = fmaf(P[SM_W1 + SM_IN * k + m], x[m], a);",
+     "a = fmaf(P[SM_W1 + SM_H * m + k], x[m], a);"),
+    ("sm_weight_map_sign", "sensor_model_impl.h", "*w = 0.5f * (o[0] + sqrtf(o[0] * o[0] + 4.0f));",
+     "*w = 0.5f * (-o[0] + sqrtf(o[0] * o[0] + 4.0f));"),
+    ("sm_truncation_scale", "sensor_model_impl.h", "*e = vs * (1.0f + 7.0f * s);", "*e = vs * (1.0f + 6.0f * s);"),
+    ("sm_normal_from_wrong_ray", "sensor_model_impl.h", "const float ax = dr * rxr - dl * rxl,",
+     "const float ax = dr * rxr - dl * rxr,"),
+    ("sm_patch_not_clipped", "sensor_model_impl.h",
+     "v = q - d;\n                            v = v < -0.5f ? -0.5f : (v > 0.5f ? 0.5f : v);",
+     "v = q - d;"),
+    ("sm_gradient_sign", "sensor_model_impl.h", "gw[f * npx + k] += gD * (x - Dp) / sw;",
+     "gw[f * npx + k] += gD * (Dp - x) / sw;"),
+    ("sm_pixel_truncation_ignored", "oracle_impl.h", "REAL e = (REAL)f->eps_map[idx];", "REAL e = f->eps;"),
+    ("sm_bf16_truncates", "sensor_model_impl.h", "u += 0x7fffu + ((u >> 16) & 1u);", "u += 0u;"),
     ("beam_at_pixel_edge", "oracle_impl.h",
      "REAL uc = (theta - f->az_start) * f->alpha - half;", "REAL uc = (theta - f->az_start) * f->alpha;"),
 ]
@@ -65,7 +84,7 @@ def run_mutant(fname, orig, mutant):
     """Builds the oracle with one planted mistake and runs the pin suites
     against it; returns (anchor count, pytest return code)."""
     with tempfile.TemporaryDirectory() as tmp:
-        for f in ("tsdf_oracle.c", "tsdf_oracle.h", "oracle_impl.h"):
+        for f in ("tsdf_oracle.c", "tsdf_oracle.h", "oracle_impl.h", "sensor_model_impl.h"):
             shutil.copy(os.path.join(ORACLE, f), tmp)
         path = os.path.join(tmp, fname)
         text = open(path).read()
@@ -78,7 +97,8 @@ def run_mutant(fname, orig, mutant):
         env = dict(os.environ, TSDF_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_lidar.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_lidar.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_sensor_model.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
         return 1, r.returncode
 
