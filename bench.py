@@ -67,19 +67,26 @@ def measured_traffic(launches_bytes: float):
     return s.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, frames_host, budget_s: float):
+def cpu_baseline(w, frames_host, budget_s: float, min_s: float = 10.0):
+    """The binary32 oracle on one thread over the sequence, each pass into a
+    fresh map, until `min_s` seconds have passed (at most `budget_s`)."""
     import oracle
-    om = oracle.OracleMap.from_params(w.params)
-    updates, n, t0 = 0, 0, time.perf_counter()
-    for d, T in zip(frames_host, w.poses):
-        updates += om.integrate(d, w.camera.K, T)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
+    updates, n, passes, t0 = 0, 0, 0, time.perf_counter()
+    while True:
+        om = oracle.OracleMap.from_params(w.params)
+        passes += 1
+        for d, T in zip(frames_host, w.poses):
+            updates += om.integrate(d, w.camera.K, T)
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        del om
+        if time.perf_counter() - t0 > min(min_s, budget_s):
             break
     dt = time.perf_counter() - t0
     return {"value": updates / dt, "unit": "voxel updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} frames of the 300-frame sequence, binary32 oracle, one thread, "
-                      f"{dt:.1f} s, {n / dt:.1f} frames/s"}
+            "sample": f"{n} frames ({passes} pass(es) over the 300-frame sequence, each into a fresh map), "
+                      f"binary32 oracle, one thread, {dt:.1f} s, {n / dt:.1f} frames/s"}
 
 
 def counters(m):

@@ -428,6 +428,11 @@ hipError_t ensure_sm_maps(tsdf_map *m, long long pixels)
     if (m->sm_maps && m->sm_slot >= pixels)
         return hipSuccess;
     long long slot = std::max<long long>(pixels, 640ll * 480ll);
+    if (m->sm_maps) {
+        hipError_t e = hipDeviceSynchronize();    // earlier launches may still read the old maps
+        if (e != hipSuccess)
+            return e;
+    }
     (void)hipFree(m->sm_maps);
     m->sm_maps = nullptr;
     m->sm_slot = 0;

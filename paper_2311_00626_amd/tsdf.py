@@ -404,7 +404,14 @@ class SmTrainer:
         if not (vox.is_cuda and vox.dtype == torch.int32 and vox.is_contiguous() and vox.numel() == 3 * target.numel()):
             raise ValueError("vox must be a contiguous int32 CUDA tensor of shape (n, 3)")
         n = len(depths)
-        ptrs = (C.c_void_p * n)(*[_dev_f32(d, "depth").data_ptr() for d in depths])
+        if not 1 <= n <= self.max_frames:
+            raise ValueError(f"need 1..{self.max_frames} frames")
+        for d in depths:
+            if tuple(_dev_f32(d, "depth").shape) != (self.height, self.width):
+                raise ValueError(f"depth must be ({self.height}, {self.width})")
+        if len(poses) != n:
+            raise ValueError("one pose per frame")
+        ptrs = (C.c_void_p * n)(*[d.data_ptr() for d in depths])
         T = np.ascontiguousarray(np.stack([_host_f32(t, 16) for t in poses]).reshape(-1))
         Kh = _host_f32(K, 4)
         out = (C.c_double * 2)()
