@@ -64,6 +64,19 @@ extern "C" {
 #define TSDF_WEIGHT_LEARNED 2         /* per-pixel weight and truncation from the learned sensor
                                          model (tsdf_set_sensor_model); pinhole views only */
 
+/* Allocation.  TSDF_ALLOC_EXACT: a frame allocates exactly the blocks in
+ * which it updates at least one voxel.  TSDF_ALLOC_RAY_WALK: the paper's
+ * literal rule (§IV-B: blocks in view are found by ray tracing through the
+ * block grid, Amanatides & Woo): the blocks entered by the ray from the camera
+ * through each valid pixel's centre, from depth 0 to min(d + epsilon,
+ * max_range), are allocated whether or not a voxel of theirs is updated, and
+ * voxels are updated only inside them (ties step x, then y, then z; a block
+ * boundary exactly at the end depth is crossed).  The touched list is then the
+ * visited set.  Ray-walk maps accept integrate_depth only (TSDF_EINVAL for
+ * range images, batches and graph steps). */
+#define TSDF_ALLOC_EXACT 0
+#define TSDF_ALLOC_RAY_WALK 1
+
 #define TSDF_STORAGE_FP32 0   /* (distance, weight) as two binary32: 8 B per voxel, 4 KiB per block */
 #define TSDF_STORAGE_FP16 1   /* two binary16, rounded to nearest-even after each binary32 update:
                                  4 B per voxel, 2 KiB per block */
@@ -79,6 +92,8 @@ typedef struct {
     int storage;               /* TSDF_STORAGE_*; the update arithmetic is binary32 either way */
     long long block_capacity;  /* number of 8^3-voxel blocks the pool holds, >= 1 */
     long long hash_capacity;   /* hash slots; 0 = smallest power of two >= 2 * block_capacity */
+    int allocation;            /* TSDF_ALLOC_*: which blocks a frame allocates */
+    int reserved;              /* 0 */
 } tsdf_params;
 
 /* Fills *p with the defaults: max_weight 100, max_range 5 m, constant weight,
@@ -229,7 +244,8 @@ TSDF_API const char *tsdf_strerror(int status);
  *               multiple of 8), 1 .. 65536;
  *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
  *               each XCD reads about 1/8 of every depth image;
- *   chunk       lattice blocks a wave culls per pass, 1 .. 64;
+ *   chunk       lattice blocks a workgroup culls per pass, in units of 64, 1 .. 8
+ *               (automatic: about one pass per workgroup);
  *   footprint   footprint culling: a pre-pass reduces every view to the
  *               largest valid measurement per 8/16/32/64-pixel tile, and a
  *               block is skipped when its nearest point lies beyond the

@@ -63,6 +63,8 @@ def _load():
     lib.ora_dense_integrate.restype = C.c_longlong
     lib.ora_dense_integrate.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int,
                                         f32p, C.c_int, C.c_int, f32p, f32p, i32p, i32p, f64p, f64p]
+    lib.ora_integrate_depth_dda.restype = C.c_longlong
+    lib.ora_integrate_depth_dda.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
     lib.ora_round_bf16.restype = C.c_float
     lib.ora_round_bf16.argtypes = [C.c_float]
     lib.ora_sm_features.restype = None
@@ -135,6 +137,15 @@ class OracleMap:
         n = _lib.ora_integrate_range(self._h, rng, W, H, _f32(lidar.params(), 6), _f32(T_world_sensor, 16))
         if n < 0:
             raise ValueError("oracle rejected the range image")
+        return int(n)
+
+    def integrate_dda(self, depth: np.ndarray, K, T_world_cam) -> int:
+        """One pinhole frame with ray-DDA allocation (blocks along pixel rays)."""
+        depth = _f32(depth)
+        H, W = depth.shape
+        n = _lib.ora_integrate_depth_dda(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16))
+        if n < 0:
+            raise ValueError("oracle rejected the frame")
         return int(n)
 
     def integrate_learned(self, depth: np.ndarray, K, T_world_cam, w_map, eps_map) -> int:

@@ -343,6 +343,120 @@ static long long FN(integrate_learned)(ora_map *m, const float *depth, int width
     return FN(integrate_prepared)(m, &f, K, NULL, T);
 }
 
+/* Paper-literal allocation (§IV-B: the blocks in view are found by ray
+ * tracing through the block grid, Amanatides & Woo): for every valid pixel,
+ * the ray from the camera centre through the pixel centre is walked through
+ * the grid of blocks (edge 8 vs) from depth 0 to min(d + epsilon, max range)
+ * (depth along the optical axis; the ray direction has unit camera z).  A
+ * block is visited when the walk enters it; at a tie the walk steps x, then
+ * y, then z; a boundary exactly at the end depth is crossed.  Writes the
+ * packed keys of the visited blocks (with repeats) to *keys and returns
+ * their number, or -1 when out of memory. */
+static long long FN(dda_keys)(const FN(frame) *f, const float T[16], uint64_t **keys)
+{
+    const REAL half = (REAL)0.5;
+    const REAL B = (REAL)8 * f->vs;
+    const REAL o[3] = {(REAL)T[3], (REAL)T[7], (REAL)T[11]};
+    long long n = 0, cap = 1 << 16;
+    uint64_t *out = (uint64_t *)malloc((size_t)cap * sizeof(uint64_t));
+    if (!out)
+        return -1;
+    for (int j = 0; j < f->height; ++j)
+        for (int i = 0; i < f->width; ++i) {
+            const REAL d = (REAL)f->depth[(size_t)j * (size_t)f->width + (size_t)i];
+            if (!(d > 0 && d <= f->d_max))
+                continue;
+            const REAL a = (((REAL)i + half) - f->cx) / f->fx;
+            const REAL b = (((REAL)j + half) - f->cy) / f->fy;
+            REAL dir[3], tmax[3], tdel[3];
+            int32_t c[3], step[3];
+            REAL te = d + f->eps;
+            if (!(te <= f->d_max))
+                te = f->d_max;
+            for (int k = 0; k < 3; ++k) {
+                dir[k] = ((REAL)T[4 * k] * a + (REAL)T[4 * k + 1] * b) + (REAL)T[4 * k + 2];
+                c[k] = (int32_t)FLOOR(o[k] / B);
+                if (dir[k] > 0) {
+                    step[k] = 1;
+                    tmax[k] = ((REAL)(c[k] + 1) * B - o[k]) / dir[k];
+                    tdel[k] = B / dir[k];
+                } else if (dir[k] < 0) {
+                    step[k] = -1;
+                    tmax[k] = ((REAL)c[k] * B - o[k]) / dir[k];
+                    tdel[k] = B / -dir[k];
+                } else {
+                    step[k] = 0;
+                    tmax[k] = (REAL)INFINITY;
+                    tdel[k] = (REAL)INFINITY;
+                }
+            }
+            for (int it = 0; it < (1 << 16); ++it) {
+                if (n == cap) {
+                    cap *= 2;
+                    uint64_t *g = (uint64_t *)realloc(out, (size_t)cap * sizeof(uint64_t));
+                    if (!g) {
+                        free(out);
+                        return -1;
+                    }
+                    out = g;
+                }
+                out[n++] = ((uint64_t)(uint32_t)(c[0] + (1 << 20)) << 42) |
+                           ((uint64_t)(uint32_t)(c[1] + (1 << 20)) << 21) | (uint64_t)(uint32_t)(c[2] + (1 << 20));
+                const int ax = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
+                if (!(tmax[ax] <= te))
+                    break;
+                c[ax] += step[ax];
+                tmax[ax] += tdel[ax];
+            }
+        }
+    *keys = out;
+    return n;
+}
+
+static long long FN(integrate_dda)(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                   const float T[16])
+{
+    FN(frame) f;
+    FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    m->n_touched = 0;
+    uint64_t *keys = 0;
+    long long nk = FN(dda_keys)(&f, T, &keys);
+    if (nk < 0)
+        return -1;
+    qsort(keys, (size_t)nk, sizeof(uint64_t), key_cmp);
+    long long updates = 0;
+    REAL xs[512], ws[512];
+    unsigned char hit[512];
+    for (long long q = 0; q < nk; ++q) {
+        if (q > 0 && keys[q] == keys[q - 1])
+            continue;
+        const int32_t bx = (int32_t)((keys[q] >> 42) & 0x1FFFFF) - (1 << 20);
+        const int32_t by = (int32_t)((keys[q] >> 21) & 0x1FFFFF) - (1 << 20);
+        const int32_t bz = (int32_t)(keys[q] & 0x1FFFFF) - (1 << 20);
+        for (int k = 0; k < 512; ++k)
+            hit[k] = (unsigned char)FN(voxel_measure)(&f, 8 * bx + (k & 7), 8 * by + ((k >> 3) & 7),
+                                                      8 * bz + (k >> 6), &xs[k], &ws[k]);
+        long long b = map_find_or_insert(m, bx, by, bz);
+        if (b < 0 || touched_push(m, b) != 0) {
+            free(keys);
+            return -1;
+        }
+        REAL *D = FN(dist_ptr)(m) + 512 * b;
+        REAL *W = FN(weight_ptr)(m) + 512 * b;
+        for (int k = 0; k < 512; ++k)
+            if (hit[k]) {
+                FN(voxel_fuse)(&D[k], &W[k], xs[k], ws[k], f.w_max);
+                if (m->storage16) {
+                    D[k] = (REAL)ora_round_binary16((float)D[k]);
+                    W[k] = (REAL)ora_round_binary16((float)W[k]);
+                }
+                ++updates;
+            }
+    }
+    free(keys);
+    return updates;
+}
+
 static long long FN(integrate_prepared)(ora_map *m, FN(frame) *fp, const float K[4], const float *model,
                                         const float T[16])
 {

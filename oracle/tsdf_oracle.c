@@ -197,6 +197,12 @@ float ora_atan2_f32(float y, float x)
     return y < 0.0f ? -a : a;
 }
 
+static int key_cmp(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
 #define REAL float
 #define SFX _f32
 #define SQRT sqrtf
@@ -284,6 +290,15 @@ long long ora_integrate_depth(ora_map *m, const float *depth, int width, int hei
         return -1;
     return m->precision == 32 ? integrate_f32(m, depth, width, height, K, T)
                               : integrate_f64(m, depth, width, height, K, T);
+}
+
+long long ora_integrate_depth_dda(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                  const float T[16])
+{
+    if (!m || !frame_args_ok(depth, width, height, K, T))
+        return -1;
+    return m->precision == 32 ? integrate_dda_f32(m, depth, width, height, K, T)
+                              : integrate_dda_f64(m, depth, width, height, K, T);
 }
 
 long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, int height,

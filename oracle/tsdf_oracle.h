@@ -62,6 +62,14 @@ float ora_round_binary16(float x);
  * Returns the number of voxel updates, or -1 on bad arguments / no memory. */
 long long ora_integrate_depth(ora_map *m, const float *depth, int width, int height,
                               const float K[4], const float T_world_cam[16]);
+/* Same frame, with the paper-literal allocation: the blocks visited by a
+ * walk through the block grid (Amanatides & Woo) along every valid pixel's
+ * centre ray, from the camera to min(d + epsilon, max range), are allocated
+ * (even when none of their voxels is updated) and integrated; voxels of other
+ * blocks are not updated.  The touched list is the visited set. */
+long long ora_integrate_depth_dda(ora_map *m, const float *depth, int width, int height,
+                                  const float K[4], const float T_world_cam[16]);
+
 /* Same, with this frame's own max range (> 0) in place of the map's. */
 long long ora_integrate_depth_range(ora_map *m, const float *depth, int width, int height,
                                     const float K[4], const float T_world_cam[16], float max_range);

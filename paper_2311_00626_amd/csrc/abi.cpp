@@ -30,6 +30,8 @@ struct tsdf_map {
     float *tiles = nullptr;               // footprint pyramids, kMaxViews slots (allocated on first use)
     float *sm_params = nullptr;           // learned sensor model parameters (kSmParams)
     float2 *sm_maps = nullptr;            // per-pixel (weight, truncation), kMaxViews slots
+    unsigned char *walk_marks = nullptr;  // ray-walk allocation: one byte per lattice entry
+    long long walk_cap = 0;
     long long sm_slot = 0;                // pixels per slot of sm_maps
     // kernel timing
     bool profiling;
@@ -74,6 +76,10 @@ bool params_valid(const tsdf_params *p)
     if (p->hash_capacity != 0 && (p->hash_capacity & (p->hash_capacity - 1)) != 0)
         return false;
     if (p->hash_capacity != 0 && p->hash_capacity < p->block_capacity)
+        return false;
+    if ((p->allocation != TSDF_ALLOC_EXACT && p->allocation != TSDF_ALLOC_RAY_WALK) || p->reserved != 0)
+        return false;
+    if (p->allocation == TSDF_ALLOC_RAY_WALK && p->weighting == TSDF_WEIGHT_LEARNED)
         return false;
     return true;
 }
@@ -124,6 +130,9 @@ void free_device(tsdf_map *m)
     (void)hipFree(m->sm_maps);
     m->sm_maps = nullptr;
     m->sm_slot = 0;
+    (void)hipFree(m->walk_marks);
+    m->walk_marks = nullptr;
+    m->walk_cap = 0;
 }
 
 void free_events(tsdf_map *m)
@@ -343,14 +352,20 @@ int schedule(const tsdf_map *m, Lattice &lat)
     const tsdf_launch_config &lc = m->launch;
     long long max_groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
     max_groups = std::max<long long>(kPartitions, max_groups / kPartitions * kPartitions);
-    const long long full_waves = max_groups * kWavesPerGroup;
     const int parts = lc.partitions > 0 ? lc.partitions : 1;
-    long long groups = (lat.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
-    groups = (groups + kPartitions - 1) / kPartitions * kPartitions;
-    groups = std::max<long long>(kPartitions, std::min<long long>(groups, max_groups));
-    const long long chunk = lc.chunk > 0 ? lc.chunk : (lat.n_lat > 4 * full_waves ? 8 : 1);
+    long long chunk = lc.chunk;
+    if (chunk <= 0) {
+        // about one chunk per workgroup: n_lat / (workgroups per band) entries, in 64s
+        const double per = (double)lat.n_lat / (double)(max_groups / parts) / 64.0;
+        chunk = std::llround(per);
+    }
     lat.chunk = (int)std::max(1ll, std::min<long long>(chunk, kMaxChunk));
     lat.partitions = parts;
+    const long long span = 64ll * lat.chunk;
+    const long long n_chunks = (lat.n_lat + span - 1) / span;
+    long long groups = n_chunks * parts;
+    groups = (groups + kPartitions - 1) / kPartitions * kPartitions;
+    groups = std::max<long long>(kPartitions, std::min<long long>(groups, max_groups));
     return (int)groups;
 }
 
@@ -470,6 +485,61 @@ hipError_t prepare_learned(tsdf_map *m, CameraView *cams, int n_views, hipStream
         cams[v].sm_maps = out;
     }
     return e;
+}
+
+// Ray-walk allocation: widens the lattice by one block on every side (the
+// walk stays inside the frustum, the margin absorbs binary32 rounding at its
+// ends), marks the visited blocks and points the view at the marks.
+hipError_t prepare_walk(tsdf_map *m, FrameArgs &fa, const float T[16], hipStream_t s)
+{
+    if (m->p.allocation != TSDF_ALLOC_RAY_WALK)
+        return hipSuccess;
+    Lattice &lat = fa.lat;
+    for (int a = 0; a < 3; ++a) {
+        lat.lat_min[a] -= 1;
+        lat.lat_dim[a] += 2;
+    }
+    lat.n_lat = (long long)lat.lat_dim[0] * lat.lat_dim[1] * lat.lat_dim[2];
+    if (lat.n_lat >= (1ll << 31))
+        return hipErrorInvalidValue;
+    if (!m->walk_marks || m->walk_cap < lat.n_lat) {
+        if (m->walk_marks) {
+            hipError_t e = hipDeviceSynchronize();   // earlier launches may still read the old marks
+            if (e != hipSuccess)
+                return e;
+        }
+        (void)hipFree(m->walk_marks);
+        m->walk_marks = nullptr;
+        m->walk_cap = 0;
+        const long long cap = std::max<long long>(lat.n_lat, 1ll << 20);
+        hipError_t e = hipMalloc((void **)&m->walk_marks, (size_t)cap);
+        if (e != hipSuccess)
+            return e;
+        m->walk_cap = cap;
+    }
+    DdaArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            a.Rwc[3 * i + j] = T[4 * i + j];
+        a.o[i] = T[4 * i + 3];
+    }
+    a.fx = fa.cam.fx;
+    a.fy = fa.cam.fy;
+    a.cx = fa.cam.cx;
+    a.cy = fa.cam.cy;
+    a.width = fa.cam.width;
+    a.height = fa.cam.height;
+    a.depth = fa.cam.depth;
+    a.d_max = fa.cam.d_max;
+    a.eps = m->eps;
+    a.vs = m->p.voxel_size_m;
+    a.lat = lat;
+    a.marks = m->walk_marks;
+    a.overflow = m->dm.counters + kErrorBits;
+    fa.cam.dda_marks = m->walk_marks;
+    lat.partitions = 1;
+    return launch_dda_mark(a, lat.n_lat, s);
 }
 
 struct CounterSnapshot {
@@ -622,14 +692,19 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
-    if (e == hipSuccess)
+    const bool walk = m->p.allocation == TSDF_ALLOC_RAY_WALK;
+    if (e == hipSuccess && !walk)
         e = prepare_footprint(m, fa, s);
     if (e == hipSuccess)
         e = prepare_learned(m, &fa.cam, 1, s);
+    if (e == hipSuccess)
+        e = prepare_walk(m, fa, T_world_cam, s);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
     const int groups = schedule(m, fa.lat);
+    if (walk)
+        fa.lat.partitions = 1;    // every lattice entry is read by exactly one thread
     e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
@@ -647,8 +722,8 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
                         lidar->polar_fov_rad};
     if (!lidar_valid(lidar->width, lidar->height, A, lidar->interp_max_diff_m, lidar->max_range_m))
         return TSDF_EINVAL;
-    if (m->p.weighting == TSDF_WEIGHT_LEARNED)
-        return TSDF_EINVAL;    // the learned model is defined on pinhole depth images
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED || m->p.allocation == TSDF_ALLOC_RAY_WALK)
+        return TSDF_EINVAL;    // both are defined on pinhole depth images, one frame per launch
     if (m->sticky)
         return TSDF_ESTATE;
     const float range = lidar->max_range_m > 0.0f ? lidar->max_range_m : m->p.max_range_m;
@@ -782,6 +857,8 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
         return st;
     if (m->p.weighting == TSDF_WEIGHT_LEARNED && (spherical || !m->sm_params))
         return TSDF_EINVAL;
+    if (m->p.allocation == TSDF_ALLOC_RAY_WALK)
+        return TSDF_EINVAL;
     if (m->sticky)
         return TSDF_ESTATE;
     va.parity = (int)(m->frames & 1);
@@ -808,7 +885,7 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
     if (!m || !out)
         return TSDF_EINVAL;
     *out = nullptr;
-    if (m->p.weighting == TSDF_WEIGHT_LEARNED)
+    if (m->p.weighting == TSDF_WEIGHT_LEARNED || m->p.allocation == TSDF_ALLOC_RAY_WALK)
         return TSDF_EINVAL;
     tsdf_step *st = new (std::nothrow) tsdf_step();
     if (!st)

@@ -505,48 +505,72 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
     return (int)(lb % (uint32_t)kPartitions);
 }
 
-// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
-// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
-// P = 8) scans all chunks; each lane bands and culls one block, and the
-// surviving blocks of this partition are handed to body(bx, by, bz, view_mask)
-// one at a time (wave-uniform).
+// Walks the launch's lattice with the whole workgroup.  The lattice is cut
+// into chunks of lat.chunk x 64 consecutive blocks; a workgroup takes one
+// chunk at a time (with P = lat.partitions bands, the P workgroups
+// blockIdx.x / P share each chunk and workgroup blockIdx.x mod P keeps the
+// blocks of its band).  Every thread culls one block of the chunk, the
+// survivors are compacted in LDS (one LDS atomic per wave), and the
+// workgroup's waves take them round-robin: body(bx, by, bz, view_mask) runs
+// wave-uniform on one block at a time.  Survivors of a chunk are thus spread
+// over all waves of the workgroup instead of queueing behind the wave that
+// culled them.  Every thread of the workgroup must call this (it holds
+// barriers); the chunk loop is uniform across the workgroup.
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body)
 {
+    __shared__ uint32_t s_block[64 * kWavesPerGroup];
+    __shared__ uint32_t s_mask[64 * kWavesPerGroup];
+    __shared__ uint32_t s_count;
     const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
     const uint32_t P = (uint32_t)lat.partitions;
     const int part = (int)(blockIdx.x % P);
-    const uint32_t waves_pp = (gridDim.x / P) * (uint32_t)kWavesPerGroup;
-    const uint32_t wave_pp = (blockIdx.x / P) * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6);
+    const uint32_t groups_pp = gridDim.x / P;
     const uint32_t n_lat = (uint32_t)lat.n_lat;
-    const uint32_t chunk = (uint32_t)lat.chunk;
-    const uint32_t n_chunks = (n_lat + chunk - 1) / chunk;
+    const uint32_t span = 64u * (uint32_t)lat.chunk;
+    const uint32_t n_chunks = (n_lat + span - 1) / span;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    for (uint32_t c = wave_pp; c < n_chunks; c += waves_pp) {
-        const uint32_t lb = c * chunk + (uint32_t)lane;
+    for (uint32_t c = blockIdx.x / P; c < n_chunks; c += groups_pp) {
+        if (threadIdx.x == 0)
+            s_count = 0;
+        __syncthreads();
+        const uint32_t lb = c * span + threadIdx.x;
         uint32_t vmask = 0;
-        int bx = 0, by = 0, bz = 0;
-        if ((uint32_t)lane < chunk && lb < n_lat) {
+        if (threadIdx.x < span && lb < n_lat) {
             const uint32_t rest = lb / dim_x;
-            bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-            by = lat.lat_min[1] + (int)(rest % dim_y);
-            bz = lat.lat_min[2] + (int)(rest / dim_y);
-            if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
+            const int bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+            const int by = lat.lat_min[1] + (int)(rest % dim_y);
+            const int bz = lat.lat_min[2] + (int)(rest / dim_y);
+            if (cams[0].dda_marks)
+                vmask = cams[0].dda_marks[lb] ? 1u : 0u;     // ray-walk allocation: the walk decides
+            else if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
                 for (int v = 0; v < n_views; ++v)
                     if (lane_block_in_view(cams[v], mc, bx, by, bz))
                         vmask |= 1u << v;
         }
-        unsigned long long todo = __ballot(vmask != 0);
-        while (todo) {
-            const int src = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            const int sbx = __builtin_amdgcn_readlane(bx, src);
-            const int sby = __builtin_amdgcn_readlane(by, src);
-            const int sbz = __builtin_amdgcn_readlane(bz, src);
-            const uint32_t svm = (uint32_t)__builtin_amdgcn_readlane((int)vmask, src);
-            body(sbx, sby, sbz, svm);
+        const unsigned long long keep = __ballot(vmask != 0);
+        if (keep) {
+            uint32_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(&s_count, (uint32_t)__popcll(keep));
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            if (vmask) {
+                const uint32_t k = base + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull));
+                s_block[k] = lb;
+                s_mask[k] = vmask;
+            }
         }
+        __syncthreads();
+        const uint32_t n = s_count;
+        for (uint32_t k = (uint32_t)wave; k < n; k += kWavesPerGroup) {
+            const uint32_t b = s_block[k];
+            const uint32_t rest = b / dim_x;
+            body(lat.lat_min[0] + (int)(b - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
+                 lat.lat_min[2] + (int)(rest / dim_y), s_mask[k]);
+        }
+        __syncthreads();
     }
 }
 

@@ -13,7 +13,8 @@
 //                  first hash probe window is already in flight.
 //   3. allocate -- only if a ballot finds an updated voxel is the block looked
 //                  up in the block hash and, if new, inserted (64-bit
-//                  atomicCAS) with a fresh zeroed pool slot (§IV-A).
+//                  atomicCAS) with a fresh zeroed pool slot (§IV-A); with
+//                  ray-walk allocation every block the walk visited is.
 //   4. update   -- the weighted average runs on 512-byte slab loads and stores
 //                  of (distance, weight) pairs, predicated per lane.
 //   5. compact  -- touched pool slots collect in a wave register and are
@@ -52,7 +53,8 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
         const float py = ((float)(8 * by + ly) + 0.5f) * fa.mc.vs;
         float xs[8], ws[8];
         const uint32_t hit = measure_view<WEIGHTING, SPHERICAL>(fa.cam, fa.mc, px, py, bz, xs, ws);
-        if (__ballot(hit != 0) == 0ull)
+        // ray-walk allocation keeps every visited block, updated or not
+        if (!fa.cam.dda_marks && __ballot(hit != 0) == 0ull)
             return;
 
         const uint32_t slot = find_or_insert(dm, key, h, w0);

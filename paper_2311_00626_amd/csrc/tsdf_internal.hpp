@@ -16,7 +16,7 @@ constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of 
 constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
 constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
 constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
-constexpr int kMaxChunk = 64;                       // lattice blocks culled together by one wave
+constexpr int kMaxChunk = 8;                        // lattice blocks a workgroup culls per pass, in 64s
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
 // Weighting functions (the tsdf_params weighting codes).
@@ -64,6 +64,7 @@ enum ErrorBits : uint32_t {
     kErrHashFull = 2u,
     kErrTouchedOverflow = 4u,
     kErrInsertRace = 8u,
+    kErrWalkOutside = 16u,     // a ray walk left the frame's lattice (a bound was too small)
 };
 
 // Device-side view of a map.  Passed to kernels by value.
@@ -106,6 +107,9 @@ struct CameraView {
     float cos_pol_start, cos_pol_end;   // polar band edges (cone culling)
     // learned sensor model: per-pixel (weight, truncation) pairs (pinhole views)
     const float2 *sm_maps;
+    // ray-walk allocation: byte per lattice entry, set for the blocks the walk
+    // visited (nullptr: exact-touch allocation with culling)
+    const unsigned char *dda_marks;
     // depth footprint pyramid of this view (nullptr: no footprint culling)
     float *tiles;
     int tile_cols[kTileLevels];         // tiles per row at each level
@@ -123,13 +127,13 @@ struct MapConsts {
     float margin_z;         // conservative slack of the near/far culling planes
 };
 
-// Block lattice scanned by one launch.  Waves cull `chunk` consecutive
-// lattice entries at a time, one per lane.
+// Block lattice scanned by one launch.  Workgroups cull 64 x `chunk`
+// consecutive lattice entries at a time, one per thread.
 struct Lattice {
     int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
-    int chunk;              // 1 .. kMaxChunk
+    int chunk;              // 1 .. kMaxChunk (in units of 64 lattice entries)
     int partitions;         // 1 or kPartitions ownership bands
 };
 
@@ -188,6 +192,20 @@ hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long 
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
                               hipStream_t stream);
+// Ray-walk allocation pre-pass (dda.hip).
+struct DdaArgs {
+    float Rwc[9];           // world-from-camera rotation, row-major
+    float o[3];             // camera centre in the world
+    float fx, fy, cx, cy;
+    int width, height;
+    const float *depth;
+    float d_max, eps, vs;
+    Lattice lat;            // the launch's lattice (marks are indexed by lattice entry)
+    unsigned char *marks;
+    uint32_t *overflow;     // set when a walk leaves the lattice (a bound was too small)
+};
+hipError_t launch_dda_mark(const DdaArgs &a, long long n_marks, hipStream_t stream);
+
 // Builds the footprint pyramids of the views whose `tiles` is set.
 hipError_t launch_footprint_tiles(const ViewsArgs &va, hipStream_t stream);
 hipError_t launch_footprint_tiles_dev(const ViewsArgs *va_dev, hipStream_t stream);

@@ -22,6 +22,7 @@ WEIGHTINGS = {"constant": 0, "linear_dropoff": 1, "learned": 2}
 SM_NPARAM = 2018
 SM_MAX_FRAMES = 16
 STORAGES = {"fp32": 0, "fp16": 1}
+ALLOCATIONS = {"exact": 0, "ray_walk": 1}
 
 
 class TsdfError(RuntimeError):
@@ -71,7 +72,8 @@ class tsdf_params(C.Structure):
     _fields_ = [("voxel_size_m", C.c_float), ("truncation_vox", C.c_float),
                 ("max_weight", C.c_float), ("max_range_m", C.c_float),
                 ("weighting", C.c_int), ("storage", C.c_int),
-                ("block_capacity", C.c_longlong), ("hash_capacity", C.c_longlong)]
+                ("block_capacity", C.c_longlong), ("hash_capacity", C.c_longlong),
+                ("allocation", C.c_int), ("reserved", C.c_int)]
 
 
 def _load() -> C.CDLL:
@@ -184,7 +186,7 @@ class TsdfMap:
 
     def __init__(self, voxel_size: float, truncation_vox: float, *, max_weight: float = 100.0,
                  max_range: float = 5.0, weighting: str = "constant", storage: str = "fp32",
-                 block_capacity: int = 1 << 18, hash_capacity: int = 0):
+                 block_capacity: int = 1 << 18, hash_capacity: int = 0, allocation: str = "exact"):
         p = default_params(voxel_size, truncation_vox)
         p.max_weight = max_weight
         p.max_range_m = max_range
@@ -192,6 +194,7 @@ class TsdfMap:
         p.storage = STORAGES[storage]
         p.block_capacity = block_capacity
         p.hash_capacity = hash_capacity
+        p.allocation = ALLOCATIONS[allocation]
         h = C.c_void_p()
         _check(lib.create_map_ex(C.byref(p), C.byref(h)), "create_map_ex")
         self._h = h

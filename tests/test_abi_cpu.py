@@ -41,7 +41,7 @@ def test_struct_layouts(t):
 
 
 def test_params_struct_layout(t):
-    assert C.sizeof(t.tsdf_params) == 40
+    assert C.sizeof(t.tsdf_params) == 48
     p = t.default_params(0.04, 4.0)
     assert p.voxel_size_m == pytest.approx(0.04) and p.truncation_vox == 4.0
     assert p.max_weight == 100.0 and p.max_range_m == 5.0 and p.weighting == 0
@@ -61,7 +61,8 @@ def test_invalid_create_arguments_rejected_before_device(t):
         assert not h.value
     p = t.default_params(0.05, 4.0)
     for field, bad in (("max_weight", 0.0), ("max_range_m", -1.0), ("weighting", 7), ("storage", 2),
-                       ("block_capacity", 0), ("hash_capacity", 3), ("hash_capacity", -8)):
+                       ("block_capacity", 0), ("hash_capacity", 3), ("hash_capacity", -8), ("allocation", 2),
+                       ("reserved", 1)):
         q = t.default_params(0.05, 4.0)
         setattr(q, field, bad)
         assert t.lib.create_map_ex(C.byref(q), C.byref(h)) == t.EINVAL, field

@@ -1,7 +1,7 @@
 """The pins must catch plausible mistakes in the oracle.  Each case plants one
 mistake in a temporary copy of the oracle sources (on the CPU), builds it, and
-runs the pin suites (pinhole, LiDAR and learned sensor model) against it; the
-suite has to fail."""
+runs the pin suites (pinhole, LiDAR, learned sensor model, ray walk) against
+it; the suite has to fail."""
 import os
 import shutil
 import subprocess
@@ -39,7 +39,9 @@ MUTANTS = [
      "/* voxel centre p_L */\n    REAL px = ((REAL)gx + half) * f->vs;",
      "/* voxel centre p_L */\n    REAL px = ((REAL)gx) * f->vs;"),
     ("dropoff_sign", "oracle_impl.h", "w = (f->eps + dp) * f->span_inv;", "w = (f->eps - dp) * f->span_inv;"),
-    ("max_range_exclusive", "oracle_impl.h", "if (!(d > 0 && d <= f->d_max))", "if (!(d > 0 && d < f->d_max))"),
+    ("max_range_exclusive", "oracle_impl.h",
+     "/* a measurement is valid iff 0 < d <= max range (NaN, Inf, <= 0 fail) */\n    if (!(d > 0 && d <= f->d_max))",
+     "/* a measurement is valid iff 0 < d <= max range (NaN, Inf, <= 0 fail) */\n    if (!(d > 0 && d < f->d_max))"),
     ("scan_box_misses_truncation_band", "oracle_impl.h", "double zfar = zmax + (double)f->eps;",
      "double zfar = zmax - (double)f->eps;"),
     ("binary16_rounds_toward_zero", "tsdf_oracle.c", "float r = nearbyintf(ax / q) * q;",
@@ -75,6 +77,15 @@ MUTANTS = [
      "gw[f * npx + k] += gD * (Dp - x) / sw;"),
     ("sm_pixel_truncation_ignored", "oracle_impl.h", "REAL e = (REAL)f->eps_map[idx];", "REAL e = f->eps;"),
     ("sm_bf16_truncates", "sensor_model_impl.h", "u += 0x7fffu + ((u >> 16) & 1u);", "u += 0u;"),
+    # ray-walk allocation
+    ("walk_tie_order", "oracle_impl.h",
+     "const int ax = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);",
+     "const int ax = (tmax[2] <= tmax[1] && tmax[2] <= tmax[0]) ? 2 : (tmax[1] <= tmax[0] ? 1 : 0);"),
+    ("walk_stops_at_depth", "oracle_impl.h", "REAL te = d + f->eps;", "REAL te = d;"),
+    ("walk_through_pixel_corner", "oracle_impl.h", "const REAL a = (((REAL)i + half) - f->cx) / f->fx;",
+     "const REAL a = ((REAL)i - f->cx) / f->fx;"),
+    ("walk_negative_step_boundary", "oracle_impl.h", "tmax[k] = ((REAL)c[k] * B - o[k]) / dir[k];",
+     "tmax[k] = ((REAL)(c[k] - 1) * B - o[k]) / dir[k];"),
     ("beam_at_pixel_edge", "oracle_impl.h",
      "REAL uc = (theta - f->az_start) * f->alpha - half;", "REAL uc = (theta - f->az_start) * f->alpha;"),
 ]
@@ -98,7 +109,8 @@ def run_mutant(fname, orig, mutant):
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                             os.path.join(ROOT, "tests", "test_oracle_lidar.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_sensor_model.py")],
+                            os.path.join(ROOT, "tests", "test_oracle_sensor_model.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_dda.py")],
                            cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
         return 1, r.returncode
 
