@@ -94,7 +94,8 @@ def counters(m):
     return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
 
 
-def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int) -> dict:
+def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int,
+                setup=None, **map_kw) -> dict:
     """One integrate_depth launch per frame over `steps` frames (cycling the
     sequence) after `warmup` untimed ones; HIP events around each launch."""
     import torch
@@ -102,7 +103,9 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     n_frames = frames.shape[0]
     H, W = frames.shape[1], frames.shape[2]
     K = w.camera.K
-    m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity)
+    m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity, **map_kw)
+    if setup is not None:
+        setup(m)
     for k in range(warmup):
         m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
     torch.cuda.synchronize()
@@ -121,7 +124,8 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, steps, 4 if storage == "fp16" else 8) / steps
     kern = kernel_ms / 1e3 / max(launches, 1)
     return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
-            "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9}
+            "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9,
+            "blocks": b1}
 
 
 def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
@@ -148,6 +152,50 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
     del frames
     torch.cuda.empty_cache()
     return out
+
+
+def walk_leg(w, frames, poses, steps: int, warmup: int) -> dict:
+    """The paper-literal ray-walk allocation on the same frames."""
+    r = timed_plain(w, frames, poses, "fp32", steps, warmup, 1 << 16, allocation="ray_walk")
+    return {"allocation": "ray walk along pixel-centre rays to min(d + eps, max range)",
+            "value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
+            "frames_per_s": steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
+            "blocks_allocated": r["blocks"], "kernel_ms_mean": r["kernel_s"] * 1e3,
+            "note": "ms_per_step includes the per-pixel walk kernel; kernel_ms_mean is the integration kernel"}
+
+
+def learned_leg(w, frames, poses, steps: int, warmup: int) -> dict:
+    """Learned sensor-model weighting on the same frames (untrained model: the
+    cost does not depend on the parameter values), and the training step time
+    on one 640x480 room at 2 cm."""
+    import torch
+    from paper_2311_00626_amd import sensor_model as sm
+    params = sm.init_params(0)
+    r = timed_plain(w, frames, poses, "fp32", steps, warmup, 1 << 16, setup=lambda m: m.set_sensor_model(params),
+                    weighting="learned")
+    out = {"weighting": "learned sensor model (27-32-32-2 perceptron per pixel, bfloat16)",
+           "value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
+           "frames_per_s": steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
+           "kernel_ms_mean": r["kernel_s"] * 1e3,
+           "note": "ms_per_step includes the per-pixel inference pre-pass"}
+    vs = 0.02
+    room = sm.prepare_room(1000, 24, synth_cam_640(), vs, window=8)
+    n = 30
+    sm.train([room], vs, steps=3, lr=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sm.train([room], vs, steps=n, lr=1e-3, log_every=n + 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    targets = sum(int(wd.target.numel()) for wd in room.windows) / len(room.windows)
+    out["training"] = {"window_frames": 8, "target_voxels_per_window": targets, "steps": n,
+                       "ms_per_step": dt / n * 1e3, "workload": "learning room 1000, 640x480, 2 cm"}
+    return out
+
+
+def synth_cam_640():
+    from paper_2311_00626_amd import synth
+    return synth.CAM_640
 
 
 def rig_leg(n_steps: int, warmup: int):
@@ -236,7 +284,7 @@ def main():
                     help="after timing, run one plain device copy of this size (PMC scaling)")
     ap.add_argument("--rig-steps", type=int, default=500,
                     help="steps of the multi-sensor rig leg (4 cameras + LiDAR, graph-replayed; 0 = skip it)")
-    ap.add_argument("--legs", default="plain,fp16,batched,rig,precision",
+    ap.add_argument("--legs", default="plain,fp16,batched,rig,precision,walk,learned",
                     help="comma-separated legs to run (plain is always run)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -320,6 +368,10 @@ def main():
     rig = rig_leg(args.rig_steps, args.warmup) if args.rig_steps > 0 and "rig" in legs else None
     precision = ([precision_leg(vs, args.steps, args.warmup) for vs in (0.01, 0.02)]
                  if "precision" in legs else None)
+    walk = walk_leg(w, frames, poses, args.steps, args.warmup) if "walk" in legs else None
+    if walk is not None:
+        walk["blocks_allocated_exact_touch"] = p32["blocks"]
+    learned = learned_leg(w, frames, poses, args.steps, args.warmup) if "learned" in legs else None
 
     if args.copy_calibration_mib > 0:
         src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
@@ -360,6 +412,10 @@ def main():
         result["rig"] = rig
     if precision is not None:
         result["precision"] = precision
+    if walk is not None:
+        result["ray_walk"] = walk
+    if learned is not None:
+        result["learned"] = learned
     if batched is not None:
         result["batched"] = batched
     if not args.skip_cpu_baseline:

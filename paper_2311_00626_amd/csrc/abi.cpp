@@ -353,15 +353,13 @@ int schedule(const tsdf_map *m, Lattice &lat)
     long long max_groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
     max_groups = std::max<long long>(kPartitions, max_groups / kPartitions * kPartitions);
     const int parts = lc.partitions > 0 ? lc.partitions : 1;
-    long long chunk = lc.chunk;
-    if (chunk <= 0) {
-        // about one chunk per workgroup: n_lat / (workgroups per band) entries, in 64s
-        const double per = (double)lat.n_lat / (double)(max_groups / parts) / 64.0;
-        chunk = std::llround(per);
-    }
-    lat.chunk = (int)std::max(1ll, std::min<long long>(chunk, kMaxChunk));
+    const long long per_band = max_groups / parts;
+    // lattice entries per workgroup pass: explicit (64 x chunk), or the
+    // lattice shared evenly over the workgroups of a band (one pass each)
+    long long span = lc.chunk > 0 ? 64ll * lc.chunk : (lat.n_lat + per_band - 1) / per_band;
+    span = std::max(1ll, std::min<long long>(span, 64ll * kWavesPerGroup));
+    lat.chunk = (int)span;
     lat.partitions = parts;
-    const long long span = 64ll * lat.chunk;
     const long long n_chunks = (lat.n_lat + span - 1) / span;
     long long groups = n_chunks * parts;
     groups = (groups + kPartitions - 1) / kPartitions * kPartitions;

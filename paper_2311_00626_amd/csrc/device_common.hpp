@@ -506,7 +506,8 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
 }
 
 // Walks the launch's lattice with the whole workgroup.  The lattice is cut
-// into chunks of lat.chunk x 64 consecutive blocks; a workgroup takes one
+// into chunks of lat.chunk consecutive blocks (at most one per thread); a
+// workgroup takes one
 // chunk at a time (with P = lat.partitions bands, the P workgroups
 // blockIdx.x / P share each chunk and workgroup blockIdx.x mod P keeps the
 // blocks of its band).  Every thread culls one block of the chunk, the
@@ -529,7 +530,7 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
     const int part = (int)(blockIdx.x % P);
     const uint32_t groups_pp = gridDim.x / P;
     const uint32_t n_lat = (uint32_t)lat.n_lat;
-    const uint32_t span = 64u * (uint32_t)lat.chunk;
+    const uint32_t span = (uint32_t)lat.chunk;
     const uint32_t n_chunks = (n_lat + span - 1) / span;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     for (uint32_t c = blockIdx.x / P; c < n_chunks; c += groups_pp) {

@@ -117,9 +117,10 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes);
 }
 
-// Arguments passed by value (eager launches).
+// Arguments passed by value (eager launches).  Four waves per SIMD (two
+// workgroups per CU) cap the kernel at 128 VGPRs.
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
-__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
+__global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
 {
     integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, va);
 }
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel(De
 // Arguments read from device memory (graph replays: the host rewrites them
 // between replays through a captured copy).
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
-__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_views_kernel_dev(DeviceMap dm,
+__global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_kernel_dev(DeviceMap dm,
                                                                                   const ViewsArgs *__restrict__ va)
 {
     integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, *va);

@@ -127,13 +127,13 @@ struct MapConsts {
     float margin_z;         // conservative slack of the near/far culling planes
 };
 
-// Block lattice scanned by one launch.  Workgroups cull 64 x `chunk`
-// consecutive lattice entries at a time, one per thread.
+// Block lattice scanned by one launch.  Workgroups cull `chunk` consecutive
+// lattice entries at a time, one per thread.
 struct Lattice {
     int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
-    int chunk;              // 1 .. kMaxChunk (in units of 64 lattice entries)
+    int chunk;              // 1 .. 64 * kWavesPerGroup lattice entries per workgroup pass
     int partitions;         // 1 or kPartitions ownership bands
 };
 
