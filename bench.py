@@ -94,6 +94,10 @@ def counters(m):
     return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
 
 
+def candidates(m) -> int:
+    return m.full_stats()["candidate_blocks"]
+
+
 def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int,
                 setup=None, **map_kw) -> dict:
     """One integrate_depth launch per frame over `steps` frames (cycling the
@@ -110,6 +114,7 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
         m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
     torch.cuda.synchronize()
     b0, u0, _, t0_ = counters(m)
+    c0 = candidates(m)
     m.profile(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -125,7 +130,7 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     kern = kernel_ms / 1e3 / max(launches, 1)
     return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
             "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9,
-            "blocks": b1}
+            "blocks": b1, "candidates": candidates(m) - c0}
 
 
 def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
@@ -144,6 +149,7 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
                         "frames_per_s": min(steps, 290) / r["elapsed"],
                         "updates_per_frame": r["updates"] / min(steps, 290),
                         "touched_blocks_per_frame": r["touched"] / min(steps, 290),
+                        "candidate_blocks_per_frame": r["candidates"] / min(steps, 290),
                         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
                                      "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
                                      "kernel": f"integrate_depth_kernel<{storage}>",
@@ -399,6 +405,7 @@ def main():
                    "parallelism": "single GPU"},
         "voxel_updates": updates,
         "touched_blocks": touched,
+        "candidate_blocks": p32["candidates"],
         "new_blocks": new_blocks,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

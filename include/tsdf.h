@@ -227,6 +227,7 @@ typedef struct {
     long long voxel_writes;    /* one per voxel per call that updated it (stores to the pool) */
     long long touched_blocks;  /* one per block per call in which any of its voxels was updated */
     long long launches;        /* integration calls enqueued */
+    long long candidate_blocks;  /* one per block per call that survived culling and was measured */
 } tsdf_stats;
 
 /* Fills *out.  Synchronises hip_stream. */

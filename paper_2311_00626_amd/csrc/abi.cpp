@@ -347,20 +347,27 @@ hipError_t use_device(const tsdf_map *m)
 // Image-band ownership per XCD (partitions = 8) cuts L2 fills but measured
 // slower on both regimes, so it is only used when asked for.  Fields of the
 // map's launch configuration override these choices.
+constexpr long long kCoarseLattice = 1ll << 17;   // lattices at least this large walk super-blocks first
+
 int schedule(const tsdf_map *m, Lattice &lat)
 {
     const tsdf_launch_config &lc = m->launch;
     long long max_groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
     max_groups = std::max<long long>(kPartitions, max_groups / kPartitions * kPartitions);
     const int parts = lc.partitions > 0 ? lc.partitions : 1;
+    lat.partitions = parts;
+    // two-level walk (super-blocks of 4^3 blocks) for large lattices
+    lat.coarse = lat.n_lat >= kCoarseLattice && parts == 1 && m->p.allocation != TSDF_ALLOC_RAY_WALK ? 1 : 0;
+    long long units = lat.n_lat;
+    if (lat.coarse)
+        units = (long long)((lat.lat_dim[0] + 3) / 4) * ((lat.lat_dim[1] + 3) / 4) * ((lat.lat_dim[2] + 3) / 4);
     const long long per_band = max_groups / parts;
-    // lattice entries per workgroup pass: explicit (64 x chunk), or the
-    // lattice shared evenly over the workgroups of a band (one pass each)
-    long long span = lc.chunk > 0 ? 64ll * lc.chunk : (lat.n_lat + per_band - 1) / per_band;
+    // units per workgroup pass: explicit (64 x chunk), or the units shared
+    // evenly over the workgroups of a band (one pass each)
+    long long span = lc.chunk > 0 ? 64ll * lc.chunk : (units + per_band - 1) / per_band;
     span = std::max(1ll, std::min<long long>(span, 64ll * kWavesPerGroup));
     lat.chunk = (int)span;
-    lat.partitions = parts;
-    const long long n_chunks = (lat.n_lat + span - 1) / span;
+    const long long n_chunks = (units + span - 1) / span;
     long long groups = n_chunks * parts;
     groups = (groups + kPartitions - 1) / kPartitions * kPartitions;
     groups = std::max<long long>(kPartitions, std::min<long long>(groups, max_groups));
@@ -949,6 +956,7 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
     (void)schedule(m, lat);      // chunk and partitions for this lattice; the grid is fixed
     va.lat.chunk = lat.chunk;
     va.lat.partitions = lat.partitions;
+    va.lat.coarse = lat.coarse;
     hipError_t e = use_device(m);
     if (e == hipSuccess)
         e = prepare_footprint(m, va, nullptr, false);   // the graph builds the pyramids
@@ -1090,10 +1098,11 @@ int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream)
     int st = read_counters(m, cs, (hipStream_t)hip_stream);
     if (st != TSDF_OK)
         return st;
-    unsigned long long upd = 0, wr = 0;
+    unsigned long long upd = 0, wr = 0, cand = 0;
     for (int k = 0; k < kSubLists; ++k) {
         upd += cs.t[kTotalUpdates + k * kTotalsStride];
         wr += cs.t[kTotalWrites + k * kTotalsStride];
+        cand += cs.t[kTotalCandidates + k * kTotalsStride];
     }
     long long per[kSubLists];
     last_touched_counts(m, cs, per);
@@ -1105,6 +1114,7 @@ int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream)
     out->voxel_writes = (long long)wr;
     out->touched_blocks = touched;
     out->launches = m->frames;
+    out->candidate_blocks = (long long)cand;
     return TSDF_OK;
 }
 

@@ -209,9 +209,9 @@ __device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long lon
 // below -margin for some plane; the margin exceeds the binary32 error of any
 // voxel's projection, so no block holding an updated voxel is ever dropped.
 __device__ __forceinline__ bool lane_block_in_pinhole(const CameraView &cv, const MapConsts &mc, int bx, int by,
-                                                      int bz)
+                                                      int bz, int nb = 1)
 {
-    const float e = 8.0f * mc.vs;
+    const float e = 8.0f * (float)nb * mc.vs;
     const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
     const float x0 = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
     const float y0 = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
@@ -251,9 +251,9 @@ __device__ __forceinline__ bool lane_block_in_pinhole(const CameraView &cv, cons
 // it): z - |p| cos(phi_start) and -z + |p| cos(phi_end) are concave, so their
 // minimum over the box is at a corner.
 __device__ __forceinline__ bool lane_block_in_spherical(const CameraView &cv, const MapConsts &mc, int bx, int by,
-                                                        int bz)
+                                                        int bz, int nb = 1)
 {
-    const float e = 8.0f * mc.vs;
+    const float e = 8.0f * (float)nb * mc.vs;
     const float lo[3] = {(float)(8 * bx) * mc.vs, (float)(8 * by) * mc.vs, (float)(8 * bz) * mc.vs};
     float d2 = 0.0f;
 #pragma unroll
@@ -358,9 +358,9 @@ __device__ __forceinline__ float footprint_max(const CameraView &cv, int i0, int
 // rectangle is widened by 2 pixels, far beyond the binary32 error of either
 // projection.  Blocks reaching within 1 mm of the camera plane are kept.
 __device__ __forceinline__ bool lane_block_footprint_pinhole(const CameraView &cv, const MapConsts &mc, int bx,
-                                                             int by, int bz)
+                                                             int by, int bz, int nb = 1)
 {
-    const float e = 8.0f * mc.vs;
+    const float e = 8.0f * (float)nb * mc.vs;
     const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
     float zmin = 3.0e38f, umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
 #pragma unroll
@@ -399,11 +399,12 @@ __device__ __forceinline__ bool lane_block_footprint_pinhole(const CameraView &c
 // reaches the sensor are kept; so are those nearly reaching the z axis (all
 // azimuths), and, for a partial-circle sensor, those straddling azimuth +-pi.
 __device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView &cv, const MapConsts &mc, int bx,
-                                                               int by, int bz)
+                                                               int by, int bz, int nb = 1)
 {
-    const float e = 8.0f * mc.vs;
-    const float X = ((float)(8 * bx) + 4.0f) * mc.vs, Y = ((float)(8 * by) + 4.0f) * mc.vs,
-                Z = ((float)(8 * bz) + 4.0f) * mc.vs;
+    const float e = 8.0f * (float)nb * mc.vs;
+    const float half = 4.0f * (float)nb;
+    const float X = ((float)(8 * bx) + half) * mc.vs, Y = ((float)(8 * by) + half) * mc.vs,
+                Z = ((float)(8 * bz) + half) * mc.vs;
     const float x = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
     const float y = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
     const float z = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
@@ -462,16 +463,19 @@ __device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView 
     return !ok || Rc - rad <= dm + mc.eps + mc.margin_z;
 }
 
-__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+// Culling of the box of nb x nb x nb blocks whose first block is (bx, by, bz)
+// against one view: false only when no voxel in the box can be updated.
+__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz,
+                                                   int nb = 1)
 {
     if (cv.model == kModelSpherical) {
-        if (!lane_block_in_spherical(cv, mc, bx, by, bz))
+        if (!lane_block_in_spherical(cv, mc, bx, by, bz, nb))
             return false;
-        return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz);
+        return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz, nb);
     }
-    if (!lane_block_in_pinhole(cv, mc, bx, by, bz))
+    if (!lane_block_in_pinhole(cv, mc, bx, by, bz, nb))
         return false;
-    return !cv.tiles || lane_block_footprint_pinhole(cv, mc, bx, by, bz);
+    return !cv.tiles || lane_block_footprint_pinhole(cv, mc, bx, by, bz, nb);
 }
 
 // Ownership band of a block (one per XCD): the image-column band of the
@@ -505,6 +509,108 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
     return (int)(lb % (uint32_t)kPartitions);
 }
 
+// Two-level walk for large lattices: the lattice is covered by super-blocks
+// of kSuper^3 blocks; a workgroup culls a chunk of lat.chunk super-blocks
+// (one per thread, the whole box against each view), then, kWavesPerGroup
+// surviving super-blocks at a time, each wave culls the blocks of one of them
+// (one per lane, only against the views that kept the super-block); the
+// surviving blocks are compacted in LDS and the waves take them round-robin.
+// A culled super-block holds no updatable voxel, so its blocks are skipped
+// without a test.  No partitions (P = 1) and no ray-walk marks.
+constexpr int kSuper = 4;
+
+template <class Body>
+__device__ __forceinline__ void scan_lattice_coarse(const Lattice &lat, const CameraView *cams, int n_views,
+                                                    const MapConsts &mc, uint32_t *s_block, uint32_t *s_mask,
+                                                    uint32_t &s_count, Body &&body)
+{
+    __shared__ uint32_t s_sup[64 * kWavesPerGroup];
+    __shared__ uint32_t s_supmask[64 * kWavesPerGroup];
+    __shared__ uint32_t s_nsup;
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1],
+                   dim_z = (uint32_t)lat.lat_dim[2];
+    const uint32_t sx = (dim_x + kSuper - 1) / kSuper, sy = (dim_y + kSuper - 1) / kSuper,
+                   sz = (dim_z + kSuper - 1) / kSuper;
+    const uint32_t n_sup = sx * sy * sz;
+    const uint32_t span = (uint32_t)lat.chunk;
+    const uint32_t n_chunks = (n_sup + span - 1) / span;
+    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        if (threadIdx.x == 0)
+            s_nsup = 0;
+        __syncthreads();
+        const uint32_t sb = c * span + threadIdx.x;
+        uint32_t vmask = 0;
+        if (threadIdx.x < span && sb < n_sup) {
+            const uint32_t rest = sb / sx;
+            const int ox = lat.lat_min[0] + kSuper * (int)(sb - rest * sx);
+            const int oy = lat.lat_min[1] + kSuper * (int)(rest % sy);
+            const int oz = lat.lat_min[2] + kSuper * (int)(rest / sy);
+            for (int v = 0; v < n_views; ++v)
+                if (lane_block_in_view(cams[v], mc, ox, oy, oz, kSuper))
+                    vmask |= 1u << v;
+        }
+        const unsigned long long keep = __ballot(vmask != 0);
+        if (keep) {
+            uint32_t base = 0;
+            if (lane == 0)
+                base = atomicAdd(&s_nsup, (uint32_t)__popcll(keep));
+            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+            if (vmask) {
+                const uint32_t k = base + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull));
+                s_sup[k] = sb;
+                s_supmask[k] = vmask;
+            }
+        }
+        __syncthreads();
+        const uint32_t n_s = s_nsup;
+        for (uint32_t first = 0; first < n_s; first += kWavesPerGroup) {
+            if (threadIdx.x == 0)
+                s_count = 0;
+            __syncthreads();
+            const uint32_t k = first + (uint32_t)wave;
+            if (k < n_s) {
+                const uint32_t sbk = s_sup[k];
+                const uint32_t smask = s_supmask[k];
+                const uint32_t rest = sbk / sx;
+                const uint32_t x = kSuper * (sbk - rest * sx) + (uint32_t)(lane & 3);
+                const uint32_t y = kSuper * (rest % sy) + (uint32_t)((lane >> 2) & 3);
+                const uint32_t z = kSuper * (rest / sy) + (uint32_t)(lane >> 4);
+                uint32_t bmask = 0;
+                if (x < dim_x && y < dim_y && z < dim_z) {
+                    const int bx = lat.lat_min[0] + (int)x, by = lat.lat_min[1] + (int)y,
+                              bz = lat.lat_min[2] + (int)z;
+                    for (int v = 0; v < n_views; ++v)
+                        if (((smask >> v) & 1u) && lane_block_in_view(cams[v], mc, bx, by, bz))
+                            bmask |= 1u << v;
+                }
+                const unsigned long long bkeep = __ballot(bmask != 0);
+                if (bkeep) {
+                    uint32_t base = 0;
+                    if (lane == 0)
+                        base = atomicAdd(&s_count, (uint32_t)__popcll(bkeep));
+                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+                    if (bmask) {
+                        const uint32_t q = base + (uint32_t)__popcll(bkeep & ((1ull << lane) - 1ull));
+                        s_block[q] = x + dim_x * (y + dim_y * z);
+                        s_mask[q] = bmask;
+                    }
+                }
+            }
+            __syncthreads();
+            const uint32_t n = s_count;
+            for (uint32_t q = (uint32_t)wave; q < n; q += kWavesPerGroup) {
+                const uint32_t b = s_block[q];
+                const uint32_t rest = b / dim_x;
+                body(lat.lat_min[0] + (int)(b - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
+                     lat.lat_min[2] + (int)(rest / dim_y), s_mask[q]);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Walks the launch's lattice with the whole workgroup.  The lattice is cut
 // into chunks of lat.chunk consecutive blocks (at most one per thread); a
 // workgroup takes one
@@ -533,6 +639,10 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
     const uint32_t span = (uint32_t)lat.chunk;
     const uint32_t n_chunks = (n_lat + span - 1) / span;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    if (lat.coarse) {
+        scan_lattice_coarse(lat, cams, n_views, mc, s_block, s_mask, s_count, body);
+        return;
+    }
     for (uint32_t c = blockIdx.x / P; c < n_chunks; c += groups_pp) {
         if (threadIdx.x == 0)
             s_count = 0;
@@ -776,34 +886,41 @@ __device__ __forceinline__ void push_touched(const DeviceMap &dm, int parity, in
 }
 
 // End of a launch: prefix sum over the workgroup's waves, one atomic on the
-// sub-list counter, entries written; voxel-update counts summed likewise.
+// sub-list counter, entries written; voxel-update, voxel-write and
+// candidate-block counts summed likewise.
 template <int WAVES>
 __device__ __forceinline__ void finish_group(const DeviceMap &dm, int parity, int sub, uint32_t pending,
-                                             int n_pending, uint32_t n_updates, uint32_t n_writes)
+                                             int n_pending, uint32_t n_updates, uint32_t n_writes,
+                                             uint32_t n_candidates)
 {
     __shared__ uint32_t s_count[WAVES];
     __shared__ uint32_t s_updates[WAVES];
     __shared__ uint32_t s_writes[WAVES];
+    __shared__ uint32_t s_cands[WAVES];
     __shared__ uint32_t s_base;
     const int wave = (int)(threadIdx.x >> 6);
     if (lane_id() == 0) {
         s_count[wave] = (uint32_t)n_pending;
         s_updates[wave] = n_updates;
         s_writes[wave] = n_writes;
+        s_cands[wave] = n_candidates;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t total = 0, upd = 0, wr = 0;
+        uint32_t total = 0, upd = 0, wr = 0, cand = 0;
         for (int k = 0; k < WAVES; ++k) {
             total += s_count[k];
             upd += s_updates[k];
             wr += s_writes[k];
+            cand += s_cands[k];
         }
         s_base = total ? atomicAdd(&dm.counters[touched_counter(parity, sub)], total) : 0u;
         if (upd)
             atomicAdd(&dm.totals[kTotalUpdates + sub * kTotalsStride], (unsigned long long)upd);
         if (wr)
             atomicAdd(&dm.totals[kTotalWrites + sub * kTotalsStride], (unsigned long long)wr);
+        if (cand)
+            atomicAdd(&dm.totals[kTotalCandidates + sub * kTotalsStride], (unsigned long long)cand);
     }
     __syncthreads();
     uint32_t before = 0;

@@ -42,7 +42,9 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
     int n_pending = 0;                 // wave-uniform
     uint32_t n_updates = 0;            // wave-uniform
 
+    uint32_t n_cands = 0;              // wave-uniform: candidate blocks measured
     scan_lattice(fa.lat, &fa.cam, 1, fa.mc, [&](int bx, int by, int bz, uint32_t) {
+        ++n_cands;
         // first hash probe window, consumed only if the block is touched
         const unsigned long long key = pack_key(bx, by, bz);
         const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
         push_touched(dm, parity, sub, slot, pending, n_pending);
     });
     // one write per update: a single view updates a voxel at most once
-    finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates);
+    finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates, n_cands);
 }
 
 }  // namespace

@@ -43,7 +43,9 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     uint32_t n_updates = 0;   // voxel updates, one per voxel per view
     uint32_t n_writes = 0;    // voxels stored, one per voxel per launch
 
+    uint32_t n_cands = 0;     // candidate blocks measured (one per block per launch)
     scan_lattice(va.lat, va.cam, va.n_views, va.mc, [&](int bx, int by, int bz, uint32_t vmask) {
+        ++n_cands;
         const unsigned long long key = pack_key(bx, by, bz);
         const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
         const ProbeWindow w0 = load_window(dm, h, 0);
@@ -114,7 +116,7 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
     });
-    finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes);
+    finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes, n_cands);
 }
 
 // Arguments passed by value (eager launches).  Four waves per SIMD (two

@@ -56,7 +56,8 @@ enum Total : int {
     kTotalUpdates = 0,                               // kSubLists lines of voxel-update sub-totals
     kTotalWrites = kSubLists * kTotalsStride,        // kSubLists lines of voxel-write sub-totals
     kTotalTouched = 2 * kSubLists * kTotalsStride,   // touched blocks of completed earlier launches
-    kNumTotalWords = (2 * kSubLists + 1) * kTotalsStride
+    kTotalCandidates = (2 * kSubLists + 1) * kTotalsStride,   // kSubLists lines: candidate blocks measured
+    kNumTotalWords = (3 * kSubLists + 1) * kTotalsStride
 };
 
 enum ErrorBits : uint32_t {
@@ -135,6 +136,7 @@ struct Lattice {
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
     int chunk;              // 1 .. 64 * kWavesPerGroup lattice entries per workgroup pass
     int partitions;         // 1 or kPartitions ownership bands
+    int coarse;             // 1: two-level walk over super-blocks of 4^3 blocks (chunk counts super-blocks)
 };
 
 // Arguments of a single-frame launch.

@@ -34,7 +34,7 @@ class TsdfError(RuntimeError):
 class tsdf_stats(C.Structure):
     _fields_ = [("blocks", C.c_longlong), ("voxel_updates", C.c_longlong),
                 ("voxel_writes", C.c_longlong), ("touched_blocks", C.c_longlong),
-                ("launches", C.c_longlong)]
+                ("launches", C.c_longlong), ("candidate_blocks", C.c_longlong)]
 
 
 class tsdf_depth_view(C.Structure):

@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(t):
 def test_struct_layouts(t):
     assert C.sizeof(t.tsdf_depth_view) == 112
     assert C.sizeof(t.tsdf_lidar_model) == 32
-    assert C.sizeof(t.tsdf_stats) == 40
+    assert C.sizeof(t.tsdf_stats) == 48
 
 
 def test_params_struct_layout(t):
