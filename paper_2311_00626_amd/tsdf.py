@@ -203,8 +203,11 @@ class TsdfMap:
 
     @classmethod
     def from_params(cls, params, **kw) -> "TsdfMap":
-        return cls(params.voxel_size, params.truncation_vox, max_weight=params.max_weight,
-                   max_range=params.max_range, weighting=params.weighting, **kw)
+        """A map with the fields of `params` (synth.MapParams); keyword
+        arguments override them."""
+        args = dict(max_weight=params.max_weight, max_range=params.max_range, weighting=params.weighting)
+        args.update(kw)
+        return cls(params.voxel_size, params.truncation_vox, **args)
 
     @property
     def handle(self) -> C.c_void_p:
