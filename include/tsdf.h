@@ -245,8 +245,7 @@ TSDF_API const char *tsdf_strerror(int status);
  *               multiple of 8), 1 .. 65536;
  *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
  *               each XCD reads about 1/8 of every depth image;
- *   chunk       lattice blocks a workgroup culls per pass, in units of 64, 1 .. 8
- *               (automatic: the lattice shared evenly, one pass per workgroup);
+ *   chunk       lattice blocks a wave culls per pass, 1 .. 64;
  *   footprint   footprint culling: a pre-pass reduces every view to the
  *               largest valid measurement per 8/16/32/64-pixel tile, and a
  *               block is skipped when its nearest point lies beyond the

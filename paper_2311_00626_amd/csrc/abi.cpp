@@ -347,30 +347,19 @@ hipError_t use_device(const tsdf_map *m)
 // Image-band ownership per XCD (partitions = 8) cuts L2 fills but measured
 // slower on both regimes, so it is only used when asked for.  Fields of the
 // map's launch configuration override these choices.
-constexpr long long kCoarseLattice = 1ll << 17;   // lattices at least this large walk super-blocks first
-
 int schedule(const tsdf_map *m, Lattice &lat)
 {
     const tsdf_launch_config &lc = m->launch;
     long long max_groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
     max_groups = std::max<long long>(kPartitions, max_groups / kPartitions * kPartitions);
+    const long long full_waves = max_groups * kWavesPerGroup;
     const int parts = lc.partitions > 0 ? lc.partitions : 1;
-    lat.partitions = parts;
-    // two-level walk (super-blocks of 4^3 blocks) for large lattices
-    lat.coarse = lat.n_lat >= kCoarseLattice && parts == 1 && m->p.allocation != TSDF_ALLOC_RAY_WALK ? 1 : 0;
-    long long units = lat.n_lat;
-    if (lat.coarse)
-        units = (long long)((lat.lat_dim[0] + 3) / 4) * ((lat.lat_dim[1] + 3) / 4) * ((lat.lat_dim[2] + 3) / 4);
-    const long long per_band = max_groups / parts;
-    // units per workgroup pass: explicit (64 x chunk), or the units shared
-    // evenly over the workgroups of a band (one pass each)
-    long long span = lc.chunk > 0 ? 64ll * lc.chunk : (units + per_band - 1) / per_band;
-    span = std::max(1ll, std::min<long long>(span, 64ll * kWavesPerGroup));
-    lat.chunk = (int)span;
-    const long long n_chunks = (units + span - 1) / span;
-    long long groups = n_chunks * parts;
+    long long groups = (lat.n_lat + kWavesPerGroup - 1) / kWavesPerGroup;
     groups = (groups + kPartitions - 1) / kPartitions * kPartitions;
     groups = std::max<long long>(kPartitions, std::min<long long>(groups, max_groups));
+    const long long chunk = lc.chunk > 0 ? lc.chunk : (lat.n_lat > 4 * full_waves ? 8 : 1);
+    lat.chunk = (int)std::max(1ll, std::min<long long>(chunk, kMaxChunk));
+    lat.partitions = parts;
     return (int)groups;
 }
 
@@ -956,7 +945,6 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
     (void)schedule(m, lat);      // chunk and partitions for this lattice; the grid is fixed
     va.lat.chunk = lat.chunk;
     va.lat.partitions = lat.partitions;
-    va.lat.coarse = lat.coarse;
     hipError_t e = use_device(m);
     if (e == hipSuccess)
         e = prepare_footprint(m, va, nullptr, false);   // the graph builds the pyramids

@@ -209,9 +209,9 @@ __device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long lon
 // below -margin for some plane; the margin exceeds the binary32 error of any
 // voxel's projection, so no block holding an updated voxel is ever dropped.
 __device__ __forceinline__ bool lane_block_in_pinhole(const CameraView &cv, const MapConsts &mc, int bx, int by,
-                                                      int bz, int nb = 1)
+                                                      int bz)
 {
-    const float e = 8.0f * (float)nb * mc.vs;
+    const float e = 8.0f * mc.vs;
     const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
     const float x0 = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
     const float y0 = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
@@ -251,9 +251,9 @@ __device__ __forceinline__ bool lane_block_in_pinhole(const CameraView &cv, cons
 // it): z - |p| cos(phi_start) and -z + |p| cos(phi_end) are concave, so their
 // minimum over the box is at a corner.
 __device__ __forceinline__ bool lane_block_in_spherical(const CameraView &cv, const MapConsts &mc, int bx, int by,
-                                                        int bz, int nb = 1)
+                                                        int bz)
 {
-    const float e = 8.0f * (float)nb * mc.vs;
+    const float e = 8.0f * mc.vs;
     const float lo[3] = {(float)(8 * bx) * mc.vs, (float)(8 * by) * mc.vs, (float)(8 * bz) * mc.vs};
     float d2 = 0.0f;
 #pragma unroll
@@ -358,9 +358,9 @@ __device__ __forceinline__ float footprint_max(const CameraView &cv, int i0, int
 // rectangle is widened by 2 pixels, far beyond the binary32 error of either
 // projection.  Blocks reaching within 1 mm of the camera plane are kept.
 __device__ __forceinline__ bool lane_block_footprint_pinhole(const CameraView &cv, const MapConsts &mc, int bx,
-                                                             int by, int bz, int nb = 1)
+                                                             int by, int bz)
 {
-    const float e = 8.0f * (float)nb * mc.vs;
+    const float e = 8.0f * mc.vs;
     const float X = (float)(8 * bx) * mc.vs, Y = (float)(8 * by) * mc.vs, Z = (float)(8 * bz) * mc.vs;
     float zmin = 3.0e38f, umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
 #pragma unroll
@@ -399,12 +399,11 @@ __device__ __forceinline__ bool lane_block_footprint_pinhole(const CameraView &c
 // reaches the sensor are kept; so are those nearly reaching the z axis (all
 // azimuths), and, for a partial-circle sensor, those straddling azimuth +-pi.
 __device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView &cv, const MapConsts &mc, int bx,
-                                                               int by, int bz, int nb = 1)
+                                                               int by, int bz)
 {
-    const float e = 8.0f * (float)nb * mc.vs;
-    const float half = 4.0f * (float)nb;
-    const float X = ((float)(8 * bx) + half) * mc.vs, Y = ((float)(8 * by) + half) * mc.vs,
-                Z = ((float)(8 * bz) + half) * mc.vs;
+    const float e = 8.0f * mc.vs;
+    const float X = ((float)(8 * bx) + 4.0f) * mc.vs, Y = ((float)(8 * by) + 4.0f) * mc.vs,
+                Z = ((float)(8 * bz) + 4.0f) * mc.vs;
     const float x = cv.R[0] * X + cv.R[1] * Y + cv.R[2] * Z + cv.t[0];
     const float y = cv.R[3] * X + cv.R[4] * Y + cv.R[5] * Z + cv.t[1];
     const float z = cv.R[6] * X + cv.R[7] * Y + cv.R[8] * Z + cv.t[2];
@@ -463,19 +462,18 @@ __device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView 
     return !ok || Rc - rad <= dm + mc.eps + mc.margin_z;
 }
 
-// Culling of the box of nb x nb x nb blocks whose first block is (bx, by, bz)
-// against one view: false only when no voxel in the box can be updated.
-__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz,
-                                                   int nb = 1)
+// Culling of block (bx, by, bz) against one view: false only when no voxel
+// of the block can be updated.
+__device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
 {
     if (cv.model == kModelSpherical) {
-        if (!lane_block_in_spherical(cv, mc, bx, by, bz, nb))
+        if (!lane_block_in_spherical(cv, mc, bx, by, bz))
             return false;
-        return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz, nb);
+        return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz);
     }
-    if (!lane_block_in_pinhole(cv, mc, bx, by, bz, nb))
+    if (!lane_block_in_pinhole(cv, mc, bx, by, bz))
         return false;
-    return !cv.tiles || lane_block_footprint_pinhole(cv, mc, bx, by, bz, nb);
+    return !cv.tiles || lane_block_footprint_pinhole(cv, mc, bx, by, bz);
 }
 
 // Ownership band of a block (one per XCD): the image-column band of the
@@ -509,151 +507,35 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
     return (int)(lb % (uint32_t)kPartitions);
 }
 
-// Two-level walk for large lattices: the lattice is covered by super-blocks
-// of kSuper^3 blocks; a workgroup culls a chunk of lat.chunk super-blocks
-// (one per thread, the whole box against each view), then, kWavesPerGroup
-// surviving super-blocks at a time, each wave culls the blocks of one of them
-// (one per lane, only against the views that kept the super-block); the
-// surviving blocks are compacted in LDS and the waves take them round-robin.
-// A culled super-block holds no updatable voxel, so its blocks are skipped
-// without a test.  No partitions (P = 1) and no ray-walk marks.
-constexpr int kSuper = 4;
-
-template <class Body>
-__device__ __forceinline__ void scan_lattice_coarse(const Lattice &lat, const CameraView *cams, int n_views,
-                                                    const MapConsts &mc, uint32_t *s_block, uint32_t *s_mask,
-                                                    uint32_t &s_count, Body &&body)
-{
-    __shared__ uint32_t s_sup[64 * kWavesPerGroup];
-    __shared__ uint32_t s_supmask[64 * kWavesPerGroup];
-    __shared__ uint32_t s_nsup;
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1],
-                   dim_z = (uint32_t)lat.lat_dim[2];
-    const uint32_t sx = (dim_x + kSuper - 1) / kSuper, sy = (dim_y + kSuper - 1) / kSuper,
-                   sz = (dim_z + kSuper - 1) / kSuper;
-    const uint32_t n_sup = sx * sy * sz;
-    const uint32_t span = (uint32_t)lat.chunk;
-    const uint32_t n_chunks = (n_sup + span - 1) / span;
-    for (uint32_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-        if (threadIdx.x == 0)
-            s_nsup = 0;
-        __syncthreads();
-        const uint32_t sb = c * span + threadIdx.x;
-        uint32_t vmask = 0;
-        if (threadIdx.x < span && sb < n_sup) {
-            const uint32_t rest = sb / sx;
-            const int ox = lat.lat_min[0] + kSuper * (int)(sb - rest * sx);
-            const int oy = lat.lat_min[1] + kSuper * (int)(rest % sy);
-            const int oz = lat.lat_min[2] + kSuper * (int)(rest / sy);
-            for (int v = 0; v < n_views; ++v)
-                if (lane_block_in_view(cams[v], mc, ox, oy, oz, kSuper))
-                    vmask |= 1u << v;
-        }
-        const unsigned long long keep = __ballot(vmask != 0);
-        if (keep) {
-            uint32_t base = 0;
-            if (lane == 0)
-                base = atomicAdd(&s_nsup, (uint32_t)__popcll(keep));
-            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-            if (vmask) {
-                const uint32_t k = base + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull));
-                s_sup[k] = sb;
-                s_supmask[k] = vmask;
-            }
-        }
-        __syncthreads();
-        const uint32_t n_s = s_nsup;
-        for (uint32_t first = 0; first < n_s; first += kWavesPerGroup) {
-            if (threadIdx.x == 0)
-                s_count = 0;
-            __syncthreads();
-            const uint32_t k = first + (uint32_t)wave;
-            if (k < n_s) {
-                const uint32_t sbk = s_sup[k];
-                const uint32_t smask = s_supmask[k];
-                const uint32_t rest = sbk / sx;
-                const uint32_t x = kSuper * (sbk - rest * sx) + (uint32_t)(lane & 3);
-                const uint32_t y = kSuper * (rest % sy) + (uint32_t)((lane >> 2) & 3);
-                const uint32_t z = kSuper * (rest / sy) + (uint32_t)(lane >> 4);
-                uint32_t bmask = 0;
-                if (x < dim_x && y < dim_y && z < dim_z) {
-                    const int bx = lat.lat_min[0] + (int)x, by = lat.lat_min[1] + (int)y,
-                              bz = lat.lat_min[2] + (int)z;
-                    for (int v = 0; v < n_views; ++v)
-                        if (((smask >> v) & 1u) && lane_block_in_view(cams[v], mc, bx, by, bz))
-                            bmask |= 1u << v;
-                }
-                const unsigned long long bkeep = __ballot(bmask != 0);
-                if (bkeep) {
-                    uint32_t base = 0;
-                    if (lane == 0)
-                        base = atomicAdd(&s_count, (uint32_t)__popcll(bkeep));
-                    base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-                    if (bmask) {
-                        const uint32_t q = base + (uint32_t)__popcll(bkeep & ((1ull << lane) - 1ull));
-                        s_block[q] = x + dim_x * (y + dim_y * z);
-                        s_mask[q] = bmask;
-                    }
-                }
-            }
-            __syncthreads();
-            const uint32_t n = s_count;
-            for (uint32_t q = (uint32_t)wave; q < n; q += kWavesPerGroup) {
-                const uint32_t b = s_block[q];
-                const uint32_t rest = b / dim_x;
-                body(lat.lat_min[0] + (int)(b - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
-                     lat.lat_min[2] + (int)(rest / dim_y), s_mask[q]);
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Walks the launch's lattice with the whole workgroup.  The lattice is cut
-// into chunks of lat.chunk consecutive blocks (at most one per thread); a
-// workgroup takes one
-// chunk at a time (with P = lat.partitions bands, the P workgroups
-// blockIdx.x / P share each chunk and workgroup blockIdx.x mod P keeps the
-// blocks of its band).  Every thread culls one block of the chunk, the
-// survivors are compacted in LDS (one LDS atomic per wave), and the
-// workgroup's waves take them round-robin: body(bx, by, bz, view_mask) runs
-// wave-uniform on one block at a time.  Survivors of a chunk are thus spread
-// over all waves of the workgroup instead of queueing behind the wave that
-// culled them.  Every thread of the workgroup must call this (it holds
-// barriers); the chunk loop is uniform across the workgroup.
+// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
+// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
+// P = 8) scans all chunks; each lane bands and culls one block of a chunk of
+// lat.chunk consecutive lattice blocks, and the surviving blocks of this
+// partition are handed to body(bx, by, bz, view_mask) one at a time
+// (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
+// lattice block is a candidate exactly when marked.
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body)
 {
-    __shared__ uint32_t s_block[64 * kWavesPerGroup];
-    __shared__ uint32_t s_mask[64 * kWavesPerGroup];
-    __shared__ uint32_t s_count;
     const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
     const uint32_t P = (uint32_t)lat.partitions;
     const int part = (int)(blockIdx.x % P);
-    const uint32_t groups_pp = gridDim.x / P;
-    const uint32_t n_lat = (uint32_t)lat.n_lat;
-    const uint32_t span = (uint32_t)lat.chunk;
-    const uint32_t n_chunks = (n_lat + span - 1) / span;
+    const uint32_t waves_pp = (gridDim.x / P) * (uint32_t)kWavesPerGroup;
+    const uint32_t wave_pp = (blockIdx.x / P) * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6);
+    const uint32_t chunk = (uint32_t)lat.chunk;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    if (lat.coarse) {
-        scan_lattice_coarse(lat, cams, n_views, mc, s_block, s_mask, s_count, body);
-        return;
-    }
-    for (uint32_t c = blockIdx.x / P; c < n_chunks; c += groups_pp) {
-        if (threadIdx.x == 0)
-            s_count = 0;
-        __syncthreads();
-        const uint32_t lb = c * span + threadIdx.x;
+    const uint32_t n_lat = (uint32_t)lat.n_lat;
+    const uint32_t n_chunks = (n_lat + chunk - 1) / chunk;
+    for (uint32_t c = wave_pp; c < n_chunks; c += waves_pp) {
+        const uint32_t lb = c * chunk + (uint32_t)lane;
         uint32_t vmask = 0;
-        if (threadIdx.x < span && lb < n_lat) {
+        int bx = 0, by = 0, bz = 0;
+        if ((uint32_t)lane < chunk && lb < n_lat) {
             const uint32_t rest = lb / dim_x;
-            const int bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-            const int by = lat.lat_min[1] + (int)(rest % dim_y);
-            const int bz = lat.lat_min[2] + (int)(rest / dim_y);
+            bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+            by = lat.lat_min[1] + (int)(rest % dim_y);
+            bz = lat.lat_min[2] + (int)(rest / dim_y);
             if (cams[0].dda_marks)
                 vmask = cams[0].dda_marks[lb] ? 1u : 0u;     // ray-walk allocation: the walk decides
             else if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
@@ -661,27 +543,16 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
                     if (lane_block_in_view(cams[v], mc, bx, by, bz))
                         vmask |= 1u << v;
         }
-        const unsigned long long keep = __ballot(vmask != 0);
-        if (keep) {
-            uint32_t base = 0;
-            if (lane == 0)
-                base = atomicAdd(&s_count, (uint32_t)__popcll(keep));
-            base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
-            if (vmask) {
-                const uint32_t k = base + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull));
-                s_block[k] = lb;
-                s_mask[k] = vmask;
-            }
+        unsigned long long todo = __ballot(vmask != 0);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int sbx = __builtin_amdgcn_readlane(bx, src);
+            const int sby = __builtin_amdgcn_readlane(by, src);
+            const int sbz = __builtin_amdgcn_readlane(bz, src);
+            const uint32_t svm = (uint32_t)__builtin_amdgcn_readlane((int)vmask, src);
+            body(sbx, sby, sbz, svm);
         }
-        __syncthreads();
-        const uint32_t n = s_count;
-        for (uint32_t k = (uint32_t)wave; k < n; k += kWavesPerGroup) {
-            const uint32_t b = s_block[k];
-            const uint32_t rest = b / dim_x;
-            body(lat.lat_min[0] + (int)(b - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
-                 lat.lat_min[2] + (int)(rest / dim_y), s_mask[k]);
-        }
-        __syncthreads();
     }
 }
 

@@ -16,7 +16,7 @@ constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of 
 constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
 constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
 constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
-constexpr int kMaxChunk = 8;                        // lattice blocks a workgroup culls per pass, in 64s
+constexpr int kMaxChunk = 64;                       // lattice blocks culled together by one wave
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
 // Weighting functions (the tsdf_params weighting codes).
@@ -128,15 +128,14 @@ struct MapConsts {
     float margin_z;         // conservative slack of the near/far culling planes
 };
 
-// Block lattice scanned by one launch.  Workgroups cull `chunk` consecutive
-// lattice entries at a time, one per thread.
+// Block lattice scanned by one launch.  Waves cull `chunk` consecutive
+// lattice entries at a time, one per lane.
 struct Lattice {
     int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
-    int chunk;              // 1 .. 64 * kWavesPerGroup lattice entries per workgroup pass
+    int chunk;              // 1 .. kMaxChunk
     int partitions;         // 1 or kPartitions ownership bands
-    int coarse;             // 1: two-level walk over super-blocks of 4^3 blocks (chunk counts super-blocks)
 };
 
 // Arguments of a single-frame launch.
