@@ -257,8 +257,15 @@ TSDF_API const char *tsdf_strerror(int status);
 #define TSDF_FOOTPRINT_AUTO 0
 #define TSDF_FOOTPRINT_NEVER 1
 #define TSDF_FOOTPRINT_ALWAYS 2
+#define TSDF_COMPACT_AUTO 0
+#define TSDF_COMPACT_NEVER 1
+#define TSDF_COMPACT_ALWAYS 2
 typedef struct {
     int max_groups, partitions, chunk, footprint;
+    int compaction;   /* TSDF_COMPACT_*: a cull pre-pass compacts the surviving blocks into a list
+                         that the integration kernel deals out evenly to its waves (automatic for
+                         lattices of at least 65536 blocks; one band only, not with ray-walk
+                         allocation) */
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);
 

@@ -32,6 +32,8 @@ struct tsdf_map {
     float2 *sm_maps = nullptr;            // per-pixel (weight, truncation), kMaxViews slots
     unsigned char *walk_marks = nullptr;  // ray-walk allocation: one byte per lattice entry
     long long walk_cap = 0;
+    uint2 *cand = nullptr;                // compacted launches: candidate list
+    long long cand_cap = 0;
     long long sm_slot = 0;                // pixels per slot of sm_maps
     // kernel timing
     bool profiling;
@@ -133,6 +135,9 @@ void free_device(tsdf_map *m)
     (void)hipFree(m->walk_marks);
     m->walk_marks = nullptr;
     m->walk_cap = 0;
+    (void)hipFree(m->cand);
+    m->cand = nullptr;
+    m->cand_cap = 0;
 }
 
 void free_events(tsdf_map *m)
@@ -481,6 +486,46 @@ hipError_t prepare_learned(tsdf_map *m, CameraView *cams, int n_views, hipStream
     return e;
 }
 
+// Compacted launch policy: explicit, or automatic for large lattices; one
+// band only, and not with ray-walk marks (the marks are the candidates).
+constexpr long long kCompactAutoLattice = 1ll << 16;
+
+bool use_compaction(const tsdf_map *m, const Lattice &lat)
+{
+    if (m->p.allocation == TSDF_ALLOC_RAY_WALK || (m->launch.partitions > 1))
+        return false;
+    if (m->launch.compaction == TSDF_COMPACT_NEVER)
+        return false;
+    if (m->launch.compaction == TSDF_COMPACT_ALWAYS)
+        return true;
+    return lat.n_lat >= kCompactAutoLattice;
+}
+
+// Points the lattice at a candidate list large enough for every block of it.
+hipError_t prepare_compaction(tsdf_map *m, Lattice &lat)
+{
+    lat.cand = nullptr;
+    if (!use_compaction(m, lat))
+        return hipSuccess;
+    if (!m->cand || m->cand_cap < lat.n_lat) {
+        if (m->cand) {
+            hipError_t e = hipDeviceSynchronize();   // earlier launches may still read the old list
+            if (e != hipSuccess)
+                return e;
+        }
+        (void)hipFree(m->cand);
+        m->cand = nullptr;
+        m->cand_cap = 0;
+        const long long cap = std::max<long long>(lat.n_lat, 1ll << 18);
+        hipError_t e = hipMalloc((void **)&m->cand, sizeof(uint2) * (size_t)cap);
+        if (e != hipSuccess)
+            return e;
+        m->cand_cap = cap;
+    }
+    lat.cand = m->cand;
+    return hipSuccess;
+}
+
 // Ray-walk allocation: widens the lattice by one block on every side (the
 // walk stays inside the frustum, the margin absorbs binary32 rounding at its
 // ends), marks the visited blocks and points the view at the marks.
@@ -610,7 +655,7 @@ int create_map_ex(const tsdf_params *p, tsdf_map **out)
     if (p->weighting == TSDF_WEIGHT_LEARNED)
         m->eps = 8.0f * p->voxel_size_m;    // bound of every per-pixel truncation (culling only)
     m->max_groups = 512;   // a multiple of kPartitions
-    m->launch = tsdf_launch_config{0, 0, 0, 0};
+    m->launch = tsdf_launch_config{0, 0, 0, 0, 0};
     m->frames = 0;
     m->profiling = false;
     m->ev_used = 0;
@@ -695,10 +740,21 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
         e = prepare_walk(m, fa, T_world_cam, s);
     if (e != hipSuccess)
         return hip_status(e);
+    if (e == hipSuccess)
+        e = prepare_compaction(m, fa.lat);
+    if (e != hipSuccess)
+        return hip_status(e);
     const bool timed = timing_begin(m, s);
-    const int groups = schedule(m, fa.lat);
+    int groups = schedule(m, fa.lat);
     if (walk)
         fa.lat.partitions = 1;    // every lattice entry is read by exactly one thread
+    if (fa.lat.cand) {
+        groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
+                                                           kPartitions * kPartitions);
+        e = launch_cull_frame(m->dm, fa, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
     e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
@@ -737,10 +793,19 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
         e = prepare_footprint(m, fa, s);
     if (e == hipSuccess)
         e = prepare_learned(m, &fa.cam, 1, s);
+    if (e == hipSuccess)
+        e = prepare_compaction(m, fa.lat);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
-    const int groups = schedule(m, fa.lat);
+    int groups = schedule(m, fa.lat);
+    if (fa.lat.cand) {
+        groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
+                                                           kPartitions * kPartitions);
+        e = launch_cull_frame(m->dm, fa, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
     e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
@@ -862,10 +927,19 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
         e = prepare_footprint(m, va, s, true);
     if (e == hipSuccess)
         e = prepare_learned(m, va.cam, va.n_views, s);
+    if (e == hipSuccess)
+        e = prepare_compaction(m, va.lat);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
-    const int groups = schedule(m, va.lat);
+    int groups = schedule(m, va.lat);
+    if (va.lat.cand) {
+        groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
+                                                           kPartitions * kPartitions);
+        e = launch_cull_views(m->dm, va, s);
+        if (e != hipSuccess)
+            return hip_status(e);
+    }
     e = launch_integrate_views(m->dm, va, m->p.weighting, groups, s);
     if (e != hipSuccess)
         return hip_status(e);
@@ -907,6 +981,8 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
             hipError_t e1 = hipMemcpyAsync(st->dev[k], st->pinned[k], sizeof(ViewsArgs), hipMemcpyHostToDevice, cs);
             if (e1 == hipSuccess)
                 e1 = launch_footprint_tiles_dev(st->dev[k], cs);
+            if (e1 == hipSuccess)
+                e1 = launch_cull_views_dev(m->dm, st->dev[k], 1024, cs);
             hipError_t e2 = e1 == hipSuccess ? launch_integrate_views_dev(m->dm, st->dev[k], st->spherical,
                                                                           m->p.weighting, st->groups, cs)
                                              : e1;
@@ -948,6 +1024,8 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
     hipError_t e = use_device(m);
     if (e == hipSuccess)
         e = prepare_footprint(m, va, nullptr, false);   // the graph builds the pyramids
+    if (e == hipSuccess)
+        e = prepare_compaction(m, va.lat);              // and culls into the list
     if (e != hipSuccess)
         return hip_status(e);
     const int k = st->next;
@@ -1136,12 +1214,14 @@ int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *lc)
 {
     if (!m)
         return TSDF_EINVAL;
-    tsdf_launch_config c = {0, 0, 0, 0};
+    tsdf_launch_config c = {0, 0, 0, 0, 0};
     if (lc)
         c = *lc;
     if (c.max_groups < 0 || c.max_groups > 65536 || c.chunk < 0 || c.chunk > kMaxChunk ||
         (c.footprint != TSDF_FOOTPRINT_AUTO && c.footprint != TSDF_FOOTPRINT_NEVER &&
          c.footprint != TSDF_FOOTPRINT_ALWAYS) ||
+        (c.compaction != TSDF_COMPACT_AUTO && c.compaction != TSDF_COMPACT_NEVER &&
+         c.compaction != TSDF_COMPACT_ALWAYS) ||
         (c.partitions != 0 && c.partitions != 1 && c.partitions != kPartitions))
         return TSDF_EINVAL;
     m->launch = c;

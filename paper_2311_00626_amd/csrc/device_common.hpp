@@ -810,6 +810,69 @@ __device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
         if (prev != 0)
             atomicAdd(&dm.totals[kTotalTouched], (unsigned long long)prev);
     }
+    // the candidate count of the other parity is next used by the following
+    // launch's cull kernel, which runs after this launch
+    if (blockIdx.x == 0 && threadIdx.x == kSubLists)
+        atomicExch(&dm.counters[cand_counter(parity ^ 1)], 0u);
+}
+
+// Cull kernel of a compacted launch: every thread culls lattice blocks
+// (grid-stride) against the views; each wave appends its survivors
+// (lattice index, view mask) to lat.cand with one atomic on the launch's
+// candidate counter.
+__device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice &lat, const CameraView *cams,
+                                             int n_views, const MapConsts &mc, int parity)
+{
+    const int lane = lane_id();
+    const uint32_t n_lat = (uint32_t)lat.n_lat;
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+    // the loop runs the same number of times in every lane of a wave
+    const uint32_t wave_first = first - (uint32_t)lane;
+    for (uint32_t base = wave_first; base < n_lat; base += stride) {
+        const uint32_t lb = base + (uint32_t)lane;
+        uint32_t vmask = 0;
+        if (lb < n_lat) {
+            const uint32_t rest = lb / dim_x;
+            const int bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+            const int by = lat.lat_min[1] + (int)(rest % dim_y);
+            const int bz = lat.lat_min[2] + (int)(rest / dim_y);
+            for (int v = 0; v < n_views; ++v)
+                if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                    vmask |= 1u << v;
+        }
+        const unsigned long long keep = __ballot(vmask != 0);
+        if (keep) {
+            uint32_t at = 0;
+            if (lane == 0)
+                at = atomicAdd(&dm.counters[cand_counter(parity)], (uint32_t)__popcll(keep));
+            at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
+            if (vmask)
+                lat.cand[at + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull))] = make_uint2(lb, vmask);
+        }
+    }
+}
+
+// List walk of a compacted launch: the waves of the grid take the
+// candidates round-robin (wave-uniform) and hand each to body(bx, by, bz,
+// view_mask).  The count was written by the cull kernel earlier on the stream.
+template <class Body>
+__device__ __forceinline__ void scan_list(const DeviceMap &dm, const Lattice &lat, int parity, Body &&body)
+{
+    const uint32_t n = __hip_atomic_load(&dm.counters[cand_counter(parity)], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
+    const uint32_t waves = gridDim.x * (uint32_t)kWavesPerGroup;
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    for (uint32_t i = blockIdx.x * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6); i < count; i += waves) {
+        const uint2 e = lat.cand[i];
+        const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.x);
+        const uint32_t vmask = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.y);
+        const uint32_t rest = lb / dim_x;
+        body(lat.lat_min[0] + (int)(lb - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
+             lat.lat_min[2] + (int)(rest / dim_y), vmask);
+    }
 }
 
 }  // namespace dev

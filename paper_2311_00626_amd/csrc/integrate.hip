@@ -28,8 +28,10 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING, int STORAGE, int SPHERICAL>
-__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa)
+// LIST: the candidates come from the cull kernel's list (compacted launch)
+// instead of this kernel's own walk of the lattice.
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool LIST>
+__device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const FrameArgs &fa)
 {
     const int lane = lane_id();
     const int lx = lane & 7;
@@ -43,7 +45,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
     uint32_t n_updates = 0;            // wave-uniform
 
     uint32_t n_cands = 0;              // wave-uniform: candidate blocks measured
-    scan_lattice(fa.lat, &fa.cam, 1, fa.mc, [&](int bx, int by, int bz, uint32_t) {
+    auto block = [&](int bx, int by, int bz, uint32_t) {
         ++n_cands;
         // first hash probe window, consumed only if the block is touched
         const unsigned long long key = pack_key(bx, by, bz);
@@ -82,22 +84,58 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(De
             IO::store(blk, off[s], dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
-    });
+    };
+    if constexpr (LIST)
+        scan_list(dm, fa.lat, parity, block);
+    else
+        scan_lattice(fa.lat, &fa.cam, 1, fa.mc, block);
     // one write per update: a single view updates a voxel at most once
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates, n_cands);
 }
 
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_kernel(DeviceMap dm, FrameArgs fa)
+{
+    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, false>(dm, fa);
+}
+
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kernel(DeviceMap dm, FrameArgs fa)
+{
+    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, fa);
+}
+
+__global__ __launch_bounds__(256) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
+{
+    cull_to_list(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity);
+}
+
 }  // namespace
+
+hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream)
+{
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((fa.lat.n_lat + 255) / 256, 2048));
+    hipLaunchKernelGGL(cull_frame_kernel, dim3(groups), dim3(256), 0, stream, dm, fa);
+    return hipGetLastError();
+}
 
 template <int WEIGHTING, int SPHERICAL>
 static void launch_depth_storage(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
 {
-    if (dm.storage == 1)
+    if (fa.lat.cand) {
+        if (dm.storage == 1)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
+                               stream, dm, fa);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
+                               stream, dm, fa);
+    } else if (dm.storage == 1) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0, stream,
                            dm, fa);
-    else
+    } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0, stream,
                            dm, fa);
+    }
 }
 
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,

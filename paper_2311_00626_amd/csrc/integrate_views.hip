@@ -28,7 +28,8 @@ namespace {
 
 using namespace dev;
 
-template <int WEIGHTING, int STORAGE, int SPHERICAL>
+// LIST: candidates from the cull kernel's list instead of the lattice walk.
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool LIST>
 __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const ViewsArgs &va)
 {
     const int lane = lane_id();
@@ -44,7 +45,7 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     uint32_t n_writes = 0;    // voxels stored, one per voxel per launch
 
     uint32_t n_cands = 0;     // candidate blocks measured (one per block per launch)
-    scan_lattice(va.lat, va.cam, va.n_views, va.mc, [&](int bx, int by, int bz, uint32_t vmask) {
+    auto block = [&](int bx, int by, int bz, uint32_t vmask) {
         ++n_cands;
         const unsigned long long key = pack_key(bx, by, bz);
         const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
@@ -115,7 +116,11 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
             IO::store(blk, ((any >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
         }
         push_touched(dm, parity, sub, slot, pending, n_pending);
-    });
+    };
+    if constexpr (LIST)
+        scan_list(dm, va.lat, parity, block);
+    else
+        scan_lattice(va.lat, va.cam, va.n_views, va.mc, block);
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes, n_cands);
 }
 
@@ -124,29 +129,80 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
 __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_kernel(DeviceMap dm, ViewsArgs va)
 {
-    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, va);
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, false>(dm, va);
+}
+
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_list_kernel(DeviceMap dm, ViewsArgs va)
+{
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, va);
 }
 
 // Arguments read from device memory (graph replays: the host rewrites them
-// between replays through a captured copy).
+// between replays through a captured copy).  A replay holds both the walking
+// and the list kernel; the one the arguments do not select exits at once.
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
 __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_kernel_dev(DeviceMap dm,
                                                                                   const ViewsArgs *__restrict__ va)
 {
-    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL>(dm, *va);
+    if (va->lat.cand)
+        return;
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, false>(dm, *va);
+}
+
+template <int WEIGHTING, int STORAGE, int SPHERICAL>
+__global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_list_kernel_dev(
+    DeviceMap dm, const ViewsArgs *__restrict__ va)
+{
+    if (!va->lat.cand)
+        return;
+    integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, *va);
+}
+
+__global__ __launch_bounds__(256) void cull_views_kernel(DeviceMap dm, ViewsArgs va)
+{
+    cull_to_list(dm, va.lat, va.cam, va.n_views, va.mc, va.parity);
+}
+
+__global__ __launch_bounds__(256) void cull_views_kernel_dev(DeviceMap dm, const ViewsArgs *__restrict__ va)
+{
+    if (!va->lat.cand)
+        return;
+    cull_to_list(dm, va->lat, va->cam, va->n_views, va->mc, va->parity);
 }
 
 }  // namespace
 
+hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream)
+{
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((va.lat.n_lat + 255) / 256, 2048));
+    hipLaunchKernelGGL(cull_views_kernel, dim3(groups), dim3(256), 0, stream, dm, va);
+    return hipGetLastError();
+}
+
+hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, hipStream_t stream)
+{
+    hipLaunchKernelGGL(cull_views_kernel_dev, dim3((unsigned)groups), dim3(256), 0, stream, dm, va_dev);
+    return hipGetLastError();
+}
+
 template <int WEIGHTING, int SPHERICAL>
 static void launch_views_storage(const DeviceMap &dm, const ViewsArgs &va, dim3 grid, dim3 block, hipStream_t stream)
 {
-    if (dm.storage == 1)
+    if (va.lat.cand) {
+        if (dm.storage == 1)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
+                               stream, dm, va);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
+                               stream, dm, va);
+    } else if (dm.storage == 1) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0, stream,
                            dm, va);
-    else
+    } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0, stream,
                            dm, va);
+    }
 }
 
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
@@ -174,16 +230,23 @@ hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int 
     return hipGetLastError();
 }
 
+// Both the walking and the list kernel (each returns at once unless the
+// replay's arguments select it).
 template <int WEIGHTING, int SPHERICAL>
 static void launch_views_dev_storage(const DeviceMap &dm, const ViewsArgs *va, dim3 grid, dim3 block,
                                      hipStream_t stream)
 {
-    if (dm.storage == 1)
+    if (dm.storage == 1) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
                            stream, dm, va);
-    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
+                           stream, dm, va);
+    } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
                            stream, dm, va);
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
+                           stream, dm, va);
+    }
 }
 
 hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,

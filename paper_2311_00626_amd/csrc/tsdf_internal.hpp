@@ -45,8 +45,13 @@ enum Counter : int {
     kNumBlocks = 0,                                  // pool slots handed out (may exceed capacity after overflow)
     kErrorBits = 1 * kLineWords,                     // sticky ErrorBits
     kTouchedBase = 2 * kLineWords,                   // [parity][sub-list] touched counts
-    kNumCounterWords = (2 + 2 * kSubLists) * kLineWords
+    kCandBase = (2 + 2 * kSubLists) * kLineWords,    // [parity] candidate-list lengths (compacted launches)
+    kNumCounterWords = (4 + 2 * kSubLists) * kLineWords
 };
+__host__ __device__ constexpr int cand_counter(int parity)
+{
+    return kCandBase + parity * kLineWords;
+}
 __host__ __device__ constexpr int touched_counter(int parity, int sub)
 {
     return kTouchedBase + (parity * kSubLists + sub) * kLineWords;
@@ -136,6 +141,10 @@ struct Lattice {
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
     int chunk;              // 1 .. kMaxChunk
     int partitions;         // 1 or kPartitions ownership bands
+    // Compacted launches: a cull kernel writes the surviving blocks (lattice
+    // index, view mask) here and the integration kernel deals them out to its
+    // waves; nullptr: the integration kernel walks the lattice itself.
+    uint2 *cand;
 };
 
 // Arguments of a single-frame launch.
@@ -193,6 +202,12 @@ hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long 
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
                               hipStream_t stream);
+// Compacted launches (integrate.hip, integrate_views.hip): the cull kernels
+// fill lat.cand; the list kernels integrate its entries.
+hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream);
+hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream);
+hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, hipStream_t stream);
+
 // Ray-walk allocation pre-pass (dda.hip).
 struct DdaArgs {
     float Rwc[9];           // world-from-camera rotation, row-major

@@ -62,10 +62,12 @@ def lidar_struct(lidar) -> tsdf_lidar_model:
 
 MAX_VIEWS = 16
 FOOTPRINT = {"auto": 0, "never": 1, "always": 2}
+COMPACTION = {"auto": 0, "never": 1, "always": 2}
 
 
 class tsdf_launch_config(C.Structure):
-    _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("footprint", C.c_int)]
+    _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("footprint", C.c_int),
+                ("compaction", C.c_int)]
 
 
 class tsdf_params(C.Structure):
@@ -325,10 +327,10 @@ class TsdfMap:
         return b.cpu().numpy(), d.cpu().numpy(), w.cpu().numpy()
 
     def set_launch_config(self, max_groups: int = 0, partitions: int = 0, chunk: int = 0,
-                          footprint: str = "auto") -> None:
+                          footprint: str = "auto", compaction: str = "auto") -> None:
         """Launch shape of the integration kernels (0 = automatic); footprint
-        culling "auto", "never" or "always"."""
-        c = tsdf_launch_config(max_groups, partitions, chunk, FOOTPRINT[footprint])
+        culling and compacted launches "auto", "never" or "always"."""
+        c = tsdf_launch_config(max_groups, partitions, chunk, FOOTPRINT[footprint], COMPACTION[compaction])
         _check(lib.tsdf_set_launch_config(self._h, C.byref(c)), "tsdf_set_launch_config")
 
     # -- kernel timing -------------------------------------------------------
