@@ -1,12 +1,14 @@
 """Launch-shape autotuner for the integration kernels.
 
 The kernels walk the block lattice of a frame (or of a batch of views) with a
-persistent grid.  Four knobs shape that walk (tsdf_set_launch_config in the C
+persistent grid.  Five knobs shape that walk (tsdf_set_launch_config in the C
 ABI): the number of workgroups per launch, the number of consecutive lattice
 blocks a wave culls at once, one per lane (the chunk), whether workgroups are
-banded over image columns (partitions), and whether blocks are also culled
-against a per-view pyramid of tile depth maxima (footprint).  None of them
-changes a result: every configuration leaves a bit-identical map.  Which one
+banded over image columns (partitions), whether blocks are also culled
+against a per-view pyramid of tile depth maxima (footprint), and whether a
+cull pass first compacts the surviving blocks into a list that the waves then
+share evenly (compaction; chunk and partitions do not apply to it).  None of
+them changes a result: every configuration leaves a bit-identical map.  Which one
 is fastest depends on the sensor sizes, the voxel size and the batch, so the
 tuner measures the candidates on a few steps of the caller's own workload,
 timing the integration launches with the library's HIP events, and keeps the
@@ -34,13 +36,18 @@ class LaunchConfig:
     partitions: int = 0      # 0 = library default (1)
     chunk: int = 0           # 0 = automatic from the lattice size
     footprint: str = "auto"  # footprint culling: auto, never, always
+    compaction: str = "auto"  # compacted launch: auto, never, always
 
     def apply(self, m) -> None:
-        m.set_launch_config(self.max_groups, self.partitions, self.chunk, self.footprint)
+        m.set_launch_config(self.max_groups, self.partitions, self.chunk, self.footprint, self.compaction)
 
 
 def default_candidates() -> List[LaunchConfig]:
-    return [LaunchConfig(g, p, c, f) for g in GROUPS for p in PARTITIONS for c in CHUNKS for f in FOOTPRINTS]
+    """The lattice-walk grid, then the compacted launches (grid size and
+    footprint culling only)."""
+    walk = [LaunchConfig(g, p, c, f, "never") for g in GROUPS for p in PARTITIONS for c in CHUNKS
+            for f in FOOTPRINTS]
+    return walk + [LaunchConfig(g, 1, 0, f, "always") for g in GROUPS for f in FOOTPRINTS]
 
 
 @dataclass
