@@ -98,10 +98,21 @@ def candidates(m) -> int:
     return m.full_stats()["candidate_blocks"]
 
 
+def region_events():
+    """Start/stop events for a timed region on the current stream, the stream
+    every launch of the region goes to."""
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
 def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int,
                 setup=None, **map_kw) -> dict:
     """One integrate_depth launch per frame over `steps` frames (cycling the
-    sequence) after `warmup` untimed ones; HIP events around each launch."""
+    sequence) after `warmup` untimed ones.  One HIP event pair on the launch
+    stream brackets the timed region; the mean launch duration is its time over
+    the launches (it includes the gap between consecutive launches, so it bounds
+    the kernel's own duration from above; per-launch events would add several
+    microseconds of their own to every launch)."""
     import torch
     from paper_2311_00626_amd.tsdf import TsdfMap
     n_frames = frames.shape[0]
@@ -115,15 +126,16 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     torch.cuda.synchronize()
     b0, u0, _, t0_ = counters(m)
     c0 = candidates(m)
-    m.profile(True)
+    ev = region_events()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    ev[0].record()
     for k in range(warmup, warmup + steps):
         m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    ev[1].record()
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    kernel_ms, launches = m.profile_read()
-    m.profile(False)
+    kernel_ms, launches = ev[0].elapsed_time(ev[1]), steps
     b1, u1, _, t1_ = counters(m)
     assert m.status() == 0, "map overflowed"
     alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, steps, 4 if storage == "fp16" else 8) / steps
@@ -152,7 +164,8 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
                         "candidate_blocks_per_frame": r["candidates"] / min(steps, 290),
                         "roofline": {"bound": "hbm", "achieved": r["achieved"], "peak": HBM_PEAK_GBS,
                                      "unit": "GB/s", "frac": r["achieved"] / HBM_PEAK_GBS,
-                                     "kernel": f"integrate_depth_kernel<{storage}>",
+                                     "kernel": f"integrate_depth<{storage}> per frame (footprint and cull "
+                                               "pre-passes included on lattices large enough to use them)",
                                      "kernel_ms_mean": r["kernel_s"] * 1e3,
                                      "algorithmic_bytes_per_launch": r["alg_per_launch"]}}
     del frames
@@ -167,7 +180,7 @@ def walk_leg(w, frames, poses, steps: int, warmup: int) -> dict:
             "value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
             "frames_per_s": steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
             "blocks_allocated": r["blocks"], "kernel_ms_mean": r["kernel_s"] * 1e3,
-            "note": "ms_per_step includes the per-pixel walk kernel; kernel_ms_mean is the integration kernel"}
+            "note": "kernel_ms_mean is GPU time per frame: the per-pixel walk and the integration kernel"}
 
 
 def learned_leg(w, frames, poses, steps: int, warmup: int) -> dict:
@@ -183,7 +196,7 @@ def learned_leg(w, frames, poses, steps: int, warmup: int) -> dict:
            "value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
            "frames_per_s": steps / r["elapsed"], "ms_per_step": r["elapsed"] / steps * 1e3,
            "kernel_ms_mean": r["kernel_s"] * 1e3,
-           "note": "ms_per_step includes the per-pixel inference pre-pass"}
+           "note": "kernel_ms_mean is GPU time per frame: the per-pixel inference pre-pass and the integration kernel"}
     vs = 0.02
     room = sm.prepare_room(1000, 24, synth_cam_640(), vs, window=8)
     n = 30
@@ -248,16 +261,17 @@ def rig_leg(n_steps: int, warmup: int):
         step.run(*data[k])
     torch.cuda.synchronize()
     st0 = m.full_stats()
-    m.profile(True)
+    ev = region_events()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     timed = range(min(warmup, n_steps), n_steps)
+    ev[0].record()
     for k in timed:
         step.run(*data[k])
+    ev[1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t_start
-    kms, kl = m.profile_read()
-    m.profile(False)
+    kms, kl = ev[0].elapsed_time(ev[1]), len(timed)
     st1 = m.full_stats()
     step.close()
     assert m.status() == 0, "map overflowed"
@@ -346,15 +360,16 @@ def main():
         mb.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
         torch.cuda.synchronize()
         bb0, ub0, wb0, tb0 = counters(mb)
-        mb.profile(True)
+        ev = region_events()
         torch.cuda.synchronize()
         tb_start = time.perf_counter()
+        ev[0].record()
         for a in range(first, n_frames, B):
             mb.integrate_depth_views([frames[k] for k in range(a, a + B)], [K] * B, poses[a:a + B])
+        ev[1].record()
         torch.cuda.synchronize()
         tb_end = time.perf_counter()
-        kms, kl = mb.profile_read()
-        mb.profile(False)
+        kms, kl = ev[0].elapsed_time(ev[1]), len(range(first, n_frames, B))
         bb1, ub1, wb1, tb1 = counters(mb)
         assert mb.status() == 0, "map overflowed"
         nfb = n_frames - first

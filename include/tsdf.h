@@ -251,7 +251,7 @@ TSDF_API const char *tsdf_strerror(int status);
  *               block is skipped when its nearest point lies beyond the
  *               largest measurement under its image footprint plus epsilon
  *               (no voxel of it can be updated).  TSDF_FOOTPRINT_AUTO uses it
- *               for launches whose block lattice has at least 65536 blocks;
+ *               for launches whose block lattice has at least 16384 blocks;
  *               views larger than 4096 pixels a side are never culled this way.
  * NULL restores the automatic choice.  Errors: TSDF_EINVAL. */
 #define TSDF_FOOTPRINT_AUTO 0
@@ -264,7 +264,7 @@ typedef struct {
     int max_groups, partitions, chunk, footprint;
     int compaction;   /* TSDF_COMPACT_*: a cull pre-pass compacts the surviving blocks into a list
                          that the integration kernel deals out evenly to its waves (automatic for
-                         lattices of at least 65536 blocks; one band only, not with ray-walk
+                         lattices of at least 16384 blocks; one band only, not with ray-walk
                          allocation) */
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);

@@ -371,7 +371,7 @@ int schedule(const tsdf_map *m, Lattice &lat)
 // Footprint culling policy for one launch: explicit, or automatic when the
 // lattice is large enough for the culled measurement work to outweigh the
 // pyramid pass.
-constexpr long long kFootprintAutoLattice = 1ll << 16;
+constexpr long long kFootprintAutoLattice = 1ll << 14;
 
 bool use_footprint(const tsdf_map *m, const Lattice &lat)
 {
@@ -488,7 +488,7 @@ hipError_t prepare_learned(tsdf_map *m, CameraView *cams, int n_views, hipStream
 
 // Compacted launch policy: explicit, or automatic for large lattices; one
 // band only, and not with ray-walk marks (the marks are the candidates).
-constexpr long long kCompactAutoLattice = 1ll << 16;
+constexpr long long kCompactAutoLattice = 1ll << 14;
 
 bool use_compaction(const tsdf_map *m, const Lattice &lat)
 {
@@ -738,8 +738,6 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
         e = prepare_learned(m, &fa.cam, 1, s);
     if (e == hipSuccess)
         e = prepare_walk(m, fa, T_world_cam, s);
-    if (e != hipSuccess)
-        return hip_status(e);
     if (e == hipSuccess)
         e = prepare_compaction(m, fa.lat);
     if (e != hipSuccess)

@@ -141,9 +141,17 @@ def _check(status: int, where: str) -> None:
         raise TsdfError(status, where)
 
 
-def _stream_ptr(stream: Optional[torch.cuda.Stream]) -> int:
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return s.cuda_stream
+_RAW_STREAM = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
+def _stream_ptr(stream: Optional[torch.cuda.Stream], device: Optional[int] = None) -> int:
+    """HIP stream handle: `stream`, else torch's current stream on `device`
+    (the current device if None)."""
+    if stream is not None:
+        return stream.cuda_stream
+    if _RAW_STREAM is not None:      # a plain integer, without building a Stream object
+        return _RAW_STREAM(torch.cuda.current_device() if device is None else device)
+    return torch.cuda.current_stream(device).cuda_stream
 
 
 def _host_f32(a, n: int) -> np.ndarray:
@@ -236,7 +244,7 @@ class TsdfMap:
         Th = _host_f32(T_world_cam, 16)
         H, W = depth.shape
         st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
-                                 _stream_ptr(stream))
+                                 _stream_ptr(stream, depth.get_device()))
         _check(st, "integrate_depth")
 
     def integrate_range(self, rng: torch.Tensor, lidar, T_world_sensor,
