@@ -183,13 +183,15 @@ typedef struct {
  * the views.  Only enqueues work; errors as integrate_depth. */
 TSDF_API int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views, void *hip_stream);
 
-/* A batched step replayed from a hipGraph.  tsdf_step_create captures, once,
+/* A batched step replayed from a hipGraph.  A step holds graphs of
  * [a copy of the step's launch arguments from pinned host memory to device
- * memory] + [the integrate_depth_views kernel reading them] into two
- * instantiated graphs used alternately.  tsdf_step_run validates the views,
- * writes the arguments and launches one graph on hip_stream: the same result
- * as integrate_depth_views, with one graph launch as the only per-step
- * submission.  with_spherical must be nonzero for steps holding range images.
+ * memory] + [the kernels of integrate_depth_views reading them: footprint
+ * pre-pass, cull kernel and integration kernel, as the launch shape selects]
+ * for two staging slots used alternately; each variant is captured and
+ * instantiated on its first use (tsdf_step_create captures the plain one).
+ * tsdf_step_run validates the views, writes the arguments and launches one
+ * graph on hip_stream: the same result as integrate_depth_views, with one
+ * graph launch as the only per-step submission.  with_spherical must be nonzero for steps holding range images.
  * A step belongs to its map and must be destroyed before it; runs on one map
  * must be ordered on one stream.  tsdf_step_run may wait for the replay before
  * last to finish (it reuses that one's staging slot). */
@@ -263,8 +265,8 @@ TSDF_API const char *tsdf_strerror(int status);
 typedef struct {
     int max_groups, partitions, chunk, footprint;
     int compaction;   /* TSDF_COMPACT_*: a cull pre-pass compacts the surviving blocks into a list
-                         that the integration kernel deals out evenly to its waves (automatic for
-                         lattices of at least 16384 blocks; one band only, not with ray-walk
+                         that the integration kernel deals out evenly to its waves (automatic once
+                         lattice blocks x views reach 16384; one band only, not with ray-walk
                          allocation) */
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);

@@ -486,11 +486,12 @@ hipError_t prepare_learned(tsdf_map *m, CameraView *cams, int n_views, hipStream
     return e;
 }
 
-// Compacted launch policy: explicit, or automatic for large lattices; one
-// band only, and not with ray-walk marks (the marks are the candidates).
-constexpr long long kCompactAutoLattice = 1ll << 14;
+// Compacted launch policy: explicit, or automatic once the culling work
+// (lattice blocks x views) is large; one band only, and not with ray-walk
+// marks (the marks are the candidates).
+constexpr long long kCompactAutoWork = 1ll << 14;
 
-bool use_compaction(const tsdf_map *m, const Lattice &lat)
+bool use_compaction(const tsdf_map *m, const Lattice &lat, int n_views)
 {
     if (m->p.allocation == TSDF_ALLOC_RAY_WALK || (m->launch.partitions > 1))
         return false;
@@ -498,14 +499,14 @@ bool use_compaction(const tsdf_map *m, const Lattice &lat)
         return false;
     if (m->launch.compaction == TSDF_COMPACT_ALWAYS)
         return true;
-    return lat.n_lat >= kCompactAutoLattice;
+    return lat.n_lat * n_views >= kCompactAutoWork;
 }
 
 // Points the lattice at a candidate list large enough for every block of it.
-hipError_t prepare_compaction(tsdf_map *m, Lattice &lat)
+hipError_t prepare_compaction(tsdf_map *m, Lattice &lat, int n_views)
 {
     lat.cand = nullptr;
-    if (!use_compaction(m, lat))
+    if (!use_compaction(m, lat, n_views))
         return hipSuccess;
     if (!m->cand || m->cand_cap < lat.n_lat) {
         if (m->cand) {
@@ -739,7 +740,7 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     if (e == hipSuccess)
         e = prepare_walk(m, fa, T_world_cam, s);
     if (e == hipSuccess)
-        e = prepare_compaction(m, fa.lat);
+        e = prepare_compaction(m, fa.lat, 1);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -792,7 +793,7 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
     if (e == hipSuccess)
         e = prepare_learned(m, &fa.cam, 1, s);
     if (e == hipSuccess)
-        e = prepare_compaction(m, fa.lat);
+        e = prepare_compaction(m, fa.lat, 1);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -871,14 +872,20 @@ int build_views_args(tsdf_map *m, const tsdf_depth_view *views, int n_views, Vie
 // step's launch arguments from a pinned staging slot to device memory] +
 // [the batched integration kernel reading them], used alternately so that a
 // slot is rewritten only after its previous replay has finished.
+// Graph variants of a step, captured on first use: bit 0 = footprint
+// pre-pass, bit 1 = compacted launch (cull kernel + list kernel).
+constexpr int kStepFootprint = 1;
+constexpr int kStepCompact = 2;
+constexpr int kStepModes = 4;
+
 struct tsdf_step {
     tsdf_map *m;
     bool spherical;
     int groups;
     ViewsArgs *pinned[2];
     ViewsArgs *dev[2];
-    hipGraph_t graph[2];
-    hipGraphExec_t exec[2];
+    hipGraph_t graph[2][kStepModes];
+    hipGraphExec_t exec[2][kStepModes];
     hipEvent_t done[2];
     bool pending[2];
     int next;
@@ -887,10 +894,12 @@ struct tsdf_step {
 static void step_free(tsdf_step *st)
 {
     for (int k = 0; k < 2; ++k) {
-        if (st->exec[k])
-            (void)hipGraphExecDestroy(st->exec[k]);
-        if (st->graph[k])
-            (void)hipGraphDestroy(st->graph[k]);
+        for (int mode = 0; mode < kStepModes; ++mode) {
+            if (st->exec[k][mode])
+                (void)hipGraphExecDestroy(st->exec[k][mode]);
+            if (st->graph[k][mode])
+                (void)hipGraphDestroy(st->graph[k][mode]);
+        }
         if (st->done[k])
             (void)hipEventDestroy(st->done[k]);
         if (st->pinned[k])
@@ -899,6 +908,34 @@ static void step_free(tsdf_step *st)
             (void)hipFree(st->dev[k]);
     }
     delete st;
+}
+
+// Captures the replay of staging slot k in one mode: the argument upload,
+// then only the kernels of that mode, all reading the uploaded arguments.
+static hipError_t step_capture(tsdf_step *st, int k, int mode)
+{
+    tsdf_map *m = st->m;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return e;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = hipMemcpyAsync(st->dev[k], st->pinned[k], sizeof(ViewsArgs), hipMemcpyHostToDevice, cs);
+        if (e1 == hipSuccess && (mode & kStepFootprint))
+            e1 = launch_footprint_tiles_dev(st->dev[k], cs);
+        if (e1 == hipSuccess && (mode & kStepCompact))
+            e1 = launch_cull_views_dev(m->dm, st->dev[k], kCullGroups, cs);
+        if (e1 == hipSuccess)
+            e1 = launch_integrate_views_dev(m->dm, st->dev[k], st->spherical, m->p.weighting, st->groups,
+                                            (mode & kStepCompact) != 0, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &st->graph[k][mode]);
+        e = e1 != hipSuccess ? e1 : e2;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&st->exec[k][mode], st->graph[k][mode], nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    return e;
 }
 
 extern "C" {
@@ -926,7 +963,7 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
     if (e == hipSuccess)
         e = prepare_learned(m, va.cam, va.n_views, s);
     if (e == hipSuccess)
-        e = prepare_compaction(m, va.lat);
+        e = prepare_compaction(m, va.lat, va.n_views);
     if (e != hipSuccess)
         return hip_status(e);
     const bool timed = timing_begin(m, s);
@@ -962,36 +999,18 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
     long long groups = lc.max_groups > 0 ? lc.max_groups : m->max_groups;
     st->groups = (int)std::max<long long>(kPartitions, groups / kPartitions * kPartitions);
     hipError_t e = use_device(m);
-    hipStream_t cs = nullptr;
-    if (e == hipSuccess)
-        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         e = hipHostMalloc((void **)&st->pinned[k], sizeof(ViewsArgs), hipHostMallocDefault);
         if (e == hipSuccess)
             e = hipMalloc((void **)&st->dev[k], sizeof(ViewsArgs));
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&st->done[k], hipEventDisableTiming);
-        if (e == hipSuccess) {
-            std::memset(st->pinned[k], 0, sizeof(ViewsArgs));
-            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        }
-        if (e == hipSuccess) {
-            hipError_t e1 = hipMemcpyAsync(st->dev[k], st->pinned[k], sizeof(ViewsArgs), hipMemcpyHostToDevice, cs);
-            if (e1 == hipSuccess)
-                e1 = launch_footprint_tiles_dev(st->dev[k], cs);
-            if (e1 == hipSuccess)
-                e1 = launch_cull_views_dev(m->dm, st->dev[k], 1024, cs);
-            hipError_t e2 = e1 == hipSuccess ? launch_integrate_views_dev(m->dm, st->dev[k], st->spherical,
-                                                                          m->p.weighting, st->groups, cs)
-                                             : e1;
-            hipError_t e3 = hipStreamEndCapture(cs, &st->graph[k]);
-            e = e2 != hipSuccess ? e2 : e3;
-        }
         if (e == hipSuccess)
-            e = hipGraphInstantiate(&st->exec[k], st->graph[k], nullptr, nullptr, 0);
+            std::memset(st->pinned[k], 0, sizeof(ViewsArgs));
     }
-    if (cs)
-        (void)hipStreamDestroy(cs);
+    // the plain lattice-walk replay up front, so that capture errors surface here
+    if (e == hipSuccess)
+        e = step_capture(st, 0, 0);
     if (e != hipSuccess) {
         step_free(st);
         return hip_status(e);
@@ -1023,16 +1042,22 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
     if (e == hipSuccess)
         e = prepare_footprint(m, va, nullptr, false);   // the graph builds the pyramids
     if (e == hipSuccess)
-        e = prepare_compaction(m, va.lat);              // and culls into the list
+        e = prepare_compaction(m, va.lat, va.n_views);              // and culls into the list
     if (e != hipSuccess)
         return hip_status(e);
+    int mode = va.lat.cand ? kStepCompact : 0;
+    for (int v = 0; v < va.n_views; ++v)
+        if (va.cam[v].tiles)
+            mode |= kStepFootprint;
     const int k = st->next;
     if (st->pending[k] && (e = hipEventSynchronize(st->done[k])) != hipSuccess)
+        return hip_status(e);
+    if (!st->exec[k][mode] && (e = step_capture(st, k, mode)) != hipSuccess)
         return hip_status(e);
     *st->pinned[k] = va;
     hipStream_t s = (hipStream_t)hip_stream;
     const bool timed = timing_begin(m, s);
-    e = hipGraphLaunch(st->exec[k], s);
+    e = hipGraphLaunch(st->exec[k][mode], s);
     if (e == hipSuccess)
         e = hipEventRecord(st->done[k], s);
     if (e != hipSuccess)

@@ -817,21 +817,25 @@ __device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
 }
 
 // Cull kernel of a compacted launch: every thread culls lattice blocks
-// (grid-stride) against the views; each wave appends its survivors
+// (grid-stride) against the views; a workgroup appends its survivors
 // (lattice index, view mask) to lat.cand with one atomic on the launch's
-// candidate counter.
+// candidate counter per pass (an LDS prefix over its waves' ballots), so the
+// counter sees one atomic per kCullThreads lattice blocks.
+
 __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice &lat, const CameraView *cams,
                                              int n_views, const MapConsts &mc, int parity)
 {
+    constexpr int kWaves = kCullThreads / 64;
+    __shared__ uint32_t s_count[kWaves];
+    __shared__ uint32_t s_base;
     const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
     const uint32_t n_lat = (uint32_t)lat.n_lat;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    const uint32_t stride = gridDim.x * blockDim.x;
-    const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
-    // the loop runs the same number of times in every lane of a wave
-    const uint32_t wave_first = first - (uint32_t)lane;
-    for (uint32_t base = wave_first; base < n_lat; base += stride) {
-        const uint32_t lb = base + (uint32_t)lane;
+    const uint32_t stride = gridDim.x * (uint32_t)kCullThreads;
+    // the loop runs the same number of times in every thread of the workgroup
+    for (uint32_t base = blockIdx.x * (uint32_t)kCullThreads; base < n_lat; base += stride) {
+        const uint32_t lb = base + threadIdx.x;
         uint32_t vmask = 0;
         if (lb < n_lat) {
             const uint32_t rest = lb / dim_x;
@@ -843,14 +847,22 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
                     vmask |= 1u << v;
         }
         const unsigned long long keep = __ballot(vmask != 0);
-        if (keep) {
-            uint32_t at = 0;
-            if (lane == 0)
-                at = atomicAdd(&dm.counters[cand_counter(parity)], (uint32_t)__popcll(keep));
-            at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
-            if (vmask)
-                lat.cand[at + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull))] = make_uint2(lb, vmask);
+        if (lane == 0)
+            s_count[wave] = (uint32_t)__popcll(keep);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t total = 0;
+            for (int k = 0; k < kWaves; ++k)
+                total += s_count[k];
+            s_base = total ? atomicAdd(&dm.counters[cand_counter(parity)], total) : 0u;
         }
+        __syncthreads();
+        uint32_t at = s_base;
+        for (int k = 0; k < wave; ++k)
+            at += s_count[k];
+        if (vmask)
+            lat.cand[at + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull))] = make_uint2(lb, vmask);
+        __syncthreads();   // s_count and s_base are rewritten by the next pass
     }
 }
 

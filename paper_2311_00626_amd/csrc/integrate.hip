@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kern
     integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, fa);
 }
 
-__global__ __launch_bounds__(256) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
+__global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
 {
     cull_to_list(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity);
 }
@@ -114,8 +114,9 @@ __global__ __launch_bounds__(256) void cull_frame_kernel(DeviceMap dm, FrameArgs
 
 hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream)
 {
-    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((fa.lat.n_lat + 255) / 256, 2048));
-    hipLaunchKernelGGL(cull_frame_kernel, dim3(groups), dim3(256), 0, stream, dm, fa);
+    const unsigned groups = (unsigned)std::max<long long>(
+        1, std::min<long long>((fa.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));
+    hipLaunchKernelGGL(cull_frame_kernel, dim3(groups), dim3(kCullThreads), 0, stream, dm, fa);
     return hipGetLastError();
 }
 

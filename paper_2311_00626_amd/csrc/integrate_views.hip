@@ -139,8 +139,9 @@ __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_list_k
 }
 
 // Arguments read from device memory (graph replays: the host rewrites them
-// between replays through a captured copy).  A replay holds both the walking
-// and the list kernel; the one the arguments do not select exits at once.
+// between replays through a captured copy).  The host replays the graph of the
+// scheduling form the arguments select; each kernel also checks it and exits
+// at once on a mismatch.
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
 __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_kernel_dev(DeviceMap dm,
                                                                                   const ViewsArgs *__restrict__ va)
@@ -159,12 +160,12 @@ __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_list_k
     integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, *va);
 }
 
-__global__ __launch_bounds__(256) void cull_views_kernel(DeviceMap dm, ViewsArgs va)
+__global__ __launch_bounds__(kCullThreads) void cull_views_kernel(DeviceMap dm, ViewsArgs va)
 {
     cull_to_list(dm, va.lat, va.cam, va.n_views, va.mc, va.parity);
 }
 
-__global__ __launch_bounds__(256) void cull_views_kernel_dev(DeviceMap dm, const ViewsArgs *__restrict__ va)
+__global__ __launch_bounds__(kCullThreads) void cull_views_kernel_dev(DeviceMap dm, const ViewsArgs *__restrict__ va)
 {
     if (!va->lat.cand)
         return;
@@ -175,14 +176,15 @@ __global__ __launch_bounds__(256) void cull_views_kernel_dev(DeviceMap dm, const
 
 hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream)
 {
-    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((va.lat.n_lat + 255) / 256, 2048));
-    hipLaunchKernelGGL(cull_views_kernel, dim3(groups), dim3(256), 0, stream, dm, va);
+    const unsigned groups = (unsigned)std::max<long long>(
+        1, std::min<long long>((va.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));
+    hipLaunchKernelGGL(cull_views_kernel, dim3(groups), dim3(kCullThreads), 0, stream, dm, va);
     return hipGetLastError();
 }
 
 hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, hipStream_t stream)
 {
-    hipLaunchKernelGGL(cull_views_kernel_dev, dim3((unsigned)groups), dim3(256), 0, stream, dm, va_dev);
+    hipLaunchKernelGGL(cull_views_kernel_dev, dim3((unsigned)groups), dim3(kCullThreads), 0, stream, dm, va_dev);
     return hipGetLastError();
 }
 
@@ -233,38 +235,41 @@ hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int 
 // Both the walking and the list kernel (each returns at once unless the
 // replay's arguments select it).
 template <int WEIGHTING, int SPHERICAL>
-static void launch_views_dev_storage(const DeviceMap &dm, const ViewsArgs *va, dim3 grid, dim3 block,
+static void launch_views_dev_storage(const DeviceMap &dm, const ViewsArgs *va, bool list, dim3 grid, dim3 block,
                                      hipStream_t stream)
 {
-    if (dm.storage == 1) {
+    if (list) {
+        if (dm.storage == 1)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block,
+                               0, stream, dm, va);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block,
+                               0, stream, dm, va);
+    } else if (dm.storage == 1) {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
-                           stream, dm, va);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
                            stream, dm, va);
     } else {
         hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
-                           stream, dm, va);
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_views_list_kernel_dev<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
                            stream, dm, va);
     }
 }
 
 hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,
-                                      int groups, hipStream_t stream)
+                                      int groups, bool list, hipStream_t stream)
 {
     const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
     if (weighting == kWeightLearned)
         return hipErrorInvalidValue;
     if (weighting == kWeightDropoff) {
         if (spherical)
-            launch_views_dev_storage<kWeightDropoff, 1>(dm, va_dev, grid, block, stream);
+            launch_views_dev_storage<kWeightDropoff, 1>(dm, va_dev, list, grid, block, stream);
         else
-            launch_views_dev_storage<kWeightDropoff, 0>(dm, va_dev, grid, block, stream);
+            launch_views_dev_storage<kWeightDropoff, 0>(dm, va_dev, list, grid, block, stream);
     } else {
         if (spherical)
-            launch_views_dev_storage<kWeightConstant, 1>(dm, va_dev, grid, block, stream);
+            launch_views_dev_storage<kWeightConstant, 1>(dm, va_dev, list, grid, block, stream);
         else
-            launch_views_dev_storage<kWeightConstant, 0>(dm, va_dev, grid, block, stream);
+            launch_views_dev_storage<kWeightConstant, 0>(dm, va_dev, list, grid, block, stream);
     }
     return hipGetLastError();
 }

@@ -130,13 +130,13 @@ __device__ __forceinline__ float2 sm_outputs(const float o[kSmOut], float vs)
 
 constexpr int kMapThreads = 256;
 
+// The parameters are read straight from the (read-only) parameter buffer:
+// every lane of a wave reads the same one, so they arrive through scalar loads
+// and feed the multiply-adds as scalar operands, leaving the LDS port free.
 __global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs, const float *__restrict__ params,
                                                               float2 *__restrict__ out)
 {
-    __shared__ float P[kSmParams];
-    for (int k = (int)threadIdx.x; k < kSmParams; k += kMapThreads)
-        P[k] = params[k];
-    __syncthreads();
+    const float *__restrict__ P = params;
     const int n = v.width * v.height;
     for (int p = (int)(blockIdx.x * kMapThreads + threadIdx.x); p < n; p += (int)(gridDim.x * kMapThreads)) {
         const int j = p / v.width, i = p - j * v.width;

@@ -16,7 +16,11 @@ constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of 
 constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
 constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
 constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
-constexpr int kMaxChunk = 64;                       // lattice blocks culled together by one wave
+constexpr int kMaxChunk = 64;
+// Cull kernel of a compacted launch: threads per workgroup, and the most
+// workgroups a launch uses (the grid strides over larger lattices).
+constexpr int kCullThreads = 1024;
+constexpr int kCullGroups = 512;                       // lattice blocks culled together by one wave
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
 // Weighting functions (the tsdf_params weighting codes).
@@ -196,8 +200,9 @@ hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int 
                                   hipStream_t stream);
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
                                   hipStream_t stream);
+// list: the compacted form (the cull kernel ran before it), else the lattice walk
 hipError_t launch_integrate_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, bool spherical, int weighting,
-                                      int groups, hipStream_t stream);
+                                      int groups, bool list, hipStream_t stream);
 hipError_t launch_query_tsdf(const DeviceMap &dm, const int32_t *xyz, long long n, float *dist,
                              float *weight, hipStream_t stream);
 hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32_t *xyz,
