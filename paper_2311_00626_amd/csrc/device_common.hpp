@@ -735,6 +735,30 @@ __device__ __forceinline__ void write_touched(const DeviceMap &dm, int sub, uint
     }
 }
 
+// Walk launches (small lattices, a few blocks per wave) reserve a touched
+// block's entry as soon as its pool slot is known: the atomic's round trip
+// then overlaps the block's voxel traffic instead of ending the launch, and
+// lane 0 writes the entry (write_touched_entry) once the voxel stores are
+// issued.  On large lattices the same-address atomics would queue up, so
+// compacted launches collect entries per wave and reserve per workgroup.
+__device__ __forceinline__ uint32_t reserve_touched(const DeviceMap &dm, int parity, int sub)
+{
+    uint32_t at = 0;
+    if (lane_id() == 0)
+        at = atomicAdd(&dm.counters[touched_counter(parity, sub)], 1u);
+    return at;   // meaningful in lane 0
+}
+
+__device__ __forceinline__ void write_touched_entry(const DeviceMap &dm, int sub, uint32_t at, uint32_t slot)
+{
+    if (lane_id() == 0) {
+        if (at < dm.block_cap)
+            dm.touched[(size_t)sub * dm.block_cap + at] = slot;
+        else
+            atomicOr(&dm.counters[kErrorBits], kErrTouchedOverflow);
+    }
+}
+
 // A wave whose private list is full reserves room on its own (rare).
 __device__ __forceinline__ void flush_wave(const DeviceMap &dm, int parity, int sub, uint32_t pending, int n)
 {

@@ -17,10 +17,13 @@
 //                  ray-walk allocation every block the walk visited is.
 //   4. update   -- the weighted average runs on 512-byte slab loads and stores
 //                  of (distance, weight) pairs, predicated per lane.
-//   5. compact  -- touched pool slots collect in a wave register and are
-//                  written with one atomic per workgroup; counters are
-//                  double-buffered by launch parity, so a frame needs no host
-//                  synchronisation, memset or end-of-kernel fence.
+//   5. compact  -- a touched block's pool slot is appended to the touched
+//                  list: on small lattices with an atomic issued as soon as
+//                  the slot is known, on large ones collected in a wave
+//                  register and reserved with one atomic per workgroup;
+//                  counters are double-buffered by launch parity, so a frame
+//                  needs no host synchronisation, memset or end-of-kernel
+//                  fence.
 #include "device_common.hpp"
 
 namespace tsdf {
@@ -64,6 +67,9 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
         const uint32_t slot = find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
             return;
+        uint32_t at = 0;
+        if constexpr (!LIST)
+            at = reserve_touched(dm, parity, sub);
 
         // lanes whose voxel is not updated use an out-of-range offset: no load, no store
         using IO = VoxelIO<STORAGE>;
@@ -83,7 +89,10 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
             n_updates += (uint32_t)__popcll(__ballot((hit >> s) & 1u));
             IO::store(blk, off[s], dw[s]);
         }
-        push_touched(dm, parity, sub, slot, pending, n_pending);
+        if constexpr (LIST)
+            push_touched(dm, parity, sub, slot, pending, n_pending);
+        else
+            write_touched_entry(dm, sub, at, slot);
     };
     if constexpr (LIST)
         scan_list(dm, fa.lat, parity, block);
