@@ -521,8 +521,12 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
     const int lane = lane_id();
     const uint32_t P = (uint32_t)lat.partitions;
     const int part = (int)(blockIdx.x % P);
-    const uint32_t waves_pp = (gridDim.x / P) * (uint32_t)kWavesPerGroup;
-    const uint32_t wave_pp = (blockIdx.x / P) * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6);
+    // consecutive chunks go to different workgroups (wave w of group g takes
+    // chunk w * groups + g first): neighbouring lattice blocks survive culling
+    // together, and spread this way their waves share no SIMD
+    const uint32_t groups_pp = gridDim.x / P;
+    const uint32_t waves_pp = groups_pp * (uint32_t)kWavesPerGroup;
+    const uint32_t wave_pp = (threadIdx.x >> 6) * groups_pp + (blockIdx.x / P);
     const uint32_t chunk = (uint32_t)lat.chunk;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     const uint32_t n_lat = (uint32_t)lat.n_lat;
@@ -901,7 +905,8 @@ __device__ __forceinline__ void scan_list(const DeviceMap &dm, const Lattice &la
     const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
     const uint32_t waves = gridDim.x * (uint32_t)kWavesPerGroup;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    for (uint32_t i = blockIdx.x * (uint32_t)kWavesPerGroup + (threadIdx.x >> 6); i < count; i += waves) {
+    // consecutive entries go to different workgroups, as in scan_lattice
+    for (uint32_t i = (threadIdx.x >> 6) * gridDim.x + blockIdx.x; i < count; i += waves) {
         const uint2 e = lat.cand[i];
         const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.x);
         const uint32_t vmask = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.y);

@@ -43,15 +43,32 @@ __device__ __forceinline__ float round_bf16(float x)
 
 __device__ __forceinline__ bool sm_valid(float d, float d_max) { return d > 0.0f && d <= d_max; }
 
-__device__ __forceinline__ float sm_depth(const SmView &v, int i, int j) { return v.depth[(size_t)j * v.width + i]; }
+// Depth of pixel (i, j) through a buffer descriptor over the image: outside
+// the image the offset is out of range and the load returns 0, an invalid
+// depth, so every gather is issued without a branch and all of a pixel's
+// gathers are in flight together.
+__device__ __forceinline__ uint32_t sm_off(const SmView &v, int i, int j)
+{
+    return (i >= 0 && i < v.width && j >= 0 && j < v.height) ? 4u * (uint32_t)(j * v.width + i) : kOutOfRange;
+}
 
-__device__ float sm_incidence(const SmView &v, int i, int j, float d)
+__device__ __forceinline__ float sm_load(__amdgpu_buffer_rsrc_t img, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t sm_image(const SmView &v)
+{
+    return make_rsrc(v.depth, 4u * (uint32_t)v.width * (uint32_t)v.height);
+}
+
+// pi/2 unless all 4 neighbours are valid (a pixel on the image border has a
+// neighbour outside, which reads as invalid)
+__device__ float sm_incidence(const SmView &v, __amdgpu_buffer_rsrc_t img, int i, int j, float d)
 {
     const float half_pi = 1.57079637f;
-    if (i < 1 || i > v.width - 2 || j < 1 || j > v.height - 2)
-        return half_pi;
-    const float dl = sm_depth(v, i - 1, j), dr = sm_depth(v, i + 1, j);
-    const float du = sm_depth(v, i, j - 1), dd = sm_depth(v, i, j + 1);
+    const float dl = sm_load(img, sm_off(v, i - 1, j)), dr = sm_load(img, sm_off(v, i + 1, j));
+    const float du = sm_load(img, sm_off(v, i, j - 1)), dd = sm_load(img, sm_off(v, i, j + 1));
     if (!(sm_valid(dl, v.d_max) && sm_valid(dr, v.d_max) && sm_valid(du, v.d_max) && sm_valid(dd, v.d_max)))
         return half_pi;
     const float rxl = (((float)(i - 1) + 0.5f) - v.cx) / v.fx, rxc = (((float)i + 0.5f) - v.cx) / v.fx;
@@ -71,23 +88,24 @@ __device__ float sm_incidence(const SmView &v, int i, int j, float d)
 // The 27 inputs, already rounded to bfloat16.
 __device__ __forceinline__ void sm_inputs(const SmView &v, int i, int j, float d, float x[kSmIn])
 {
+    const __amdgpu_buffer_rsrc_t img = sm_image(v);
+    float dq[25];
 #pragma unroll
     for (int dj = -2; dj <= 2; ++dj)
 #pragma unroll
-        for (int di = -2; di <= 2; ++di) {
-            const int ii = i + di, jj = j + dj;
-            float q = 0.0f;
-            if (ii >= 0 && ii < v.width && jj >= 0 && jj < v.height) {
-                const float dq = sm_depth(v, ii, jj);
-                if (sm_valid(dq, v.d_max)) {
-                    q = dq - d;
-                    q = q < -0.5f ? -0.5f : (q > 0.5f ? 0.5f : q);
-                }
-            }
-            x[(dj + 2) * 5 + (di + 2)] = round_bf16(q);
+        for (int di = -2; di <= 2; ++di)
+            dq[(dj + 2) * 5 + (di + 2)] = sm_load(img, sm_off(v, i + di, j + dj));
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        float q = 0.0f;
+        if (sm_valid(dq[k], v.d_max)) {
+            q = dq[k] - d;
+            q = q < -0.5f ? -0.5f : (q > 0.5f ? 0.5f : q);
         }
+        x[k] = round_bf16(q);
+    }
     x[25] = round_bf16(d);
-    x[26] = round_bf16(sm_incidence(v, i, j, d));
+    x[26] = round_bf16(sm_incidence(v, img, i, j, d));
 }
 
 // Forward through the hidden layers with parameters P (LDS); h1, h2 are the
