@@ -32,13 +32,12 @@ namespace {
 
 using namespace dev;
 
+// Round to the nearest bfloat16, ties to even (gfx950's v_cvt_pk_bf16_f32;
+// infinities stay infinite, binary32 values beyond the bfloat16 range round
+// to infinity, as in the bit-level definition).
 __device__ __forceinline__ float round_bf16(float x)
 {
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if ((u & 0x7f800000u) == 0x7f800000u)
-        return x;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return __builtin_bit_cast(float, u & 0xffff0000u);
+    return (float)(__bf16)x;
 }
 
 __device__ __forceinline__ bool sm_valid(float d, float d_max) { return d > 0.0f && d <= d_max; }

@@ -18,9 +18,11 @@ constexpr int kSubLists = 8;                        // touched list split over 8
 constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
 constexpr int kMaxChunk = 64;
 // Cull kernel of a compacted launch: threads per workgroup, and the most
-// workgroups a launch uses (the grid strides over larger lattices).
-constexpr int kCullThreads = 1024;
-constexpr int kCullGroups = 512;                       // lattice blocks culled together by one wave
+// workgroups a launch uses (the grid strides over larger lattices).  Three
+// 512-thread groups fit a CU at the kernel's register use where one
+// 1024-thread group did, which keeps more footprint lookups in flight.
+constexpr int kCullThreads = 512;
+constexpr int kCullGroups = 2048;                       // lattice blocks culled together by one wave
 constexpr int kLineWords = 32;                      // 128-byte line in 32-bit words
 
 // Weighting functions (the tsdf_params weighting codes).
