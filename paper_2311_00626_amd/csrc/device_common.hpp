@@ -308,7 +308,8 @@ __device__ __forceinline__ float atan2_as(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);
     const bool swap = ay > ax;
-    const float t = swap ? ax / ay : ay / ax;
+    // one division: selecting between two quotients would compute both
+    const float t = (swap ? ax : ay) / (swap ? ay : ax);
     float a = atan_unit(t);
     if (swap)
         a = 1.57079637f - a;
@@ -667,8 +668,18 @@ __device__ __forceinline__ uint32_t measure_spherical(const CameraView &cv, cons
         int i1;
         bool col_ok;
         if (cv.full_circle) {
-            i0 = ((i0 % cv.width) + cv.width) % cv.width;
-            i1 = (i0 + 1) % cv.width;
+            // i0 mod width; conditional adds cover every column an azimuth
+            // start within two turns produces, the division the rest
+            const int w = cv.width;
+            if (i0 >= -2 * w && i0 < 3 * w) {
+                i0 += i0 < 0 ? w : 0;
+                i0 += i0 < 0 ? w : 0;
+                i0 -= i0 >= w ? w : 0;
+                i0 -= i0 >= w ? w : 0;
+            } else {
+                i0 = ((i0 % w) + w) % w;
+            }
+            i1 = i0 + 1 < w ? i0 + 1 : 0;
             col_ok = true;
         } else {
             col_ok = i0 >= 0 && i0 + 1 <= cv.width - 1;

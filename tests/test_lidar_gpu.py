@@ -42,6 +42,25 @@ def test_range_box_room():
     say(assert_parity(gm, om, exact_dist=True))
 
 
+@pytest.mark.parametrize("az_start", [-math.pi, 2.5, -9.0, 15.0, -40.0])
+def test_range_full_circle_azimuth_starts(az_start):
+    """Full-circle column wrap for azimuth starts within and beyond two turns
+    of the azimuth range (the kernel wraps the former by conditional adds, the
+    latter by the integer remainder)."""
+    L = synth.LidarModel(width=200, height=12, azimuth_start=az_start, max_range=10.0, interp_max_diff=0.3)
+    room = synth.Scene(room=(4.0, 3.0, 2.5), spheres=[((2.6, 1.9, 1.2), 0.35)])
+    rng = np.random.default_rng(5)
+    poses = [synth.pose_lidar([1.4 + 0.3 * k, 1.3, 1.2], 0.4 * k) for k in range(3)]
+    imgs = [synth.add_range_noise(synth.render_range(room, L, T), rng) for T in poses]
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff", max_range=10.0)
+    say(f"case: full-circle LiDAR 200x12, azimuth start {az_start} rad, 3 scans")
+    gm, om = both(params)
+    for img, T in zip(imgs, poses):
+        gm.integrate_range(torch.as_tensor(img, device="cuda"), L, T)
+        om.integrate_range(img, L, T)
+    say(assert_parity(gm, om, exact_dist=True))
+
+
 @pytest.mark.parametrize("pol", [(60.0, 40.0), (74.0, 32.0), (30.0, 120.0)])
 def test_range_constant_sphere(pol):
     L = synth.LidarModel(width=128, height=12, polar_start=math.radians(pol[0]), polar_fov=math.radians(pol[1]),
