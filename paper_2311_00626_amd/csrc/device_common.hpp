@@ -867,6 +867,19 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
     constexpr int kWaves = kCullThreads / 64;
     __shared__ uint32_t s_count[kWaves];
     __shared__ uint32_t s_base;
+    // the views' parameters, copied once per workgroup with all threads: read
+    // view after view from the argument block, each view is a chain of cold
+    // scalar loads on every CU
+    __shared__ CameraView s_cams[kMaxViews];
+    {
+        static_assert(sizeof(CameraView) % 4 == 0, "CameraView is copied in 32-bit words");
+        const uint32_t words = (uint32_t)n_views * (uint32_t)(sizeof(CameraView) / 4);
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(cams);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(s_cams);
+        for (uint32_t k = threadIdx.x; k < words; k += (uint32_t)kCullThreads)
+            dst[k] = src[k];
+    }
+    __syncthreads();
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
     const uint32_t n_lat = (uint32_t)lat.n_lat;
@@ -882,7 +895,7 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
             const int by = lat.lat_min[1] + (int)(rest % dim_y);
             const int bz = lat.lat_min[2] + (int)(rest / dim_y);
             for (int v = 0; v < n_views; ++v)
-                if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                if (lane_block_in_view(s_cams[v], mc, bx, by, bz))
                     vmask |= 1u << v;
         }
         const unsigned long long keep = __ballot(vmask != 0);

@@ -166,29 +166,61 @@ def default_params(voxel_size: float, truncation_vox: float) -> tsdf_params:
     return p
 
 
+# tsdf_depth_view as a NumPy record (same 112-byte layout), so that a batch's
+# arguments are filled column by column instead of field by field.
+_VIEW_DTYPE = np.dtype({"names": ["depth_dev", "width", "height", "model", "max_range_m", "K",
+                                  "interp_max_diff_m", "reserved", "T_world_cam"],
+                        "formats": ["<u8", "<i4", "<i4", "<i4", "<f4", ("<f4", 4), "<f4", "<f4", ("<f4", 16)],
+                        "offsets": [0, 8, 12, 16, 20, 24, 40, 44, 48], "itemsize": C.sizeof(tsdf_depth_view)})
+
+
+class ViewBatch:
+    """The tsdf_depth_view array of a batch of views (see views_array)."""
+
+    def __init__(self, rec: np.ndarray):
+        self.rec = rec
+        self.ptr = C.cast(rec.ctypes.data, C.POINTER(tsdf_depth_view))
+
+    def __getitem__(self, k):
+        return self.ptr[k]
+
+
 def views_array(depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None):
-    """(tsdf_depth_view array, n) of a batch of depth / range images."""
+    """(ViewBatch, n) of a batch of depth / range images: the tsdf_depth_view
+    array the C entry points take (ViewBatch.ptr), kept alive by the batch."""
     n = len(depths)
-    max_ranges = [0.0] * n if max_ranges is None else list(max_ranges)
     if not 1 <= n <= MAX_VIEWS or len(Ks) != n or len(Ts) != n:
         raise ValueError(f"need 1..{MAX_VIEWS} views with matching K and T")
-    arr = (tsdf_depth_view * n)()
-    for k, (d, K, T) in enumerate(zip(depths, Ks, Ts)):
+    rec = np.zeros(n, _VIEW_DTYPE)
+    ptrs, shapes = [], []
+    for d in depths:
         if not (d.is_cuda and d.dtype == torch.float32 and d.dim() == 2 and d.is_contiguous()):
             raise ValueError("each depth must be a contiguous 2-D float32 CUDA tensor")
-        arr[k].depth_dev = d.data_ptr()
-        arr[k].height, arr[k].width = int(d.shape[0]), int(d.shape[1])
-        if hasattr(K, "params"):
-            lm = lidar_struct(K)
-            arr[k].model = MODEL_SPHERICAL
-            arr[k].K[:] = [lm.azimuth_start_rad, lm.azimuth_fov_rad, lm.polar_start_rad, lm.polar_fov_rad]
-            arr[k].interp_max_diff_m = lm.interp_max_diff_m
-            arr[k].max_range_m = float(max_ranges[k]) or lm.max_range_m
-        else:
-            arr[k].K[:] = [float(x) for x in _host_f32(K, 4)]
-            arr[k].max_range_m = float(max_ranges[k])
-        arr[k].T_world_cam[:] = [float(x) for x in _host_f32(T, 16)]
-    return arr, n
+        ptrs.append(d.data_ptr())
+        shapes.append(d.shape)
+    rec["depth_dev"] = ptrs
+    rec["height"] = [h for h, _ in shapes]
+    rec["width"] = [w for _, w in shapes]
+    T = np.asarray(Ts, dtype=np.float32)
+    if T.size != 16 * n:
+        raise ValueError("each pose must hold 16 values (row-major 4x4)")
+    rec["T_world_cam"] = T.reshape(n, 16)
+    if max_ranges is not None:
+        rec["max_range_m"] = np.asarray(max_ranges, dtype=np.float32).reshape(n)
+    if not any(hasattr(K, "params") for K in Ks):
+        rec["K"] = np.asarray(Ks, dtype=np.float32).reshape(n, 4)
+    else:
+        for k, K in enumerate(Ks):
+            if hasattr(K, "params"):
+                lm = lidar_struct(K)
+                rec["model"][k] = MODEL_SPHERICAL
+                rec["K"][k] = [lm.azimuth_start_rad, lm.azimuth_fov_rad, lm.polar_start_rad, lm.polar_fov_rad]
+                rec["interp_max_diff_m"][k] = lm.interp_max_diff_m
+                if rec["max_range_m"][k] == 0.0:
+                    rec["max_range_m"][k] = lm.max_range_m
+            else:
+                rec["K"][k] = _host_f32(K, 4)
+    return ViewBatch(rec), n
 
 
 class TsdfMap:
@@ -265,7 +297,7 @@ class TsdfMap:
         integrate_depth / integrate_range on each in order (per-view max range,
         0 = map default).  A view whose K is a LidarModel is a range image."""
         arr, n = views_array(depths, Ks, Ts, max_ranges)
-        _check(lib.integrate_depth_views(self._h, arr, n, C.c_void_p(_stream_ptr(stream))),
+        _check(lib.integrate_depth_views(self._h, arr.ptr, n, C.c_void_p(_stream_ptr(stream))),
                "integrate_depth_views")
 
     def set_sensor_model(self, params) -> None:
@@ -365,7 +397,7 @@ class TsdfStep:
     def run(self, depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None,
             stream: Optional[torch.cuda.Stream] = None) -> None:
         arr, n = views_array(depths, Ks, Ts, max_ranges)
-        _check(lib.tsdf_step_run(self._h, arr, n, C.c_void_p(_stream_ptr(stream))), "tsdf_step_run")
+        _check(lib.tsdf_step_run(self._h, arr.ptr, n, C.c_void_p(_stream_ptr(stream))), "tsdf_step_run")
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

@@ -112,3 +112,26 @@ def test_sensor_model_arguments_rejected_before_device(t):
     q.weighting = 3
     h = C.c_void_p()
     assert t.lib.create_map_ex(C.byref(q), C.byref(h)) == t.EINVAL
+
+
+def test_view_record_layout_matches_struct():
+    """The NumPy record a batch's arguments are filled in has the C struct's
+    layout: every field written through the record reads back through the
+    ctypes view of the same memory."""
+    import numpy as np
+    from paper_2311_00626_amd import tsdf as t
+    rec = np.zeros(3, t._VIEW_DTYPE)
+    assert rec.itemsize == C.sizeof(t.tsdf_depth_view) == 112
+    rec["depth_dev"] = [0x1000, 0x2000, 0x3000]
+    rec["width"], rec["height"], rec["model"] = [640, 1024, 5], [480, 64, 7], [0, 1, 0]
+    rec["max_range_m"] = [0.0, 25.0, 3.5]
+    rec["K"] = np.arange(12, dtype=np.float32).reshape(3, 4)
+    rec["interp_max_diff_m"] = [0.0, 0.2, 0.0]
+    rec["T_world_cam"] = np.arange(48, dtype=np.float32).reshape(3, 16) + 0.5
+    b = t.ViewBatch(rec)
+    for k in range(3):
+        v = b[k]
+        assert v.depth_dev == 0x1000 * (k + 1)
+        assert (v.width, v.height, v.model) == (int(rec["width"][k]), int(rec["height"][k]), int(rec["model"][k]))
+        assert v.max_range_m == rec["max_range_m"][k] and v.interp_max_diff_m == rec["interp_max_diff_m"][k]
+        assert list(v.K) == list(rec["K"][k]) and list(v.T_world_cam) == list(rec["T_world_cam"][k])
