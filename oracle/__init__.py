@@ -199,15 +199,24 @@ class OracleMap:
         return b[order], d[order], w[order]
 
 
-def dense_integrate_range(params, images, lidar, poses, gmin, gdim, precision: int = 32):
+def _dense_state(state, n):
+    """Flat (dist, weight) binary64 arrays: zeros, or a copy of an earlier
+    call's result on the same box to continue from."""
+    if state is None:
+        return np.zeros(n, np.float64), np.zeros(n, np.float64)
+    return (np.array(state[0], dtype=np.float64).reshape(n), np.array(state[1], dtype=np.float64).reshape(n))
+
+
+def dense_integrate_range(params, images, lidar, poses, gmin, gdim, precision: int = 32, state=None):
     """Dense brute force of range images over a voxel box; (dist, weight)
-    shaped (gdim[2], gdim[1], gdim[0])."""
+    shaped (gdim[2], gdim[1], gdim[0]).  `state`: the (dist, weight) of an
+    earlier dense call on the same box, to continue from (frames of several
+    sensors in their order)."""
     lib = _load()
     gmin = np.ascontiguousarray(np.asarray(gmin, np.int32))
     gdim = np.ascontiguousarray(np.asarray(gdim, np.int32))
     n = int(np.prod(gdim.astype(np.int64)))
-    dist = np.zeros(n, np.float64)
-    weight = np.zeros(n, np.float64)
+    dist, weight = _dense_state(state, n)
     for img, T in zip(images, poses):
         img = _f32(img)
         H, W = img.shape
@@ -236,15 +245,15 @@ def camera_from_world(T_world_cam, precision: int = 32):
     return R.reshape(3, 3), t
 
 
-def dense_integrate(params, frames, K, poses, gmin, gdim, precision: int = 32):
+def dense_integrate(params, frames, K, poses, gmin, gdim, precision: int = 32, state=None):
     """Brute force over a dense voxel box (no blocks, hash or candidates).
-    Returns (dist, weight) arrays shaped (gdim[2], gdim[1], gdim[0])."""
+    Returns (dist, weight) arrays shaped (gdim[2], gdim[1], gdim[0]); `state`
+    as in dense_integrate_range."""
     lib = _load()
     gmin = np.ascontiguousarray(np.asarray(gmin, np.int32))
     gdim = np.ascontiguousarray(np.asarray(gdim, np.int32))
     n = int(np.prod(gdim.astype(np.int64)))
-    dist = np.zeros(n, np.float64)
-    weight = np.zeros(n, np.float64)
+    dist, weight = _dense_state(state, n)
     for depth, T in zip(frames, poses):
         depth = _f32(depth)
         H, W = depth.shape
