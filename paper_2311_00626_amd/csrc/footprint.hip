@@ -16,6 +16,8 @@
 namespace tsdf {
 namespace {
 
+using namespace dev;
+
 constexpr int kThreads = 256;
 
 __device__ __forceinline__ float valid_or_zero(float d, float d_max)
@@ -52,18 +54,23 @@ __device__ void build_pyramids(const ViewsArgs &va)
         const int sx = (int)(k % sup_cols), sy = (int)(k / sup_cols);
         const int x0 = kTileSuper * sx + 4 * tx, y0 = kTileSuper * sy + 4 * ty;
 
+        // pixels beyond the image edge read through an out-of-range offset
+        // (value 0, which the maximum ignores): no branch, all 16 loads in flight
+        const __amdgpu_buffer_rsrc_t img = make_rsrc(cv.depth, 4u * (uint32_t)cv.width * (uint32_t)cv.height);
+        float px[16];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int y = y0 + r, x = x0 + c;
+                const uint32_t off =
+                    (y < cv.height && x < cv.width) ? 4u * (uint32_t)(y * cv.width + x) : kOutOfRange;
+                px[4 * r + c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(img, off, 0, 0));
+            }
         float m = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int y = y0 + r;
-            if (y < cv.height) {
-                const float *row = cv.depth + (size_t)y * (size_t)cv.width;
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (x0 + c < cv.width)
-                        m = fmaxf(m, valid_or_zero(row[x0 + c], cv.d_max));
-            }
-        }
+        for (int k = 0; k < 16; ++k)
+            m = fmaxf(m, valid_or_zero(px[k], cv.d_max));
         s4[ty][tx] = m;
         __syncthreads();
         if (t < 64) {
