@@ -873,10 +873,12 @@ int build_views_args(tsdf_map *m, const tsdf_depth_view *views, int n_views, Vie
 // [the batched integration kernel reading them], used alternately so that a
 // slot is rewritten only after its previous replay has finished.
 // Graph variants of a step, captured on first use: bit 0 = footprint
-// pre-pass, bit 1 = compacted launch (cull kernel + list kernel).
+// pre-pass, bit 1 = compacted launch (cull kernel + list kernel), bit 2 = the
+// cull kernel tests a block's views one lane each (the views share a model).
 constexpr int kStepFootprint = 1;
 constexpr int kStepCompact = 2;
-constexpr int kStepModes = 4;
+constexpr int kStepLaneViews = 4;
+constexpr int kStepModes = 8;
 
 struct tsdf_step {
     tsdf_map *m;
@@ -925,7 +927,7 @@ static hipError_t step_capture(tsdf_step *st, int k, int mode)
         if (e1 == hipSuccess && (mode & kStepFootprint))
             e1 = launch_footprint_tiles_dev(st->dev[k], cs);
         if (e1 == hipSuccess && (mode & kStepCompact))
-            e1 = launch_cull_views_dev(m->dm, st->dev[k], kCullGroups, cs);
+            e1 = launch_cull_views_dev(m->dm, st->dev[k], kCullGroups, (mode & kStepLaneViews) != 0, cs);
         if (e1 == hipSuccess)
             e1 = launch_integrate_views_dev(m->dm, st->dev[k], st->spherical, m->p.weighting, st->groups,
                                             (mode & kStepCompact) != 0, cs);
@@ -1045,7 +1047,7 @@ int tsdf_step_run(tsdf_step *st, const tsdf_depth_view *views, int n_views, void
         e = prepare_compaction(m, va.lat, va.n_views);              // and culls into the list
     if (e != hipSuccess)
         return hip_status(e);
-    int mode = va.lat.cand ? kStepCompact : 0;
+    int mode = va.lat.cand ? (kStepCompact | (views_share_model(va) ? kStepLaneViews : 0)) : 0;
     for (int v = 0; v < va.n_views; ++v)
         if (va.cam[v].tiles)
             mode |= kStepFootprint;

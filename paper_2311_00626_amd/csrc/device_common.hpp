@@ -855,21 +855,34 @@ __device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
         atomicExch(&dm.counters[cand_counter(parity ^ 1)], 0u);
 }
 
-// Cull kernel of a compacted launch: every thread culls lattice blocks
-// (grid-stride) against the views; a workgroup appends its survivors
-// (lattice index, view mask) to lat.cand with one atomic on the launch's
-// candidate counter per pass (an LDS prefix over its waves' ballots), so the
-// counter sees one atomic per kCullThreads lattice blocks.
+// Lanes a compacted launch's cull kernel gives each lattice block: one per
+// view, rounded up to a power of two (a wave holds 64 / lanes blocks).
+__host__ __device__ __forceinline__ int cull_lanes_per_block(int n_views)
+{
+    int lanes = 1;
+    while (lanes < n_views)
+        lanes <<= 1;
+    return lanes;
+}
 
+// Cull kernel of a compacted launch.  LANE_VIEWS: lane (block, view) tests
+// one lattice block against one view (grid-stride over blocks x
+// lanes-per-block) and one ballot gives each block's view mask -- for batches
+// whose views share one camera model; when pinhole and spherical views mix, a
+// wave would run both tests with few lanes each, so then every lane tests its
+// block against all views in turn.  The first lane of a block with a nonzero
+// mask appends (lattice index, view mask) to lat.cand.  A workgroup reserves
+// its room with one atomic on the launch's candidate counter per pass (an LDS
+// prefix over its waves' counts), and the views' parameters are copied into
+// LDS once per workgroup: read view after view from the argument block, each
+// is a chain of cold scalar loads on every CU.
+template <bool LANE_VIEWS>
 __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice &lat, const CameraView *cams,
                                              int n_views, const MapConsts &mc, int parity)
 {
     constexpr int kWaves = kCullThreads / 64;
     __shared__ uint32_t s_count[kWaves];
     __shared__ uint32_t s_base;
-    // the views' parameters, copied once per workgroup with all threads: read
-    // view after view from the argument block, each view is a chain of cold
-    // scalar loads on every CU
     __shared__ CameraView s_cams[kMaxViews];
     {
         static_assert(sizeof(CameraView) % 4 == 0, "CameraView is copied in 32-bit words");
@@ -882,23 +895,37 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
     __syncthreads();
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
-    const uint32_t n_lat = (uint32_t)lat.n_lat;
+    const int lanes = LANE_VIEWS ? cull_lanes_per_block(n_views) : 1;
+    const int shift = __builtin_ctz((unsigned)lanes);
+    const int view = lane & (lanes - 1);
+    const int group = lane & ~(lanes - 1);                         // first lane of the block's group
+    const unsigned long long group_mask = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
+    const unsigned long long n_lat = (unsigned long long)lat.n_lat;
+    const unsigned long long n_work = n_lat << shift;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    const uint32_t stride = gridDim.x * (uint32_t)kCullThreads;
+    const unsigned long long stride = (unsigned long long)gridDim.x * (unsigned long long)kCullThreads;
     // the loop runs the same number of times in every thread of the workgroup
-    for (uint32_t base = blockIdx.x * (uint32_t)kCullThreads; base < n_lat; base += stride) {
-        const uint32_t lb = base + threadIdx.x;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * kCullThreads; base < n_work; base += stride) {
+        const unsigned long long item = base + threadIdx.x;
+        const uint32_t lb = (uint32_t)(item >> shift);
         uint32_t vmask = 0;
-        if (lb < n_lat) {
+        if (item < n_work && view < n_views) {
             const uint32_t rest = lb / dim_x;
             const int bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
             const int by = lat.lat_min[1] + (int)(rest % dim_y);
             const int bz = lat.lat_min[2] + (int)(rest / dim_y);
-            for (int v = 0; v < n_views; ++v)
-                if (lane_block_in_view(s_cams[v], mc, bx, by, bz))
-                    vmask |= 1u << v;
+            if constexpr (LANE_VIEWS) {
+                vmask = lane_block_in_view(s_cams[view], mc, bx, by, bz) ? 1u : 0u;
+            } else {
+                for (int v = 0; v < n_views; ++v)
+                    if (lane_block_in_view(s_cams[v], mc, bx, by, bz))
+                        vmask |= 1u << v;
+            }
         }
-        const unsigned long long keep = __ballot(vmask != 0);
+        if constexpr (LANE_VIEWS)
+            vmask = (uint32_t)((__ballot(vmask != 0u) >> group) & group_mask);
+        const bool lead = view == 0 && vmask != 0u;
+        const unsigned long long keep = __ballot(lead);
         if (lane == 0)
             s_count[wave] = (uint32_t)__popcll(keep);
         __syncthreads();
@@ -912,7 +939,7 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
         uint32_t at = s_base;
         for (int k = 0; k < wave; ++k)
             at += s_count[k];
-        if (vmask)
+        if (lead)
             lat.cand[at + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull))] = make_uint2(lb, vmask);
         __syncthreads();   // s_count and s_base are rewritten by the next pass
     }

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kern
 
 __global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
 {
-    cull_to_list(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity);
+    cull_to_list<true>(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity);
 }
 
 }  // namespace
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, 
 hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream)
 {
     const unsigned groups = (unsigned)std::max<long long>(
-        1, std::min<long long>((fa.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));
+        1, std::min<long long>((fa.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));  // one view: one lane per block
     hipLaunchKernelGGL(cull_frame_kernel, dim3(groups), dim3(kCullThreads), 0, stream, dm, fa);
     return hipGetLastError();
 }

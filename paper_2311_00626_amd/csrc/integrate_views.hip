@@ -166,31 +166,53 @@ __global__ __launch_bounds__(64 * kWavesPerGroup, 4) void integrate_views_list_k
     integrate_views_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, *va);
 }
 
+template <bool LANE_VIEWS>
 __global__ __launch_bounds__(kCullThreads) void cull_views_kernel(DeviceMap dm, ViewsArgs va)
 {
-    cull_to_list(dm, va.lat, va.cam, va.n_views, va.mc, va.parity);
+    cull_to_list<LANE_VIEWS>(dm, va.lat, va.cam, va.n_views, va.mc, va.parity);
 }
 
+template <bool LANE_VIEWS>
 __global__ __launch_bounds__(kCullThreads) void cull_views_kernel_dev(DeviceMap dm, const ViewsArgs *__restrict__ va)
 {
     if (!va->lat.cand)
         return;
-    cull_to_list(dm, va->lat, va->cam, va->n_views, va->mc, va->parity);
+    cull_to_list<LANE_VIEWS>(dm, va->lat, va->cam, va->n_views, va->mc, va->parity);
 }
 
 }  // namespace
 
+bool views_share_model(const ViewsArgs &va)
+{
+    for (int v = 1; v < va.n_views; ++v)
+        if (va.cam[v].model != va.cam[0].model)
+            return false;
+    return true;
+}
+
 hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream)
 {
-    const unsigned groups = (unsigned)std::max<long long>(
-        1, std::min<long long>((va.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));
-    hipLaunchKernelGGL(cull_views_kernel, dim3(groups), dim3(kCullThreads), 0, stream, dm, va);
+    const bool lane_views = views_share_model(va);
+    const long long work = va.lat.n_lat * (lane_views ? cull_lanes_per_block(va.n_views) : 1);
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((work + kCullThreads - 1) / kCullThreads,
+                                                                                 kCullGroups));
+    if (lane_views)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(cull_views_kernel<true>), dim3(groups), dim3(kCullThreads), 0, stream, dm, va);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(cull_views_kernel<false>), dim3(groups), dim3(kCullThreads), 0, stream, dm,
+                           va);
     return hipGetLastError();
 }
 
-hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, hipStream_t stream)
+hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, bool lane_views,
+                                 hipStream_t stream)
 {
-    hipLaunchKernelGGL(cull_views_kernel_dev, dim3((unsigned)groups), dim3(kCullThreads), 0, stream, dm, va_dev);
+    if (lane_views)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(cull_views_kernel_dev<true>), dim3((unsigned)groups), dim3(kCullThreads), 0,
+                           stream, dm, va_dev);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(cull_views_kernel_dev<false>), dim3((unsigned)groups), dim3(kCullThreads),
+                           0, stream, dm, va_dev);
     return hipGetLastError();
 }
 

@@ -213,7 +213,11 @@ hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32
 // fill lat.cand; the list kernels integrate its entries.
 hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream);
 hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream);
-hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, hipStream_t stream);
+// lane_views: the views share one camera model (see views_share_model)
+hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, bool lane_views,
+                                 hipStream_t stream);
+// true when every view of the batch has the first view's camera model
+bool views_share_model(const ViewsArgs &va);
 
 // Ray-walk allocation pre-pass (dda.hip).
 struct DdaArgs {
