@@ -53,12 +53,17 @@ __global__ __launch_bounds__(256) void dda_mark_kernel(DdaArgs a)
                 tdel[k] = __builtin_inff();
             }
         }
+        // lattice offsets as unsigned 32-bit values: a block below the lattice
+        // wraps to a large offset, so one compare per axis tests both ends; the
+        // lattice holds fewer than 2^31 entries, so the entry index fits too
+        const uint32_t dim_x = (uint32_t)a.lat.lat_dim[0], dim_y = (uint32_t)a.lat.lat_dim[1],
+                       dim_z = (uint32_t)a.lat.lat_dim[2];
         for (int it = 0; it < (1 << 16); ++it) {
-            const long long x = (long long)c[0] - a.lat.lat_min[0];
-            const long long y = (long long)c[1] - a.lat.lat_min[1];
-            const long long z = (long long)c[2] - a.lat.lat_min[2];
-            if (x >= 0 && x < a.lat.lat_dim[0] && y >= 0 && y < a.lat.lat_dim[1] && z >= 0 && z < a.lat.lat_dim[2])
-                a.marks[x + (long long)a.lat.lat_dim[0] * (y + (long long)a.lat.lat_dim[1] * z)] = 1;
+            const uint32_t x = (uint32_t)(c[0] - a.lat.lat_min[0]);
+            const uint32_t y = (uint32_t)(c[1] - a.lat.lat_min[1]);
+            const uint32_t z = (uint32_t)(c[2] - a.lat.lat_min[2]);
+            if (x < dim_x && y < dim_y && z < dim_z)
+                a.marks[x + dim_x * (y + dim_y * z)] = 1;
             else
                 atomicOr(a.overflow, (uint32_t)kErrWalkOutside);
             const int ax = (tmax[0] <= tmax[1] && tmax[0] <= tmax[2]) ? 0 : (tmax[1] <= tmax[2] ? 1 : 2);
