@@ -553,6 +553,8 @@ hipError_t prepare_walk(tsdf_map *m, FrameArgs &fa, const float T[16], hipStream
         m->walk_cap = 0;
         const long long cap = std::max<long long>(lat.n_lat, 1ll << 20);
         hipError_t e = hipMalloc((void **)&m->walk_marks, (size_t)cap);
+        if (e == hipSuccess)
+            e = launch_fill_u8(m->walk_marks, cap, s);   // from here on the integration kernel keeps it zero
         if (e != hipSuccess)
             return e;
         m->walk_cap = cap;
@@ -579,7 +581,7 @@ hipError_t prepare_walk(tsdf_map *m, FrameArgs &fa, const float T[16], hipStream
     a.overflow = m->dm.counters + kErrorBits;
     fa.cam.dda_marks = m->walk_marks;
     lat.partitions = 1;
-    return launch_dda_mark(a, lat.n_lat, s);
+    return launch_dda_mark(a, s);
 }
 
 struct CounterSnapshot {
@@ -755,8 +757,11 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
             return hip_status(e);
     }
     e = launch_integrate_depth(m->dm, fa, m->p.weighting, groups, s);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        if (walk)   // the marks were set but not consumed: clear them for the next frame
+            (void)launch_fill_u8(m->walk_marks, fa.lat.n_lat, s);
         return hip_status(e);
+    }
     timing_end(m, s, timed);
     ++m->frames;
     return TSDF_OK;

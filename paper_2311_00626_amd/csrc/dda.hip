@@ -5,7 +5,7 @@
 // min(d + epsilon, max range) (depth along the optical axis; the direction has
 // unit camera z); every block entered is marked in a byte map over the
 // frame's block lattice, which the integration kernel then takes as its
-// candidate set (and allocates in full).  Ties step x, then y, then z; a
+// candidate set (and allocates in full), clearing every mark it reads.  Ties step x, then y, then z; a
 // boundary exactly at the end depth is crossed.  The binary32 operations and
 // their order are fixed so that the visited set is reproducible exactly.
 #include "device_common.hpp"
@@ -77,10 +77,17 @@ __global__ __launch_bounds__(256) void dda_mark_kernel(DdaArgs a)
 
 }  // namespace
 
-hipError_t launch_dda_mark(const DdaArgs &a, long long n_marks, hipStream_t stream)
+hipError_t launch_fill_u8(unsigned char *p, long long n, hipStream_t stream)
 {
-    const unsigned fill_groups = (unsigned)std::max<long long>(1, std::min<long long>((n_marks + 255) / 256, 2048));
-    hipLaunchKernelGGL(fill_u8_kernel, dim3(fill_groups), dim3(256), 0, stream, a.marks, n_marks);
+    if (n <= 0)
+        return hipSuccess;
+    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 2048));
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(groups), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dda_mark(const DdaArgs &a, hipStream_t stream)
+{
     const long long n = (long long)a.width * a.height;
     const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 2048));
     hipLaunchKernelGGL(dda_mark_kernel, dim3(groups), dim3(256), 0, stream, a);

@@ -541,8 +541,13 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
             bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
             by = lat.lat_min[1] + (int)(rest % dim_y);
             bz = lat.lat_min[2] + (int)(rest / dim_y);
-            if (cams[0].dda_marks)
-                vmask = cams[0].dda_marks[lb] ? 1u : 0u;     // ray-walk allocation: the walk decides
+            if (cams[0].dda_marks) {
+                // ray-walk allocation: the walk decides; the mark is cleared
+                // for the next frame (each entry is read by one lane only)
+                vmask = cams[0].dda_marks[lb] ? 1u : 0u;
+                if (vmask)
+                    cams[0].dda_marks[lb] = 0;
+            }
             else if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
                 for (int v = 0; v < n_views; ++v)
                     if (lane_block_in_view(cams[v], mc, bx, by, bz))

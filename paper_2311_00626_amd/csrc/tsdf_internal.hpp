@@ -121,7 +121,8 @@ struct CameraView {
     const float2 *sm_maps;
     // ray-walk allocation: byte per lattice entry, set for the blocks the walk
     // visited (nullptr: exact-touch allocation with culling)
-    const unsigned char *dda_marks;
+    unsigned char *dda_marks;     // ray-walk marks over the lattice; the integration kernel clears
+                                  // each mark it reads, so the map is all zero between frames
     // depth footprint pyramid of this view (nullptr: no footprint culling)
     float *tiles;
     int tile_cols[kTileLevels];         // tiles per row at each level
@@ -231,7 +232,10 @@ struct DdaArgs {
     unsigned char *marks;
     uint32_t *overflow;     // set when a walk leaves the lattice (a bound was too small)
 };
-hipError_t launch_dda_mark(const DdaArgs &a, long long n_marks, hipStream_t stream);
+// Marks the blocks the frame's pixel rays enter (the mark map must be zero).
+hipError_t launch_dda_mark(const DdaArgs &a, hipStream_t stream);
+// Zeroes n bytes (the mark map when it is allocated, or after a failed frame).
+hipError_t launch_fill_u8(unsigned char *p, long long n, hipStream_t stream);
 
 // Builds the footprint pyramids of the views whose `tiles` is set.
 hipError_t launch_footprint_tiles(const ViewsArgs &va, hipStream_t stream);
