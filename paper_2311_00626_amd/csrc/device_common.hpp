@@ -515,6 +515,18 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
 // partition are handed to body(bx, by, bz, view_mask) one at a time
 // (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
 // lattice block is a candidate exactly when marked.
+// Position of workgroup g among the `groups` of a launch in the order that
+// consecutive work items are dealt out (item k of a pass goes to the group at
+// position k).  Workgroups are dispatched to the 8 XCDs round-robin (group g
+// runs on XCD g mod 8), so the order lists XCD 0's groups first, then XCD
+// 1's, and so on: consecutive items land on different CUs of one XCD.
+__device__ __forceinline__ uint32_t spread_position(uint32_t g, uint32_t groups)
+{
+    if (groups % (uint32_t)kXcds != 0u)
+        return g;
+    return (g % (uint32_t)kXcds) * (groups / (uint32_t)kXcds) + g / (uint32_t)kXcds;
+}
+
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body)
@@ -522,12 +534,13 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
     const int lane = lane_id();
     const uint32_t P = (uint32_t)lat.partitions;
     const int part = (int)(blockIdx.x % P);
-    // consecutive chunks go to different workgroups (wave w of group g takes
-    // chunk w * groups + g first): neighbouring lattice blocks survive culling
-    // together, and spread this way their waves share no SIMD
+    // consecutive chunks go to different workgroups: neighbouring lattice
+    // blocks survive culling together, and spread this way their waves share
+    // no SIMD.  The order is XCD-aware (spread_position): a run of consecutive
+    // chunks stays on one XCD, whose L2 then serves their shared depth pixels
     const uint32_t groups_pp = gridDim.x / P;
     const uint32_t waves_pp = groups_pp * (uint32_t)kWavesPerGroup;
-    const uint32_t wave_pp = (threadIdx.x >> 6) * groups_pp + (blockIdx.x / P);
+    const uint32_t wave_pp = (threadIdx.x >> 6) * groups_pp + spread_position(blockIdx.x / P, groups_pp);
     const uint32_t chunk = (uint32_t)lat.chunk;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     const uint32_t n_lat = (uint32_t)lat.n_lat;
@@ -961,8 +974,9 @@ __device__ __forceinline__ void scan_list(const DeviceMap &dm, const Lattice &la
     const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
     const uint32_t waves = gridDim.x * (uint32_t)kWavesPerGroup;
     const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    // consecutive entries go to different workgroups, as in scan_lattice
-    for (uint32_t i = (threadIdx.x >> 6) * gridDim.x + blockIdx.x; i < count; i += waves) {
+    // consecutive entries go to different workgroups of one XCD, as in scan_lattice
+    for (uint32_t i = (threadIdx.x >> 6) * gridDim.x + spread_position(blockIdx.x, gridDim.x); i < count;
+         i += waves) {
         const uint2 e = lat.cand[i];
         const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.x);
         const uint32_t vmask = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.y);

@@ -16,6 +16,7 @@ constexpr int kWavesPerGroup = 8;                   // 512-thread workgroups of 
 constexpr int kQueryWavesPerGroup = 4;              // 256-thread workgroups for the query kernels
 constexpr int kSubLists = 8;                        // touched list split over 8 counters / cache lines
 constexpr int kPartitions = 8;                      // XCDs: block ownership bands, one per XCD
+constexpr int kXcds = 8;               // MI355X: 8 XCDs, workgroups dispatched round-robin
 constexpr int kMaxChunk = 64;
 // Cull kernel of a compacted launch: threads per workgroup, and the most
 // workgroups a launch uses (the grid strides over larger lattices).  Three
