@@ -246,8 +246,10 @@ TSDF_API const char *tsdf_strerror(int status);
  *   max_groups  cap on workgroups of 512 threads per launch (rounded down to a
  *               multiple of 8), 1 .. 65536;
  *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
- *               each XCD reads about 1/8 of every depth image;
- *   chunk       lattice blocks a wave culls per pass, 1 .. 64;
+ *               each XCD reads about 1/8 of every depth image (lattice-walk
+ *               launches; more than 1 turns compaction off);
+ *   chunk       lattice blocks a wave culls per pass, 1 .. 64 (lattice-walk
+ *               launches);
  *   footprint   footprint culling: a pre-pass reduces every view to the
  *               largest valid measurement per 8/16/32/64-pixel tile, and a
  *               block is skipped when its nearest point lies beyond the
@@ -271,11 +273,15 @@ typedef struct {
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);
 
-/* Kernel timing.  While enabled, every integrate_depth call records a pair of
- * HIP events on its stream around its integration kernel.  tsdf_profile_read
- * synchronises those events and returns the summed kernel time in
- * milliseconds and the number of timed launches since the last enable; it
- * then clears them.  At most 65536 launches are kept. */
+/* Kernel timing.  While enabled, every integration call (integrate_depth,
+ * integrate_range, integrate_depth_views, tsdf_step_run) records a pair of HIP
+ * events on its stream around all the kernels it enqueues (footprint, network
+ * and ray-walk pre-passes, cull and integration kernels).  tsdf_profile_read
+ * synchronises those events and returns the summed time in milliseconds and
+ * the number of timed calls since the last enable; it then clears them.  At
+ * most 65536 calls are kept.  The events themselves cost the stream a few
+ * microseconds per call, so for throughput measure a run of calls between two
+ * events of the caller's own. */
 TSDF_API int tsdf_profile(tsdf_map *m, int enable);
 TSDF_API int tsdf_profile_read(tsdf_map *m, double *total_ms, long long *launches);
 

@@ -734,6 +734,7 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    const bool timed = e == hipSuccess && timing_begin(m, s);   // every kernel of the call, pre-passes included
     const bool walk = m->p.allocation == TSDF_ALLOC_RAY_WALK;
     if (e == hipSuccess && !walk)
         e = prepare_footprint(m, fa, s);
@@ -745,7 +746,6 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
         e = prepare_compaction(m, fa.lat, 1);
     if (e != hipSuccess)
         return hip_status(e);
-    const bool timed = timing_begin(m, s);
     int groups = schedule(m, fa.lat);
     if (walk)
         fa.lat.partitions = 1;    // every lattice entry is read by exactly one thread
@@ -793,6 +793,7 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    const bool timed = e == hipSuccess && timing_begin(m, s);   // every kernel of the call, pre-passes included
     if (e == hipSuccess)
         e = prepare_footprint(m, fa, s);
     if (e == hipSuccess)
@@ -801,7 +802,6 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
         e = prepare_compaction(m, fa.lat, 1);
     if (e != hipSuccess)
         return hip_status(e);
-    const bool timed = timing_begin(m, s);
     int groups = schedule(m, fa.lat);
     if (fa.lat.cand) {
         groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
@@ -965,6 +965,7 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
     va.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
+    const bool timed = e == hipSuccess && timing_begin(m, s);   // every kernel of the call, pre-passes included
     if (e == hipSuccess)
         e = prepare_footprint(m, va, s, true);
     if (e == hipSuccess)
@@ -973,7 +974,6 @@ int integrate_depth_views(tsdf_map *m, const tsdf_depth_view *views, int n_views
         e = prepare_compaction(m, va.lat, va.n_views);
     if (e != hipSuccess)
         return hip_status(e);
-    const bool timed = timing_begin(m, s);
     int groups = schedule(m, va.lat);
     if (va.lat.cand) {
         groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
