@@ -45,6 +45,51 @@ def errors(state, ref, vs):
             "weight_mismatch_voxels": int(((W > 0) | (RW > 0)).sum() - both.sum())}
 
 
+def wall_crossings(state, vs, room, margin_vox=4):
+    """Zero crossing of D across each of the room's six walls (the room spans
+    [0, L] on each axis, L a whole number of voxels): for every voxel column
+    normal to a wall, with both voxels straddling the wall updated and D
+    changing sign from behind (D < 0) to inside (D >= 0), the crossing by
+    linear interpolation, as its offset from the wall along the inward normal
+    (m).  Columns within margin_vox voxels of another wall are skipped.
+    Returns {(axis, side): dense array of offsets, NaN where there is none}."""
+    b, d, w = state
+    lz, ly, lx = np.meshgrid(np.arange(8), np.arange(8), np.arange(8), indexing="ij")
+    loc = np.stack([lx, ly, lz], -1).reshape(-1, 3)
+    g = (b[:, None, :].astype(np.int64) * 8 + loc[None]).reshape(-1, 3)
+    D, W = d.reshape(-1).astype(np.float64), w.reshape(-1)
+    n = [int(round(L / vs)) for L in room]
+    out = {}
+    for a in range(3):
+        o1, o2 = [k for k in range(3) if k != a]
+        for side in (0, 1):
+            g_in, g_out = (0, -1) if side == 0 else (n[a] - 1, n[a])
+            grids = {}
+            for name, ga in (("in", g_in), ("out", g_out)):
+                sel = (g[:, a] == ga) & (W > 0) & (g[:, o1] >= margin_vox) & (g[:, o1] < n[o1] - margin_vox) & \
+                      (g[:, o2] >= margin_vox) & (g[:, o2] < n[o2] - margin_vox)
+                grid = np.full((n[o1], n[o2]), np.nan)
+                grid[g[sel, o1], g[sel, o2]] = D[sel]
+                grids[name] = grid
+            di, db = grids["in"], grids["out"]
+            ok = np.isfinite(di) & np.isfinite(db) & (db < 0) & (di >= 0)
+            off = np.full(di.shape, np.nan)
+            off[ok] = -0.5 * vs + vs * db[ok] / (db[ok] - di[ok])
+            out[(a, side)] = off
+    return out
+
+
+def crossing_stats(c, ref=None):
+    """Mean |.|, RMS and max |.| of the crossing offsets (or of their
+    difference from `ref` where both exist) over all walls."""
+    if ref is None:
+        v = np.concatenate([x[np.isfinite(x)] for x in c.values()])
+    else:
+        v = np.concatenate([(c[k] - ref[k])[np.isfinite(c[k]) & np.isfinite(ref[k])] for k in c])
+    return {"columns": int(v.size), "mean_abs_m": float(np.abs(v).mean()), "rms_m": float(np.sqrt((v ** 2).mean())),
+            "max_abs_m": float(np.abs(v).max())}
+
+
 @pytest.mark.parametrize("vs,n", [(0.02, 300), (0.01, 60)])
 def test_precision_fp16_fp32_vs_fp64(vs, n):
     import oracle
@@ -67,9 +112,14 @@ def test_precision_fp16_fp32_vs_fp64(vs, n):
     assert_parity(g16, o16, exact_dist=True)
     ref = o64.sorted_state()
     s32, s16 = g32.sorted_state(), g16.sorted_state()
+    room = (4.0, 3.0, 2.5)
+    z64, z32, z16 = (wall_crossings(x, vs, room) for x in (ref, s32, s16))
     report = {"workload": w.name, "frames": n, "voxel_size_m": vs,
               "fp32_storage_vs_fp64": errors(s32, ref, vs),
               "fp16_storage_vs_fp64": errors(s16, ref, vs),
+              "zero_crossing": {"fp64_oracle_vs_walls": crossing_stats(z64), "fp32_vs_walls": crossing_stats(z32),
+                                "fp16_vs_walls": crossing_stats(z16), "fp32_vs_fp64": crossing_stats(z32, z64),
+                                "fp16_vs_fp64": crossing_stats(z16, z64)},
               "pool_bytes_per_block": {"fp32": 4096, "fp16": 2048}}
     say(json.dumps(report))
     if os.path.isdir("gpurun_out"):
@@ -84,3 +134,9 @@ def test_precision_fp16_fp32_vs_fp64(vs, n):
     # binary16 near the surface: |D| <= vs, ulp(vs) <= 2^-16 m, a few ulps of drift
     assert e16["p99_abs_err_near_m"] < 4 * 2.0 ** -16
     assert e16["rms_err_near_m"] <= e16["max_abs_err_near_m"]
+    # surfaces: the fused walls sit within half a voxel of the analytic walls, and
+    # storage precision moves the crossings by far less than that
+    zc = report["zero_crossing"]
+    for k in ("fp64_oracle_vs_walls", "fp32_vs_walls", "fp16_vs_walls"):
+        assert zc[k]["columns"] > 1000 and zc[k]["rms_m"] < 0.5 * vs
+    assert zc["fp32_vs_fp64"]["rms_m"] < 1e-4 and zc["fp16_vs_fp64"]["rms_m"] < 2e-4
