@@ -97,6 +97,51 @@ def test_ragged_image_sizes(W, H):
     assert_parity(gm, om)
 
 
+def test_image_wider_than_footprint_pyramid():
+    """A 5000-pixel-wide view exceeds the footprint pyramid (4096 pixels a
+    side): with footprint culling forced on it is integrated without it, and
+    still matches the oracle; so does a 4096-pixel view, which uses it."""
+    import oracle
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff")
+    for W, H in ((5000, 40), (4096, 48)):
+        rng = np.random.default_rng(W)
+        cam = synth.PinholeCamera(W, H, 0.45 * W, 0.45 * W, W / 2 - 0.3, H / 2 + 0.2)
+        say(f"case: {W}x{H} view, footprint culling forced on")
+        d = synth.random_frame(cam, rng, 0.3, 4.0)
+        T = synth.pose_from_forward([0.2, 0.1, 1.0], 0.2, -0.1, 0.05)
+        gm = TsdfMap.from_params(params)
+        gm.set_launch_config(footprint="always")
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), cam.K, T)
+        om = oracle.OracleMap.from_params(params)
+        om.integrate(d, cam.K, T)
+        torch.cuda.synchronize()
+        assert {tuple(x) for x in gm.query_touched().cpu().numpy()} == {tuple(x) for x in om.touched()}
+        say(assert_parity(gm, om, exact_dist=True))
+
+
+def test_maximum_image_size():
+    """The largest image the ABI accepts (2^28 pixels, 16384 x 16384) matches
+    the oracle; one row more is rejected before any launch."""
+    from paper_2311_00626_amd.tsdf import TsdfError, TsdfMap
+    W = H = 16384
+    rng = np.random.default_rng(77)
+    cam = synth.PinholeCamera(W, H, 0.9 * W, 0.9 * W, W / 2 + 0.25, H / 2 - 0.25)
+    say(f"case: maximum image size {W}x{H}")
+    d = synth.random_frame(cam, rng, 0.3, 4.0)
+    T = synth.pose_from_forward([0.3, -0.2, 1.1], 0.4, -0.2, 0.1)
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff")
+    gm, om = integrate_both(params, [d], cam.K, [T], check_touched=True)
+    say(assert_parity(gm, om, exact_dist=True))
+    del d
+    big = torch.empty((H + 1, W), dtype=torch.float32, device="cuda")
+    m = TsdfMap.from_params(params, block_capacity=1 << 12)
+    with pytest.raises(TsdfError):
+        m.integrate_depth(big, cam.K, T)
+    del big
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("fill", [0.0, -1.0, float("nan"), float("inf"), 7.0])
 def test_frames_without_valid_pixels(fill):
     cam = synth.PinholeCamera(64, 48, 50.0, 50.0, 32.0, 24.0)
