@@ -251,8 +251,17 @@ __global__ __launch_bounds__(kLossThreads) void sm_fuse_loss_kernel(SmLossArgs a
 }
 
 constexpr int kTile = 64;            // pixels per LDS tile; one wave per workgroup
-constexpr int kParamsPerLane = (kSmParams + 63) / 64;
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Per pixel: recompute the forward pass, back-propagate dL/dw and dL/deps to
+// the hidden layers.  Per 64-pixel tile (staged in LDS) the weight gradients
+// are sums of outer products over the pixels -- dense contractions -- and run
+// on the matrix cores: dW1 (32 x 27) += G1^T X and dW2 (32 x 32) += G2^T H1 as
+// 32 steps of v_mfma_f32_32x32x2_f32 each (two pixels per step).  Lane l
+// supplies A[l mod 32][l / 32] and B[l / 32][l mod 32]; accumulator register r
+// of lane l holds row 8 (r / 4) + 4 (l / 32) + r mod 4, column l mod 32.  The
+// small W3 and bias sums stay on the vector units.
 __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 {
     __shared__ float P[kSmParams];
@@ -261,14 +270,15 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
     __shared__ float G1[kTile][kSmHidden + 1], G2[kTile][kSmHidden + 1];
     __shared__ float GO[kTile][kSmOut];
     const int lane = (int)threadIdx.x;
+    const int col = lane & 31, half = lane >> 5;
     for (int k = lane; k < kSmParams; k += 64)
         P[k] = a.params[k];
     const double n_used = a.acc[1];
     const float scale = n_used > 0.0 ? (float)(1.0 / n_used) : 0.0f;
-    float acc[kParamsPerLane];
-#pragma unroll
-    for (int r = 0; r < kParamsPerLane; ++r)
-        acc[r] = 0.0f;
+    v16f acc_w1 = {}, acc_w2 = {};
+    float acc_w3 = 0.0f;   // W3[half][col]
+    float acc_b = 0.0f;    // b1[col] (half 0) or b2[col] (half 1)
+    float acc_b3 = 0.0f;   // b3[lane], lanes 0 and 1
     __syncthreads();
     const long long per_frame = (long long)a.width * a.height;
     const long long total = per_frame * a.n_frames;
@@ -329,46 +339,44 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
         GO[lane][0] = go0;
         GO[lane][1] = go1;
         __syncthreads();
-        // lane owns parameters q = lane + 64 r: sum over the tile's pixels
-#pragma unroll
-        for (int r = 0; r < kParamsPerLane; ++r) {
-            const int q = lane + 64 * r;
-            float s = 0.0f;
-            if (q < kSmB1) {
-                const int k2 = q / kSmIn, m = q - k2 * kSmIn;
-                for (int t = 0; t < kTile; ++t)
-                    s += G1[t][k2] * X[t][m];
-            } else if (q < kSmW2) {
-                const int k2 = q - kSmB1;
-                for (int t = 0; t < kTile; ++t)
-                    s += G1[t][k2];
-            } else if (q < kSmB2) {
-                const int k2 = (q - kSmW2) / kSmHidden, m = (q - kSmW2) - k2 * kSmHidden;
-                for (int t = 0; t < kTile; ++t)
-                    s += G2[t][k2] * H1[t][m];
-            } else if (q < kSmW3) {
-                const int k2 = q - kSmB2;
-                for (int t = 0; t < kTile; ++t)
-                    s += G2[t][k2];
-            } else if (q < kSmB3) {
-                const int c = (q - kSmW3) / kSmHidden, m = (q - kSmW3) - c * kSmHidden;
-                for (int t = 0; t < kTile; ++t)
-                    s += GO[t][c] * H2[t][m];
-            } else if (q < kSmParams) {
-                const int c = q - kSmB3;
-                for (int t = 0; t < kTile; ++t)
-                    s += GO[t][c];
+        // dW1 += G1^T X, dW2 += G2^T H1 on the matrix cores, two pixels per step
+        const int xcol = col < kSmIn ? col : 0;   // X has 27 columns: the index stays in the row
+#pragma unroll 4
+        for (int st = 0; st < kTile / 2; ++st) {
+            const int t = 2 * st + half;
+            const float xv = col < kSmIn ? X[t][xcol] : 0.0f;
+            acc_w1 = __builtin_amdgcn_mfma_f32_32x32x2f32(G1[t][col], xv, acc_w1, 0, 0, 0);
+            acc_w2 = __builtin_amdgcn_mfma_f32_32x32x2f32(G2[t][col], H1[t][col], acc_w2, 0, 0, 0);
+        }
+        // W3, b1 / b2 and b3 on the vector units
+        {
+            const float(*Gb)[kSmHidden + 1] = half ? G2 : G1;
+            float s3 = 0.0f, sb = 0.0f, sb3 = 0.0f;
+            for (int t = 0; t < kTile; ++t) {
+                s3 += GO[t][half] * H2[t][col];
+                sb += Gb[t][col];
+                sb3 += GO[t][lane & 1];
             }
-            acc[r] += s;
+            acc_w3 += s3;
+            acc_b += sb;
+            acc_b3 += sb3;
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < kParamsPerLane; ++r) {
-        const int q = lane + 64 * r;
-        if (q < kSmParams && acc[r] != 0.0f)
-            atomicAdd(&a.grad[q], acc[r]);
+    for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r / 4) + 4 * half + (r % 4);
+        if (col < kSmIn && acc_w1[r] != 0.0f)
+            atomicAdd(&a.grad[kSmW1 + kSmIn * row + col], acc_w1[r]);
+        if (acc_w2[r] != 0.0f)
+            atomicAdd(&a.grad[kSmW2 + kSmHidden * row + col], acc_w2[r]);
     }
+    if (acc_w3 != 0.0f)
+        atomicAdd(&a.grad[kSmW3 + kSmHidden * half + col], acc_w3);
+    if (acc_b != 0.0f)
+        atomicAdd(&a.grad[(half ? kSmB2 : kSmB1) + col], acc_b);
+    if (lane < kSmOut && acc_b3 != 0.0f)
+        atomicAdd(&a.grad[kSmB3 + lane], acc_b3);
 }
 
 __global__ void sm_fill_kernel(float *p, long long n, float v)
