@@ -16,6 +16,7 @@ sample of the same frames.
 import argparse
 import hashlib
 import json
+from dataclasses import asdict
 import os
 import sys
 import time
@@ -283,9 +284,9 @@ def rig_leg(n_steps: int, warmup: int):
     return {"steps": n, "views_per_step": 5, "pixels_per_step": pixels // n_steps,
             "value": (st1["voxel_updates"] - st0["voxel_updates"]) / el, "unit": "voxel updates/s",
             "steps_per_s": n / el, "ms_per_step": el / n * 1e3,
-            "launch_config": {"max_groups": choice.max_groups, "partitions": choice.partitions, "chunk": choice.chunk},
-            "tuning": [{"config": [t.config.max_groups, t.config.partitions, t.config.chunk],
-                        "kernel_ms": round(t.kernel_ms_per_launch, 4)} for t in trials[:5]],
+            "launch_config": asdict(choice),
+            "tuning": [{"config": asdict(t.config), "kernel_ms": round(t.kernel_ms_per_launch, 4)} for t in trials[:5]]
+            + [{"worst": asdict(trials[-1].config), "kernel_ms": round(trials[-1].kernel_ms_per_launch, 4)}],
             "blocks": st1["blocks"],
             "roofline": {"bound": "hbm", "achieved": alg / ks / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": alg / ks / 1e9 / HBM_PEAK_GBS, "kernel": "integrate_views_kernel_dev (graph)",

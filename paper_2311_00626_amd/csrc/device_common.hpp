@@ -508,13 +508,6 @@ __device__ __forceinline__ int block_band(const CameraView *cams, int n_views, c
     return (int)(lb % (uint32_t)kPartitions);
 }
 
-// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
-// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
-// P = 8) scans all chunks; each lane bands and culls one block of a chunk of
-// lat.chunk consecutive lattice blocks, and the surviving blocks of this
-// partition are handed to body(bx, by, bz, view_mask) one at a time
-// (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
-// lattice block is a candidate exactly when marked.
 // Position of workgroup g among the `groups` of a launch in the order that
 // consecutive work items are dealt out (item k of a pass goes to the group at
 // position k).  Workgroups are dispatched to the 8 XCDs round-robin (group g
@@ -527,6 +520,13 @@ __device__ __forceinline__ uint32_t spread_position(uint32_t g, uint32_t groups)
     return (g % (uint32_t)kXcds) * (groups / (uint32_t)kXcds) + g / (uint32_t)kXcds;
 }
 
+// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
+// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
+// P = 8) scans all chunks; each lane bands and culls one block of a chunk of
+// lat.chunk consecutive lattice blocks, and the surviving blocks of this
+// partition are handed to body(bx, by, bz, view_mask) one at a time
+// (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
+// lattice block is a candidate exactly when marked.
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body)

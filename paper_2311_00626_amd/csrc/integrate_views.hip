@@ -13,7 +13,9 @@
 //
 // Per block of the union lattice of all views:
 //   1. culling against every view's frustum -> view mask (wave-uniform), only
-//      for blocks of the workgroup's band (XCD-local image columns);
+//      for blocks of the workgroup's band (XCD-local image columns); in a
+//      compacted launch the cull kernel has done this and the blocks come
+//      from its list;
 //   2. view 0 of the mask is measured while the first hash window is in flight;
 //   3. the block is looked up; an existing block's 512 voxels are loaded while
 //      the next view is being measured (software pipeline of depth 2);
