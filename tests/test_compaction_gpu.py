@@ -157,3 +157,44 @@ def test_compaction_rejected_with_ray_walk_is_ignored():
         om.integrate_dda(f, w.camera.K, T)
     torch.cuda.synchronize()
     say(assert_parity(m, om, exact_dist=True))
+
+
+def test_step_switches_cull_layout_between_batches():
+    """One graph step alternating between camera-only batches (the cull kernel
+    gives each view a lane) and camera + LiDAR batches (each lane tests all of
+    its block's views), with compaction forced on: bitwise equal to eager
+    launches and to the oracle."""
+    import oracle
+    scene, steps = synth.rig_sequence(4)
+    L = synth.LidarModel(width=512, height=32, max_range=12.0, interp_max_diff=0.2)
+    params = synth.MapParams(0.05, 4.0, "linear_dropoff", max_range=5.0)
+    rng = np.random.default_rng(17)
+    say("case: graph step alternating camera-only and camera+LiDAR batches, compaction forced on")
+    batches = []
+    for k, st in enumerate(steps):
+        cams = [synth.add_depth_noise(synth.render_depth(scene, c, T, device="cuda"), rng)
+                for c, T in zip(st.cameras, st.poses)]
+        imgs, Ks, Ts = cams, [c.K for c in st.cameras], list(st.poses)
+        if k % 2:
+            imgs = imgs + [synth.add_range_noise(synth.render_range(scene, L, st.lidar_pose, device="cuda"), rng)]
+            Ks, Ts = Ks + [L], Ts + [st.lidar_pose]
+        batches.append((imgs, Ks, Ts))
+    graph = gpu_map(params, block_capacity=1 << 16)
+    graph.set_launch_config(compaction="always")
+    eager = gpu_map(params, block_capacity=1 << 16)
+    eager.set_launch_config(compaction="always")
+    step = graph.step(with_spherical=True)
+    om = oracle.OracleMap.from_params(params)
+    for imgs, Ks, Ts in batches:
+        dev = [torch.as_tensor(x, device="cuda") for x in imgs]
+        step.run(dev, Ks, Ts)
+        eager.integrate_depth_views(dev, Ks, Ts)
+        torch.cuda.synchronize()
+        for x, K, T in zip(imgs, Ks, Ts):
+            if hasattr(K, "params"):
+                om.integrate_range(x, K, T)
+            else:
+                om.integrate(x, K, T)
+    step.close()
+    assert states_equal(graph, eager)
+    say(assert_parity(graph, om, exact_dist=True))
