@@ -922,6 +922,10 @@ static void step_free(tsdf_step *st)
 static hipError_t step_capture(tsdf_step *st, int k, int mode)
 {
     tsdf_map *m = st->m;
+    if (st->graph[k][mode]) {   // left by an earlier capture whose instantiation failed
+        (void)hipGraphDestroy(st->graph[k][mode]);
+        st->graph[k][mode] = nullptr;
+    }
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess)
