@@ -148,8 +148,9 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
 
 def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
     """The 640x480 box-room sequence at a fine voxel size, binary32 and
-    binary16 storage: the configuration whose per-frame voxel traffic is
-    large enough for the HBM roofline to bind."""
+    binary16 storage one frame per launch (the configuration whose per-frame
+    voxel traffic is large enough for the HBM roofline to bind), and binary32
+    16 frames per launch."""
     import torch
     from paper_2311_00626_amd import synth
     w = synth.box_room_sequence(voxel_size, n_frames=300)
@@ -169,9 +170,47 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
                                                "pre-passes included on lattices large enough to use them)",
                                      "kernel_ms_mean": r["kernel_s"] * 1e3,
                                      "algorithmic_bytes_per_launch": r["alg_per_launch"]}}
+    out["fp32_16_per_launch"] = timed_views(w, frames, poses, 16, 1 << 18)
     del frames
     torch.cuda.empty_cache()
     return out
+
+
+def timed_views(w, frames, poses, B: int, block_capacity: int) -> dict:
+    """The same sequence with B frames per integrate_depth_views launch
+    (binary32): every voxel is read and written once per launch, and the
+    footprint and cull pre-passes run once per launch.  One event pair around
+    the timed launches, as in timed_plain."""
+    import torch
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    K = w.camera.K
+    n = frames.shape[0]
+    H, W = frames.shape[1], frames.shape[2]
+    m = TsdfMap.from_params(w.params, block_capacity=block_capacity)
+    first = n % B or B
+    m.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
+    torch.cuda.synchronize()
+    b0, u0, wr0, t0_ = counters(m)
+    ev = region_events()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev[0].record()
+    for a in range(first, n, B):
+        m.integrate_depth_views([frames[k] for k in range(a, a + B)], [K] * B, poses[a:a + B])
+    ev[1].record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t_start
+    launches = (n - first) // B
+    kms = ev[0].elapsed_time(ev[1])
+    b1, u1, wr1, t1_ = counters(m)
+    assert m.status() == 0, "map overflowed"
+    alg = algorithmic_bytes(wr1 - wr0, t1_ - t0_, b1 - b0, H * W, n - first) / max(launches, 1)
+    ks = kms / 1e3 / max(launches, 1)
+    return {"views_per_launch": B, "frames": n - first, "value": (u1 - u0) / el, "unit": "voxel updates/s",
+            "frames_per_s": (n - first) / el, "ms_per_launch": el / launches * 1e3,
+            "roofline": {"bound": "hbm", "achieved": alg / ks / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg / ks / 1e9 / HBM_PEAK_GBS, "kernel": "integrate_depth_views per launch",
+                         "kernel_ms_mean": ks * 1e3, "algorithmic_bytes_per_launch": alg}}
 
 
 def walk_leg(w, frames, poses, steps: int, warmup: int) -> dict:
