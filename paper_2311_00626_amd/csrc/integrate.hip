@@ -103,11 +103,12 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
 }
 
 // With binary32 storage five waves per SIMD cap the walking kernel at 96
-// VGPRs (a frame of 640x480 at 4 cm runs 2 % faster than uncapped at ~109);
-// the binary16 form, with its conversions, runs 5 % slower under that cap and
-// keeps four.
+// VGPRs (a frame of 640x480 at 4 cm runs 2 % faster than uncapped at ~109).
+// The binary16 form, with its conversions, runs slower under that cap, and
+// already under a four-wave one (its code changes at 102 VGPRs), so it keeps
+// the compiler's own choice (two waves: the minimum a 512-thread group needs).
 template <int WEIGHTING, int STORAGE, int SPHERICAL>
-__global__ __launch_bounds__(64 * kWavesPerGroup, STORAGE == 0 ? 5 : 4) void integrate_depth_kernel(DeviceMap dm,
+__global__ __launch_bounds__(64 * kWavesPerGroup, STORAGE == 0 ? 5 : 2) void integrate_depth_kernel(DeviceMap dm,
                                                                                                    FrameArgs fa)
 {
     integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, false>(dm, fa);
