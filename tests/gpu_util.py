@@ -15,6 +15,16 @@ def say(*a):
     sys.stdout.flush()
 
 
+def write_report(name: str, data) -> None:
+    """Writes a JSON report to $TSDF_REPORT_DIR/<name> when that directory is set."""
+    import json
+    import os
+    d = os.environ.get("TSDF_REPORT_DIR")
+    if d and os.path.isdir(d):
+        with open(os.path.join(d, name), "w") as f:
+            json.dump(data, f, indent=1)
+
+
 def gpu_map(params, **kw):
     from paper_2311_00626_amd.tsdf import TsdfMap
     return TsdfMap.from_params(params, **kw)

@@ -3,14 +3,13 @@ the visited block set, the touched list and every voxel are bit-identical to
 the binary32 oracle; the walk allocates weight-0 blocks that exact-touch
 allocation does not, and the two modes agree on every voxel they share."""
 import json
-import os
 
 import numpy as np
 import pytest
 import torch
 
 from paper_2311_00626_amd import synth
-from tests.gpu_util import assert_parity, gpu_map, say
+from tests.gpu_util import assert_parity, gpu_map, say, write_report
 
 pytestmark = pytest.mark.gpu
 
@@ -56,9 +55,7 @@ def test_ray_walk_bit_exact(name):
     report = {"workload": name, "frames": n, "blocks_ray_walk": len(bw), "blocks_exact": len(be),
               "weight0_blocks_ray_walk": len(zero), "exact_blocks_not_visited": len(set(ke) - set(kw))}
     say(json.dumps(report))
-    if os.path.isdir("gpurun_out"):
-        with open(f"gpurun_out/ray_walk_{name}.json", "w") as f:
-            json.dump(report, f)
+    write_report(f"ray_walk_{name}.json", report)
     assert len(zero) > 0
     assert len(set(ke) - set(kw)) <= 0.02 * len(be)
 

@@ -2,16 +2,15 @@
 map with binary32 and with binary16 storage (binary32 update arithmetic) is
 compared with the binary64 oracle; the binary16 map is also checked bit-exact
 against the binary32-arithmetic / binary16-storage oracle.  Errors are printed
-and, when gpurun_out/ exists, written to gpurun_out/precision_<size>.json."""
+and, when $TSDF_REPORT_DIR is set, written there as precision_<size>.json."""
 import json
-import os
 
 import numpy as np
 import pytest
 import torch
 
 from paper_2311_00626_amd import synth
-from tests.gpu_util import assert_parity, say
+from tests.gpu_util import assert_parity, say, write_report
 
 pytestmark = pytest.mark.gpu
 
@@ -122,9 +121,7 @@ def test_precision_fp16_fp32_vs_fp64(vs, n):
                                 "fp16_vs_fp64": crossing_stats(z16, z64)},
               "pool_bytes_per_block": {"fp32": 4096, "fp16": 2048}}
     say(json.dumps(report))
-    if os.path.isdir("gpurun_out"):
-        with open(f"gpurun_out/precision_{int(vs * 100)}cm.json", "w") as f:
-            json.dump(report, f, indent=1)
+    write_report(f"precision_{int(vs * 100)}cm.json", report)
     e32 = report["fp32_storage_vs_fp64"]
     e16 = report["fp16_storage_vs_fp64"]
     # binary32 arithmetic vs binary64: rounding only, except voxels whose pixel

@@ -4,14 +4,13 @@ oracle; the loss and gradient kernels agree with the oracle's binary64 loss
 and gradient; training on corrupted renders lowers the surface error below the
 linear-dropoff fallback on rooms it has not seen."""
 import json
-import os
 
 import numpy as np
 import pytest
 import torch
 
 from paper_2311_00626_amd import synth
-from tests.gpu_util import assert_parity, say
+from tests.gpu_util import assert_parity, say, write_report
 
 pytestmark = pytest.mark.gpu
 
@@ -150,9 +149,7 @@ def test_training_beats_linear_dropoff_on_held_out_rooms():
     errs = [sm.surface_error(r, vs, res.params) for r in held]
     say(json.dumps({"held_out_loss_before": before, "held_out_loss_after": after, "loss_log": res.losses[:4] +
                     res.losses[-4:], "surface_error": errs}))
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/sensor_model_gain.json", "w") as f:
-            json.dump({"before": before, "after": after, "errors": errs, "losses": res.losses}, f, indent=1)
+    write_report("sensor_model_gain.json", {"before": before, "after": after, "errors": errs, "losses": res.losses})
     assert after < before
     for e in errs:
         assert e["learned"]["rms_m"] < e["fallback"]["rms_m"]
