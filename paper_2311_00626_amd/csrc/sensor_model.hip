@@ -107,9 +107,20 @@ __device__ __forceinline__ void sm_inputs(const SmView &v, int i, int j, float d
     x[26] = round_bf16(sm_incidence(v, img, i, j, d));
 }
 
-// Forward through the hidden layers with parameters P (LDS); h1, h2 are the
+// The parameter buffer seen through the constant address space: a kernel that
+// never writes it reads it with scalar loads even where a barrier stands
+// between the loads and the kernel's start.
+typedef const __attribute__((address_space(4))) float *ConstParams;
+
+__device__ __forceinline__ ConstParams as_constant(const float *p)
+{
+    return (ConstParams)p;
+}
+
+// Forward through the hidden layers with parameters P; h1, h2 are the
 // bfloat16 activations, o the binary32 outputs.
-__device__ __forceinline__ void sm_forward(const float *P, const float x[kSmIn], float h1[kSmHidden],
+template <typename Params>
+__device__ __forceinline__ void sm_forward(Params P, const float x[kSmIn], float h1[kSmHidden],
                                            float h2[kSmHidden], float o[kSmOut])
 {
 #pragma unroll 4
@@ -254,6 +265,15 @@ constexpr int kTile = 64;            // pixels per LDS tile; one wave per workgr
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// Element (t, m) of a 64 x 32 tile in LDS, rows rotated by t: a lane writing
+// its own row and 32 lanes reading one column of a row both touch 32 distinct
+// banks without a padding column, which keeps a workgroup's tiles small
+// enough for four workgroups (one per SIMD) on a compute unit.
+__device__ __forceinline__ int tile_at(int t, int m)
+{
+    return t * kSmHidden + ((m + t) & (kSmHidden - 1));
+}
+
 // Per pixel: recompute the forward pass, back-propagate dL/dw and dL/deps to
 // the hidden layers.  Per 64-pixel tile (staged in LDS) the weight gradients
 // are sums of outer products over the pixels -- dense contractions -- and run
@@ -264,37 +284,38 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // small W3 and bias sums stay on the vector units.
 __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 {
-    __shared__ float P[kSmParams];
     __shared__ float X[kTile][kSmIn + 1];
-    __shared__ float H1[kTile][kSmHidden + 1], H2[kTile][kSmHidden + 1];
-    __shared__ float G1[kTile][kSmHidden + 1], G2[kTile][kSmHidden + 1];
+    __shared__ float H1[kTile * kSmHidden], H2[kTile * kSmHidden];
+    __shared__ float G1[kTile * kSmHidden], G2[kTile * kSmHidden];
     __shared__ float GO[kTile][kSmOut];
     const int lane = (int)threadIdx.x;
     const int col = lane & 31, half = lane >> 5;
-    for (int k = lane; k < kSmParams; k += 64)
-        P[k] = a.params[k];
+    // the weights are read-only here and the same for every lane: scalar loads, as in inference
+    const ConstParams P = as_constant(a.params);
     const double n_used = a.acc[1];
     const float scale = n_used > 0.0 ? (float)(1.0 / n_used) : 0.0f;
     v16f acc_w1 = {}, acc_w2 = {};
     float acc_w3 = 0.0f;   // W3[half][col]
     float acc_b = 0.0f;    // b1[col] (half 0) or b2[col] (half 1)
     float acc_b3 = 0.0f;   // b3[lane], lanes 0 and 1
-    __syncthreads();
+    // Tiles never straddle two frames, so a tile's frame (and the buffer
+    // descriptor of its image) is the same for the whole wave.
     const long long per_frame = (long long)a.width * a.height;
-    const long long total = per_frame * a.n_frames;
-    for (long long base = (long long)blockIdx.x * kTile; base < total; base += (long long)gridDim.x * kTile) {
-        const long long p = base + lane;
+    const long long tiles_per_frame = (per_frame + kTile - 1) / kTile;
+    const long long n_tiles = tiles_per_frame * a.n_frames;
+    for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int f = (int)(tile / tiles_per_frame);
+        const long long k = (tile - (long long)f * tiles_per_frame) * kTile + lane;
         float x[kSmIn], h1[kSmHidden], h2[kSmHidden], o[kSmOut];
         float go0 = 0.0f, go1 = 0.0f;
         bool active = false;
-        if (p < total) {
-            const int f = (int)(p / per_frame);
-            const int k = (int)(p - (long long)f * per_frame);
+        if (k < per_frame) {
+            const long long p = (long long)f * per_frame + k;
             const float gw = a.gw[p], ge = a.ge[p];
-            const SmView v = a.views[f];
+            const SmView &v = a.views[f];
             const float d = v.depth[k];
             if ((gw != 0.0f || ge != 0.0f) && sm_valid(d, v.d_max)) {
-                const int j = k / v.width, i = k - j * v.width;
+                const int j = (int)k / v.width, i = (int)k - j * v.width;
                 sm_inputs(v, i, j, d, x);
                 sm_forward(P, x, h1, h2, o);
                 go0 = scale * gw * 0.5f * (1.0f + o[0] / sqrtf(o[0] * o[0] + 4.0f));
@@ -318,23 +339,28 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
             const float gh = P[kSmW3 + m] * go0 + P[kSmW3 + kSmHidden + m] * go1;
             g2[m] = h2[m] > 0.0f ? gh : 0.0f;
         }
-#pragma unroll 4
-        for (int m = 0; m < kSmHidden; ++m) {
-            float gh = 0.0f;
+        // W2^T g2 row by row of W2 (each sum still runs over k2 in order)
 #pragma unroll
-            for (int k2 = 0; k2 < kSmHidden; ++k2)
-                gh += P[kSmW2 + kSmHidden * k2 + m] * g2[k2];
-            g1[m] = h1[m] > 0.0f ? gh : 0.0f;
+        for (int m = 0; m < kSmHidden; ++m)
+            g1[m] = 0.0f;
+#pragma unroll 4
+        for (int k2 = 0; k2 < kSmHidden; ++k2) {
+#pragma unroll
+            for (int m = 0; m < kSmHidden; ++m)
+                g1[m] += P[kSmW2 + kSmHidden * k2 + m] * g2[k2];
         }
+#pragma unroll
+        for (int m = 0; m < kSmHidden; ++m)
+            g1[m] = h1[m] > 0.0f ? g1[m] : 0.0f;
 #pragma unroll
         for (int m = 0; m < kSmIn; ++m)
             X[lane][m] = x[m];
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m) {
-            H1[lane][m] = h1[m];
-            H2[lane][m] = h2[m];
-            G1[lane][m] = g1[m];
-            G2[lane][m] = g2[m];
+            H1[tile_at(lane, m)] = h1[m];
+            H2[tile_at(lane, m)] = h2[m];
+            G1[tile_at(lane, m)] = g1[m];
+            G2[tile_at(lane, m)] = g2[m];
         }
         GO[lane][0] = go0;
         GO[lane][1] = go1;
@@ -344,17 +370,19 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 #pragma unroll 4
         for (int st = 0; st < kTile / 2; ++st) {
             const int t = 2 * st + half;
-            const float xv = col < kSmIn ? X[t][xcol] : 0.0f;
-            acc_w1 = __builtin_amdgcn_mfma_f32_32x32x2f32(G1[t][col], xv, acc_w1, 0, 0, 0);
-            acc_w2 = __builtin_amdgcn_mfma_f32_32x32x2f32(G2[t][col], H1[t][col], acc_w2, 0, 0, 0);
+            const float xr = X[t][xcol];   // read unconditionally: the loop body stays one block
+            const float xv = col < kSmIn ? xr : 0.0f;
+            const int tc = tile_at(t, col);
+            acc_w1 = __builtin_amdgcn_mfma_f32_32x32x2f32(G1[tc], xv, acc_w1, 0, 0, 0);
+            acc_w2 = __builtin_amdgcn_mfma_f32_32x32x2f32(G2[tc], H1[tc], acc_w2, 0, 0, 0);
         }
         // W3, b1 / b2 and b3 on the vector units
         {
-            const float(*Gb)[kSmHidden + 1] = half ? G2 : G1;
+            const float *Gb = half ? G2 : G1;
             float s3 = 0.0f, sb = 0.0f, sb3 = 0.0f;
             for (int t = 0; t < kTile; ++t) {
-                s3 += GO[t][half] * H2[t][col];
-                sb += Gb[t][col];
+                s3 += GO[t][half] * H2[tile_at(t, col)];
+                sb += Gb[tile_at(t, col)];
                 sb3 += GO[t][lane & 1];
             }
             acc_w3 += s3;
@@ -440,8 +468,18 @@ hipError_t launch_sm_loss(const SmLossArgs &a, hipStream_t stream)
 
 hipError_t launch_sm_backward(const SmBackArgs &a, hipStream_t stream)
 {
-    const long long total = (long long)a.width * a.height * a.n_frames;
-    const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((total + kTile - 1) / kTile, 1024));
+    const long long tiles = (((long long)a.width * a.height + kTile - 1) / kTile) * a.n_frames;
+    // One round of resident workgroups (the LDS tiles bound how many share a
+    // compute unit): a grid beyond that leaves a partial second round.
+    int dev = 0, cus = 0, per_cu = 0;
+    long long resident = 1024;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sm_backward_kernel, 64, 0) == hipSuccess &&
+        cus > 0 && per_cu > 0)
+        resident = (long long)cus * per_cu;
+    const unsigned groups =
+        (unsigned)std::max<long long>(1, std::min<long long>(tiles, resident));
     hipLaunchKernelGGL(sm_backward_kernel, dim3(groups), dim3(64), 0, stream, a);
     return hipGetLastError();
 }
