@@ -189,50 +189,67 @@ __global__ __launch_bounds__(kLossThreads) void sm_fuse_loss_kernel(SmLossArgs a
     __shared__ double red[2][kLossThreads / 64];
     double loss = 0.0, used = 0.0;
     const long long stride = (long long)gridDim.x * kLossThreads;
+    const uint32_t wh = (uint32_t)a.width * (uint32_t)a.height;
     for (long long v = (long long)blockIdx.x * kLossThreads + threadIdx.x; v < a.n_vox; v += stride) {
         const float px = ((float)a.vox[3 * v] + 0.5f) * a.vs;
         const float py = ((float)a.vox[3 * v + 1] + 0.5f) * a.vs;
         const float pz = ((float)a.vox[3 * v + 2] + 0.5f) * a.vs;
-        float sw = 0.0f, swx = 0.0f, D = 0.0f, gD = 0.0f;
-        for (int stage = 0; stage < 2; ++stage) {
-            for (int f = 0; f < a.n_frames; ++f) {
-                const SmFrame &fr = a.frames[f];
-                const float xc = ((fr.R[0] * px + fr.R[1] * py) + fr.R[2] * pz) + fr.t[0];
-                const float yc = ((fr.R[3] * px + fr.R[4] * py) + fr.R[5] * pz) + fr.t[1];
-                const float zc = ((fr.R[6] * px + fr.R[7] * py) + fr.R[8] * pz) + fr.t[2];
-                if (!(zc > 0.0f))
-                    continue;
-                const float r = 1.0f / zc;
-                const float u = a.fx * (xc * r) + a.cx;
-                const float w_ = a.fy * (yc * r) + a.cy;
-                if (!(u >= 0.0f && u < (float)a.width && w_ >= 0.0f && w_ < (float)a.height))
-                    continue;
-                const size_t k = (size_t)(int)w_ * (size_t)a.width + (size_t)(int)u;
-                const float d = fr.depth[k];
-                if (!sm_valid(d, a.d_max))
-                    continue;
-                const float2 we = fr.maps[k];
-                const float dp = d - zc;
-                if (!(dp >= -we.y) || !(we.x > 0.0f))
-                    continue;
-                const float x = dp < we.y ? dp : we.y;
-                if (stage == 0) {
-                    sw += we.x;
-                    swx += we.x * x;
-                } else {
-                    atomicAdd(&fr.gw[k], gD * (x - D) / sw);
-                    if (dp > we.y)
-                        atomicAdd(&fr.ge[k], gD * we.x / sw);
-                }
+        // Every frame of the window at once: the pixel offsets first, then all
+        // depth and map gathers together (an offset out of range for a frame the
+        // voxel does not project into, or past the window, reads zeros, which
+        // fail the validity tests), then the contributions in frame order.
+        uint32_t off[kSmMaxFrames];
+        float zc[kSmMaxFrames];
+#pragma unroll
+        for (int f = 0; f < kSmMaxFrames; ++f) {
+            const SmFrame &fr = a.frames[f];
+            const float xc = ((fr.R[0] * px + fr.R[1] * py) + fr.R[2] * pz) + fr.t[0];
+            const float yc = ((fr.R[3] * px + fr.R[4] * py) + fr.R[5] * pz) + fr.t[1];
+            zc[f] = ((fr.R[6] * px + fr.R[7] * py) + fr.R[8] * pz) + fr.t[2];
+            const float r = 1.0f / zc[f];
+            const float u = a.fx * (xc * r) + a.cx;
+            const float w_ = a.fy * (yc * r) + a.cy;
+            const bool in = f < a.n_frames && zc[f] > 0.0f && u >= 0.0f && u < (float)a.width && w_ >= 0.0f &&
+                            w_ < (float)a.height;
+            off[f] = in ? (uint32_t)(int)w_ * (uint32_t)a.width + (uint32_t)(int)u : kOutOfRange;
+        }
+        float d[kSmMaxFrames];
+        float2 we[kSmMaxFrames];
+#pragma unroll
+        for (int f = 0; f < kSmMaxFrames; ++f) {
+            const bool in = off[f] != kOutOfRange;
+            d[f] = sm_load(make_rsrc(a.frames[f].depth, 4u * wh), in ? 4u * off[f] : kOutOfRange);
+            we[f] = load_f2(make_rsrc(a.frames[f].maps, 8u * wh), in ? 8u * off[f] : kOutOfRange);
+        }
+        float sw = 0.0f, swx = 0.0f;
+        float x[kSmMaxFrames];
+        uint32_t used_frames = 0u, clipped = 0u;
+#pragma unroll
+        for (int f = 0; f < kSmMaxFrames; ++f) {
+            const float dp = d[f] - zc[f];
+            const bool ok = sm_valid(d[f], a.d_max) && dp >= -we[f].y && we[f].x > 0.0f;
+            x[f] = dp < we[f].y ? dp : we[f].y;
+            if (ok) {
+                sw += we[f].x;
+                swx += we[f].x * x[f];
+                used_frames |= 1u << f;
+                if (dp > we[f].y)
+                    clipped |= 1u << f;
             }
-            if (stage == 0) {
-                if (!(sw > 0.0f))
-                    break;
-                D = swx / sw;
-                const float diff = D - a.target[v];
-                gD = 2.0f * diff;
-                loss += (double)diff * (double)diff;
-                used += 1.0;
+        }
+        if (!(sw > 0.0f))
+            continue;
+        const float D = swx / sw;
+        const float diff = D - a.target[v];
+        const float gD = 2.0f * diff;
+        loss += (double)diff * (double)diff;
+        used += 1.0;
+#pragma unroll
+        for (int f = 0; f < kSmMaxFrames; ++f) {
+            if (used_frames & (1u << f)) {
+                atomicAdd(&a.frames[f].gw[off[f]], gD * (x[f] - D) / sw);
+                if (clipped & (1u << f))
+                    atomicAdd(&a.frames[f].ge[off[f]], gD * we[f].x / sw);
             }
         }
     }
