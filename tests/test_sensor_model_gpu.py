@@ -91,11 +91,10 @@ def test_learned_map_rejections():
         m.step()
 
 
-def loss_case():
+def loss_case(width=48, height=36, idx=(0, 8, 16, 23)):
     import oracle
-    cam = synth.PinholeCamera(48, 36, 40.0, 40.0, 24.0, 18.0)
+    cam = synth.PinholeCamera(width, height, 40.0, 40.0, width / 2, height / 2)
     r, clean, noisy = room_frames(1002, 24, cam)
-    idx = [0, 8, 16, 23]
     vs = 0.1
     om = oracle.OracleMap(vs, 4.0, precision=64, weighting="constant")
     for k in idx:
@@ -109,15 +108,21 @@ def loss_case():
     return cam, [noisy[k] for k in idx], [r.poses[k] for k in idx], g[keep].astype(np.int32), D[keep], vs
 
 
-def test_loss_and_gradient_match_oracle():
+@pytest.mark.parametrize("width,height,idx", [(48, 36, (0, 8, 16, 23)), (50, 37, tuple(range(0, 24, 2)))],
+                         ids=["48x36-4frames", "50x37-12frames-partial-tile"])
+def test_loss_and_gradient_match_oracle(width, height, idx):
+    """50x37 = 1850 pixels leaves a partial 64-pixel tile at the end of every
+    frame of the backward pass; 12 frames is a window longer than the 8 of
+    training."""
     import oracle
     from paper_2311_00626_amd import sensor_model as sm
     from paper_2311_00626_amd.tsdf import SmTrainer
-    cam, frames, poses, vox, target, vs = loss_case()
+    cam, frames, poses, vox, target, vs = loss_case(width, height, idx)
     P = sm.init_params(7, scale=3.0)
-    say(f"case: loss/gradient, 4 frames 48x36, {len(vox)} target voxels, vs oracle (bfloat16-emulating binary64)")
+    say(f"case: loss/gradient, {len(idx)} frames {width}x{height}, {len(vox)} target voxels, vs oracle "
+        "(bfloat16-emulating binary64)")
     loss_o, grad_o, used_o = oracle.sm_loss_grad(P, frames, cam.K, poses, vs, 5.0, vox, target, emulate_bf16=True)
-    tr = SmTrainer(cam.width, cam.height, 4)
+    tr = SmTrainer(cam.width, cam.height, len(idx))
     grad = torch.zeros(2018, device="cuda")
     loss_g, used_g = tr.loss_grad(torch.as_tensor(P, device="cuda"), [torch.as_tensor(f, device="cuda") for f in frames],
                                   cam.K, poses, vs, 5.0, torch.as_tensor(vox, device="cuda"),
