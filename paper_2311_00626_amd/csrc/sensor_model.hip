@@ -353,10 +353,12 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
         float g2[kSmHidden], g1[kSmHidden];
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m) {
-            const float gh = P[kSmW3 + m] * go0 + P[kSmW3 + kSmHidden + m] * go1;
+            const float gh = __builtin_fmaf(P[kSmW3 + kSmHidden + m], go1, P[kSmW3 + m] * go0);
             g2[m] = h2[m] > 0.0f ? gh : 0.0f;
         }
-        // W2^T g2 row by row of W2 (each sum still runs over k2 in order)
+        // W2^T g2 row by row of W2 (each sum still runs over k2 in order), one
+        // fused multiply-add per term: the gradient is checked against the
+        // binary64 oracle to a tolerance, not bit for bit
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m)
             g1[m] = 0.0f;
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
         for (int k2 = 0; k2 < kSmHidden; ++k2) {
 #pragma unroll
             for (int m = 0; m < kSmHidden; ++m)
-                g1[m] += P[kSmW2 + kSmHidden * k2 + m] * g2[k2];
+                g1[m] = __builtin_fmaf(P[kSmW2 + kSmHidden * k2 + m], g2[k2], g1[m]);
         }
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m)
