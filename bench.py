@@ -68,16 +68,43 @@ def measured_traffic(launches_bytes: float):
     return s.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, frames_host, budget_s: float, min_s: float = 10.0):
-    """The binary32 oracle on one thread over the sequence, each pass into a
-    fresh map, until `min_s` seconds have passed (at most `budget_s`)."""
+def host_cpu() -> dict:
+    """CPU model and core counts of the host the benchmark runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_threads() -> int:
+    """Threads for the all-cores oracle: the CPUs this process may use,
+    capped by OMP_NUM_THREADS when that is set."""
+    n = host_cpu()["usable_cpus"]
+    try:
+        cap = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        cap = 0
+    return max(1, min(n, cap) if cap > 0 else n)
+
+
+def time_oracle(params, frames_host, K, poses, threads: int, min_s: float, budget_s: float, precision: int = 32):
+    """Passes of the oracle over the frames, each into a fresh map, until
+    `min_s` seconds have passed (at most `budget_s`); threads 0 = the
+    single-threaded entry point."""
     import oracle
     updates, n, passes, t0 = 0, 0, 0, time.perf_counter()
     while True:
-        om = oracle.OracleMap.from_params(w.params)
+        om = oracle.OracleMap.from_params(params, precision=precision)
         passes += 1
-        for d, T in zip(frames_host, w.poses):
-            updates += om.integrate(d, w.camera.K, T)
+        for d, T in zip(frames_host, poses):
+            updates += om.integrate(d, K, T) if threads == 0 else om.integrate_threads(d, K, T, threads)
             n += 1
             if time.perf_counter() - t0 > budget_s:
                 break
@@ -85,9 +112,34 @@ def cpu_baseline(w, frames_host, budget_s: float, min_s: float = 10.0):
         if time.perf_counter() - t0 > min(min_s, budget_s):
             break
     dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "voxel updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames ({passes} pass(es) over the 300-frame sequence, each into a fresh map), "
-                      f"binary32 oracle, one thread, {dt:.1f} s, {n / dt:.1f} frames/s"}
+    return {"updates_per_s": updates / dt, "frames": n, "passes": passes, "seconds": dt, "frames_per_s": n / dt}
+
+
+def cpu_baseline(w, frames_host, budget_s: float) -> dict:
+    """The oracle on the host: binary32 on all usable cores (the value) and
+    on one thread, over the 300-frame sequence, each pass into a fresh map;
+    and binary64 on all cores over the first frames of the 1 cm box room."""
+    from paper_2311_00626_amd import synth
+    threads = oracle_threads()
+    share = budget_s / 3.0
+    many = time_oracle(w.params, frames_host, w.camera.K, w.poses, threads, 0.6 * share, share)
+    one = time_oracle(w.params, frames_host, w.camera.K, w.poses, 0, 0.6 * share, share)
+    fine = synth.box_room_sequence(0.01, n_frames=300)
+    fine_frames = fine.frames(count=30)
+    f64 = time_oracle(fine.params, fine_frames, fine.camera.K, fine.poses[:30], threads, 0.5 * share, share,
+                      precision=64)
+    return {"value": many["updates_per_s"], "unit": "voxel updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{many['frames']} frames ({many['passes']} pass(es) over the 300-frame sequence, each into a "
+                      f"fresh map), binary32 oracle on {threads} threads (bitwise the one-thread map), "
+                      f"{many['seconds']:.1f} s, {many['frames_per_s']:.1f} frames/s",
+            "host": host_cpu(),
+            "one_thread": {"value": one["updates_per_s"], "unit": "voxel updates/s", "cores": 1,
+                           "frames_per_s": one["frames_per_s"],
+                           "sample": f"{one['frames']} frames, {one['seconds']:.1f} s"},
+            "binary64_box_room_1cm": {"value": f64["updates_per_s"], "unit": "voxel updates/s", "cores": threads,
+                                      "frames_per_s": f64["frames_per_s"], "workload": fine.name,
+                                      "sample": f"{f64['frames']} frames (first 30 of 300, passes into fresh maps), "
+                                                f"binary64 oracle, {f64['seconds']:.1f} s"}}
 
 
 def counters(m):

@@ -35,7 +35,7 @@
  *   exception crosses the ABI.  Device-side overflow (block pool, hash table,
  *   touched list) sets a sticky error word on the device that map_status()
  *   and the synchronising queries report as TSDF_EFULL; once observed, the
- *   map rejects further integration with TSDF_ESTATE.
+ *   map rejects further integration with TSDF_ESTATE until reserve() grows it.
  */
 #ifndef TSDF_H
 #define TSDF_H
@@ -110,6 +110,25 @@ TSDF_API int create_map_ex(const tsdf_params *p, tsdf_map **out);
 /* Frees the map and all its device memory after the device is idle.  NULL is
  * accepted (TSDF_OK). */
 TSDF_API int destroy_map(tsdf_map *m);
+
+/* Grows the map to hold block_capacity blocks (§IV-A: the block hash and the
+ * block storage behind it).  The block pool is reallocated and every block
+ * keeps its pool slot, voxels and touched-list entry; the hash grows to the
+ * smallest power of two at least twice the new block capacity (it never
+ * shrinks) and every allocated block's key is re-inserted into it on the
+ * device.  Graphs captured by the map's steps (tsdf_step_*) are dropped and
+ * re-captured on their next run.  A capacity not above the current one
+ * changes nothing and returns TSDF_OK.
+ * Recovery: reserve also clears a sticky TSDF_EFULL.  The calls that
+ * overflowed did not update the blocks they could not allocate (those blocks
+ * miss those calls' measurements; every other block is exact), so a caller
+ * that needs an exact map reserves ahead of time (map_stats: blocks against
+ * block_capacity) rather than after an overflow.
+ * Synchronises the device, and must not be called while any stream is being
+ * captured into a graph (TSDF_ESTATE, the map unchanged).  block_capacity:
+ * 1 .. 2^30.  Errors: TSDF_EINVAL, TSDF_ESTATE, TSDF_ENOMEM (the map
+ * unchanged), TSDF_EDEVICE. */
+TSDF_API int reserve(tsdf_map *m, long long block_capacity);
 
 /* Fuses one depth frame into the map (§IV-B, Eq. (1)-(2) and the TSDF update
  * functor):
@@ -203,15 +222,21 @@ TSDF_API int tsdf_step_destroy(tsdf_step *step);
 /* Writes the indices of all allocated blocks, sorted ascending by (x, y, z),
  * as int32 triples to out_xyz_dev (room for `capacity` blocks; min(count,
  * capacity) are written) and the total count to *out_count (host).
- * Synchronises hip_stream.  (§IV-A: the set of allocated blocks.) */
+ * Synchronises hip_stream.  (§IV-A: the set of allocated blocks.)  The sort's
+ * work buffers belong to the map and are allocated on the first call. */
 TSDF_API int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
                  void *hip_stream);
 
 /* Gathers the voxels of n_blocks blocks (int32 triples at blocks_xyz_dev):
- * out_dist_dev and out_weight_dev receive 512 float32 each per block in
- * voxel order lx + 8 ly + 64 lz (binary16 storage widens exactly), zeros for
- * blocks that are not allocated.
- * Only enqueues work. */
+ * the sampled field Phi of §III, the fused distance D and weight W of each
+ * voxel, read through the block hash (§IV-A: block index -> block of 8^3
+ * voxels stored contiguously).  out_dist_dev and out_weight_dev receive 512
+ * float32 each per block in voxel order lx + 8 ly + 64 lz (binary16 storage
+ * widens exactly), zeros for blocks that are not allocated and for indices
+ * outside the block-index range.  All three buffers are caller-owned device
+ * memory of n_blocks triples / n_blocks * 512 floats.
+ * Only enqueues work.  Errors: TSDF_EINVAL (NULL map, n_blocks < 0, NULL
+ * buffers with n_blocks > 0), TSDF_EDEVICE. */
 TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks,
                float *out_dist_dev, float *out_weight_dev, void *hip_stream);
 
@@ -230,7 +255,17 @@ typedef struct {
     long long touched_blocks;  /* one per block per call in which any of its voxels was updated */
     long long launches;        /* integration calls enqueued */
     long long candidate_blocks;  /* one per block per call that survived culling and was measured */
+    long long block_capacity;  /* blocks the pool holds (grows with reserve) */
+    long long hash_capacity;   /* slots of the block hash */
+    long long error_bits;      /* sticky device-side error bits (TSDF_ERR_*), 0 if healthy */
 } tsdf_stats;
+
+/* Device-side error bits behind TSDF_EFULL (tsdf_stats.error_bits). */
+#define TSDF_ERR_POOL_FULL 1          /* a new block found no free pool slot */
+#define TSDF_ERR_HASH_FULL 2          /* a new block's probe found no free hash slot */
+#define TSDF_ERR_TOUCHED_OVERFLOW 4   /* the touched list ran out of room */
+#define TSDF_ERR_INSERT_RACE 8        /* a published key's slot value never appeared (bounded wait) */
+#define TSDF_ERR_WALK_OUTSIDE 16      /* a ray walk left the frame's block lattice */
 
 /* Fills *out.  Synchronises hip_stream. */
 TSDF_API int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream);

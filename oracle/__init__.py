@@ -41,6 +41,8 @@ def _load():
     lib.ora_round_binary16.argtypes = [C.c_float]
     lib.ora_integrate_depth.restype = C.c_longlong
     lib.ora_integrate_depth.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p]
+    lib.ora_integrate_depth_threads.restype = C.c_longlong
+    lib.ora_integrate_depth_threads.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p, C.c_int]
     lib.ora_integrate_depth_range.restype = C.c_longlong
     lib.ora_integrate_depth_range.argtypes = [C.c_void_p, f32p, C.c_int, C.c_int, f32p, f32p, C.c_float]
     lib.ora_integrate_range.restype = C.c_longlong
@@ -125,6 +127,15 @@ class OracleMap:
                                                max_range)
         else:
             n = _lib.ora_integrate_depth(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16))
+        if n < 0:
+            raise ValueError("oracle rejected the frame")
+        return int(n)
+
+    def integrate_threads(self, depth: np.ndarray, K, T_world_cam, threads: int) -> int:
+        """integrate() on `threads` OpenMP threads (bitwise the same map)."""
+        depth = _f32(depth)
+        H, W = depth.shape
+        n = _lib.ora_integrate_depth_threads(self._h, depth, W, H, _f32(K, 4), _f32(T_world_cam, 16), int(threads))
         if n < 0:
             raise ValueError("oracle rejected the frame")
         return int(n)

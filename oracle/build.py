@@ -2,7 +2,8 @@
 
 The flags keep every binary32 operation a single correctly rounded IEEE-754
 operation: no contraction into fused multiply-add, no fast-math, SSE scalar
-arithmetic (the x86-64 default).
+arithmetic (the x86-64 default).  OpenMP serves only the multi-threaded
+entry point used to time the CPU baseline on all cores.
 """
 import os
 import subprocess
@@ -11,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libtsdf_oracle.so")
 CFLAGS = ["-std=c99", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-fexcess-precision=standard", "-Wall", "-Wno-unused-function"]
+          "-fexcess-precision=standard", "-fopenmp", "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:

@@ -513,6 +513,90 @@ static long long FN(integrate)(ora_map *m, const float *depth, int width, int he
     return FN(integrate_any)(m, depth, width, height, K, NULL, T);
 }
 
+/* The same frame as FN(integrate), spread over `threads` OpenMP threads for
+ * timing the CPU baseline on all host cores.  The scan box is taken in the
+ * same block order in chunks: the chunk's blocks are measured in parallel
+ * (each voxel exactly as above, into per-block buffers), then looked up or
+ * inserted one after the other in scan order, so the map receives the same
+ * block indices in the same order, then fused in parallel (distinct blocks).
+ * The result is bitwise the single-threaded one. */
+static long long FN(integrate_threads)(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                       const float T[16], int threads)
+{
+    enum { CHUNK = 2048 };
+    FN(frame) f;
+    FN(frame_setup)(&f, &m->p, depth, width, height, K, T);
+    m->n_touched = 0;
+    int32_t bmin[3], bmax[3];
+    if (!FN(scan_box)(&f, K, T, bmin, bmax)) {
+        for (int a = 0; a < 3; ++a) { m->scan_min[a] = 0; m->scan_max[a] = -1; }
+        return 0;
+    }
+    for (int a = 0; a < 3; ++a) { m->scan_min[a] = bmin[a]; m->scan_max[a] = bmax[a]; }
+    const long long nx = (long long)bmax[0] - bmin[0] + 1, ny = (long long)bmax[1] - bmin[1] + 1;
+    const long long nz = (long long)bmax[2] - bmin[2] + 1, n_lat = nx * ny * nz;
+    REAL *xs = (REAL *)malloc((size_t)CHUNK * 512 * sizeof(REAL));
+    REAL *ws = (REAL *)malloc((size_t)CHUNK * 512 * sizeof(REAL));
+    unsigned char *hit = (unsigned char *)malloc((size_t)CHUNK * 512);
+    unsigned char *any = (unsigned char *)malloc(CHUNK);
+    long long *slot = (long long *)malloc((size_t)CHUNK * sizeof(long long));
+    long long updates = 0;
+    int failed = !xs || !ws || !hit || !any || !slot;
+    for (long long c0 = 0; c0 < n_lat && !failed; c0 += CHUNK) {
+        const int nc = (int)(n_lat - c0 < CHUNK ? n_lat - c0 : CHUNK);
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 16)
+        for (int q = 0; q < nc; ++q) {
+            const long long lb = c0 + q;   /* scan order: x fastest, then y, then z */
+            const int32_t bx = bmin[0] + (int32_t)(lb % nx), by = bmin[1] + (int32_t)((lb / nx) % ny),
+                          bz = bmin[2] + (int32_t)(lb / (nx * ny));
+            int a = 0;
+            for (int k = 0; k < 512; ++k) {
+                hit[512 * q + k] = (unsigned char)FN(voxel_measure)(&f, 8 * bx + (k & 7), 8 * by + ((k >> 3) & 7),
+                                                                     8 * bz + (k >> 6), &xs[512 * q + k],
+                                                                     &ws[512 * q + k]);
+                a |= hit[512 * q + k];
+            }
+            any[q] = (unsigned char)a;
+        }
+        for (int q = 0; q < nc && !failed; ++q) {
+            slot[q] = -1;
+            if (!any[q])
+                continue;
+            const long long lb = c0 + q;
+            slot[q] = map_find_or_insert(m, bmin[0] + (int32_t)(lb % nx), bmin[1] + (int32_t)((lb / nx) % ny),
+                                         bmin[2] + (int32_t)(lb / (nx * ny)));
+            if (slot[q] < 0 || touched_push(m, slot[q]) != 0)
+                failed = 1;
+        }
+        if (failed)
+            break;
+        long long n_upd = 0;
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 16) reduction(+ : n_upd)
+        for (int q = 0; q < nc; ++q) {
+            if (slot[q] < 0)
+                continue;
+            REAL *D = FN(dist_ptr)(m) + 512 * slot[q];
+            REAL *W = FN(weight_ptr)(m) + 512 * slot[q];
+            for (int k = 0; k < 512; ++k)
+                if (hit[512 * q + k]) {
+                    FN(voxel_fuse)(&D[k], &W[k], xs[512 * q + k], ws[512 * q + k], f.w_max);
+                    if (m->storage16) {
+                        D[k] = (REAL)ora_round_binary16((float)D[k]);
+                        W[k] = (REAL)ora_round_binary16((float)W[k]);
+                    }
+                    ++n_upd;
+                }
+        }
+        updates += n_upd;
+    }
+    free(xs);
+    free(ws);
+    free(hit);
+    free(any);
+    free(slot);
+    return failed ? -1 : updates;
+}
+
 static void FN(export_voxels)(const ora_map *m, double *dist, double *weight)
 {
     const REAL *D = (const REAL *)m->dist;

@@ -1,9 +1,11 @@
 /*
  * tsdf_oracle.c -- CPU oracle for projective TSDF integration (nvblox §IV).
  *
- * TEST INFRASTRUCTURE ONLY (see tsdf_oracle.h).  Plain C99, single-threaded,
- * built with -ffp-contract=off -fno-fast-math so every binary32 operation is
- * one correctly rounded IEEE-754 operation.
+ * TEST INFRASTRUCTURE ONLY (see tsdf_oracle.h).  Plain C99, built with
+ * -ffp-contract=off -fno-fast-math so every binary32 operation is one
+ * correctly rounded IEEE-754 operation.  Single-threaded, except
+ * ora_integrate_depth_threads (OpenMP), which times the CPU baseline on all
+ * host cores and gives the single-threaded result bit for bit.
  *
  * The sparse map follows the paper's two-level layout (§IV-A): a hash table
  * from integer block index (x, y, z) to a block of 8 x 8 x 8 voxels stored
@@ -290,6 +292,15 @@ long long ora_integrate_depth(ora_map *m, const float *depth, int width, int hei
         return -1;
     return m->precision == 32 ? integrate_f32(m, depth, width, height, K, T)
                               : integrate_f64(m, depth, width, height, K, T);
+}
+
+long long ora_integrate_depth_threads(ora_map *m, const float *depth, int width, int height, const float K[4],
+                                      const float T[16], int threads)
+{
+    if (!m || !frame_args_ok(depth, width, height, K, T) || threads < 1)
+        return -1;
+    return m->precision == 32 ? integrate_threads_f32(m, depth, width, height, K, T, threads)
+                              : integrate_threads_f64(m, depth, width, height, K, T, threads);
 }
 
 long long ora_integrate_depth_dda(ora_map *m, const float *depth, int width, int height, const float K[4],

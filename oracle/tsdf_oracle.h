@@ -62,6 +62,12 @@ float ora_round_binary16(float x);
  * Returns the number of voxel updates, or -1 on bad arguments / no memory. */
 long long ora_integrate_depth(ora_map *m, const float *depth, int width, int height,
                               const float K[4], const float T_world_cam[16]);
+/* ora_integrate_depth on `threads` (>= 1) OpenMP threads: the blocks of the
+ * scan box are measured in parallel, inserted one by one in the same scan
+ * order and fused in parallel, so the map is bitwise the single-threaded one.
+ * For timing the CPU baseline on all host cores. */
+long long ora_integrate_depth_threads(ora_map *m, const float *depth, int width, int height,
+                                      const float K[4], const float T_world_cam[16], int threads);
 /* Same frame, with the paper-literal allocation: the blocks visited by a
  * walk through the block grid (Amanatides & Woo) along every valid pixel's
  * centre ray, from the camera to min(d + epsilon, max range), are allocated

@@ -35,6 +35,12 @@ struct tsdf_map {
     uint2 *cand = nullptr;                // compacted launches: candidate list
     long long cand_cap = 0;
     long long sm_slot = 0;                // pixels per slot of sm_maps
+    // query_blocks work buffers, allocated on its first call (block_cap keys)
+    unsigned long long *q_sorted = nullptr;
+    void *q_temp = nullptr;
+    size_t q_temp_bytes = 0;
+    unsigned long long *q_count = nullptr;
+    std::vector<tsdf_step *> steps;       // live graph steps of this map (reserve drops their graphs)
     // kernel timing
     bool profiling;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -114,6 +120,17 @@ int hip_status(hipError_t e)
     return TSDF_EDEVICE;
 }
 
+void free_query_buffers(tsdf_map *m)
+{
+    (void)hipFree(m->q_sorted);
+    (void)hipFree(m->q_temp);
+    (void)hipFree(m->q_count);
+    m->q_sorted = nullptr;
+    m->q_temp = nullptr;
+    m->q_count = nullptr;
+    m->q_temp_bytes = 0;
+}
+
 void free_device(tsdf_map *m)
 {
     DeviceMap &d = m->dm;
@@ -138,6 +155,7 @@ void free_device(tsdf_map *m)
     (void)hipFree(m->cand);
     m->cand = nullptr;
     m->cand_cap = 0;
+    free_query_buffers(m);
 }
 
 void free_events(tsdf_map *m)
@@ -898,15 +916,24 @@ struct tsdf_step {
     int next;
 };
 
-static void step_free(tsdf_step *st)
+// Destroys the step's captured graphs; each is captured again on its next use.
+static void step_drop_graphs(tsdf_step *st)
 {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 2; ++k)
         for (int mode = 0; mode < kStepModes; ++mode) {
             if (st->exec[k][mode])
                 (void)hipGraphExecDestroy(st->exec[k][mode]);
             if (st->graph[k][mode])
                 (void)hipGraphDestroy(st->graph[k][mode]);
+            st->exec[k][mode] = nullptr;
+            st->graph[k][mode] = nullptr;
         }
+}
+
+static void step_free(tsdf_step *st)
+{
+    step_drop_graphs(st);
+    for (int k = 0; k < 2; ++k) {
         if (st->done[k])
             (void)hipEventDestroy(st->done[k]);
         if (st->pinned[k])
@@ -1026,6 +1053,12 @@ int tsdf_step_create(tsdf_map *m, int with_spherical, tsdf_step **out)
         step_free(st);
         return hip_status(e);
     }
+    try {
+        m->steps.push_back(st);
+    } catch (...) {
+        step_free(st);
+        return TSDF_ENOMEM;
+    }
     *out = st;
     return TSDF_OK;
 }
@@ -1088,7 +1121,100 @@ int tsdf_step_destroy(tsdf_step *st)
     for (int k = 0; k < 2; ++k)
         if (st->pending[k])
             (void)hipEventSynchronize(st->done[k]);
+    std::vector<tsdf_step *> &v = st->m->steps;
+    v.erase(std::remove(v.begin(), v.end(), st), v.end());
     step_free(st);
+    return TSDF_OK;
+}
+
+int reserve(tsdf_map *m, long long block_capacity)
+{
+    if (!m || block_capacity < 1 || block_capacity > (1ll << 30))
+        return TSDF_EINVAL;
+    if (block_capacity <= (long long)m->dm.block_cap)
+        return TSDF_OK;
+    // no stream of this process may be capturing: the device is synchronised
+    // and memory is allocated and freed below
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return TSDF_ESTATE;
+    hipError_t e = use_device(m);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();    // every queued launch has read the old buffers
+    if (e != hipSuccess)
+        return hip_status(e);
+    const DeviceMap old = m->dm;
+    long long hc = (long long)old.hash_mask + 1;
+    while (hc < 2 * block_capacity)
+        hc *= 2;
+    const size_t bc = (size_t)block_capacity;
+    const size_t vb = voxel_bytes(old.storage) * kBlockVoxels;
+    uint32_t used = 0;
+    e = hipMemcpy(&used, old.counters + kNumBlocks, sizeof(used), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_status(e);
+    used = std::min(used, old.block_cap);   // slots past the old capacity were never published
+    DeviceMap d = old;
+    d.keys = nullptr;
+    d.vals = nullptr;
+    d.pool = nullptr;
+    d.slot_keys = nullptr;
+    d.touched = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&d.keys, sizeof(unsigned long long) * (size_t)hc);
+    if (e == hipSuccess) e = hipMalloc(&d.vals, sizeof(uint32_t) * (size_t)hc);
+    if (e == hipSuccess) e = hipMalloc(&d.pool, vb * bc);
+    if (e == hipSuccess) e = hipMalloc(&d.slot_keys, sizeof(unsigned long long) * bc);
+    if (e == hipSuccess) e = hipMalloc(&d.touched, sizeof(uint32_t) * bc * kSubLists);
+    if (e == hipSuccess) e = hipMemset(d.keys, 0xFF, sizeof(unsigned long long) * (size_t)hc);
+    if (e == hipSuccess) e = hipMemset(d.vals, 0xFF, sizeof(uint32_t) * (size_t)hc);
+    // blocks keep their pool slots; the new tail of the pool is zero (fresh blocks need no clearing)
+    if (e == hipSuccess && used > 0) e = hipMemcpy(d.pool, old.pool, vb * used, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemset((char *)d.pool + vb * used, 0, vb * (bc - used));
+    if (e == hipSuccess && used > 0)
+        e = hipMemcpy(d.slot_keys, old.slot_keys, sizeof(unsigned long long) * used, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess)
+        e = hipMemset(d.slot_keys + used, 0xFF, sizeof(unsigned long long) * (bc - used));
+    // the last launch's touched sub-lists, at the new stride
+    for (int k = 0; k < kSubLists && e == hipSuccess; ++k)
+        e = hipMemcpy(d.touched + (size_t)k * bc, old.touched + (size_t)k * old.block_cap,
+                      sizeof(uint32_t) * old.block_cap, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess && used > 0)
+        e = launch_rehash(d.slot_keys, used, d.keys, d.vals, (uint32_t)(hc - 1), nullptr);
+    // recovery: the counter drops back to the slots in use and the error word clears
+    const uint32_t zero = 0;
+    if (e == hipSuccess) e = hipMemcpy(d.counters + kNumBlocks, &used, sizeof(used), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.counters + kErrorBits, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(d.keys);
+        (void)hipFree(d.vals);
+        (void)hipFree(d.pool);
+        (void)hipFree(d.slot_keys);
+        (void)hipFree(d.touched);
+        return hip_status(e);
+    }
+    // graphs of the map's steps hold the old buffers: capture them again on their next run
+    for (tsdf_step *st : m->steps) {
+        for (int k = 0; k < 2; ++k)
+            if (st->pending[k]) {
+                (void)hipEventSynchronize(st->done[k]);
+                st->pending[k] = false;
+            }
+        step_drop_graphs(st);
+    }
+    (void)hipFree(old.keys);
+    (void)hipFree(old.vals);
+    (void)hipFree(old.pool);
+    (void)hipFree(old.slot_keys);
+    (void)hipFree(old.touched);
+    free_query_buffers(m);
+    d.hash_mask = (uint32_t)(hc - 1);
+    d.block_cap = (uint32_t)bc;
+    m->dm = d;
+    m->p.block_capacity = block_capacity;
+    m->p.hash_capacity = hc;
+    m->sticky = 0;
     return TSDF_OK;
 }
 
@@ -1103,40 +1229,49 @@ int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lon
     int st = read_counters(m, cs, s);
     if (st != TSDF_OK)
         return st;
-    long long n = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
+    const long long n = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
     *out_count = 0;
     if (n == 0)
         return m->sticky;
-    unsigned long long *sorted = nullptr;
-    hipError_t e = hipMalloc(&sorted, sizeof(unsigned long long) * (size_t)n);
-    if (e != hipSuccess)
-        return hip_status(e);
-    e = sort_keys(m->dm.slot_keys, sorted, n, s);
-    // slots reserved but never published keep kEmptyKey, which sorts last
-    long long valid = n;
-    if (e == hipSuccess) {
-        long long lo = 0, hi = n;   // first index holding kEmptyKey
-        while (lo < hi) {
-            const long long mid = (lo + hi) / 2;
-            unsigned long long k = 0;
-            e = hipMemcpy(&k, sorted + mid, sizeof(k), hipMemcpyDeviceToHost);
-            if (e != hipSuccess)
-                break;
-            if (k == kEmptyKey)
-                hi = mid;
-            else
-                lo = mid + 1;
+    // work buffers sized for the whole pool, kept for later calls
+    hipError_t e = hipSuccess;
+    if (!m->q_sorted)
+        e = hipMalloc((void **)&m->q_sorted, sizeof(unsigned long long) * (size_t)m->dm.block_cap);
+    if (e == hipSuccess && !m->q_count)
+        e = hipMalloc((void **)&m->q_count, sizeof(unsigned long long));
+    size_t need = 0;
+    if (e == hipSuccess)
+        e = sort_keys(m->dm.slot_keys, m->q_sorted, n, nullptr, &need, s);
+    if (e == hipSuccess && (!m->q_temp || need > m->q_temp_bytes)) {
+        size_t full = 0;   // the work space of a full pool, so that later calls never grow it
+        e = sort_keys(m->dm.slot_keys, m->q_sorted, m->dm.block_cap, nullptr, &full, s);
+        if (e == hipSuccess) {
+            (void)hipFree(m->q_temp);
+            m->q_temp = nullptr;
+            m->q_temp_bytes = 0;
+            const size_t bytes = std::max<size_t>(std::max(need, full), 1);
+            e = hipMalloc(&m->q_temp, bytes);
+            if (e == hipSuccess)
+                m->q_temp_bytes = bytes;
         }
-        valid = lo;
     }
-    if (e == hipSuccess && capacity > 0 && valid > 0)
-        e = launch_decode_keys(sorted, std::min(valid, capacity), out_xyz_dev, s);
+    if (e == hipSuccess) {
+        size_t bytes = m->q_temp_bytes;
+        e = sort_keys(m->dm.slot_keys, m->q_sorted, n, m->q_temp, &bytes, s);
+    }
+    // slots reserved but never published keep kEmptyKey, which sorts last
+    if (e == hipSuccess)
+        e = launch_count_valid(m->q_sorted, n, m->q_count, s);
+    if (e == hipSuccess && capacity > 0)
+        e = launch_decode_keys(m->q_sorted, std::min(n, capacity), out_xyz_dev, s);
+    unsigned long long valid = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&valid, m->q_count, sizeof(valid), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
-    (void)hipFree(sorted);
     if (e != hipSuccess)
         return hip_status(e);
-    *out_count = valid;
+    *out_count = (long long)valid;
     return m->sticky;
 }
 
@@ -1215,6 +1350,9 @@ int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream)
     out->touched_blocks = touched;
     out->launches = m->frames;
     out->candidate_blocks = (long long)cand;
+    out->block_capacity = (long long)m->dm.block_cap;
+    out->hash_capacity = (long long)m->dm.hash_mask + 1;
+    out->error_bits = (long long)cs.c[kErrorBits];
     return TSDF_OK;
 }
 

@@ -95,26 +95,39 @@ __device__ __forceinline__ uint32_t load_val(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// First 64-slot probe window of a key (lane l reads slot h + l).
+// One probe window: lane l < width reads slot (start + base + l) & mask, the
+// other lanes hold kNoKey.  The first window of a key covers its 16-slot
+// bucket (one key line, one value line), later windows 64 slots each.
 struct ProbeWindow {
     unsigned long long k;
     uint32_t v;
 };
 
-__device__ __forceinline__ ProbeWindow load_window(const DeviceMap &dm, uint32_t h, uint32_t base)
+__device__ __forceinline__ ProbeWindow load_window(const DeviceMap &dm, uint32_t start, uint32_t base, uint32_t width)
 {
-    const uint32_t pos = (h + base + (uint32_t)lane_id()) & dm.hash_mask;
-    return ProbeWindow{load_key(&dm.keys[pos]), load_val(&dm.vals[pos])};
+    ProbeWindow w{kNoKey, kInvalidSlot};
+    if ((uint32_t)lane_id() < width) {
+        const uint32_t pos = (start + base + (uint32_t)lane_id()) & dm.hash_mask;
+        w.k = load_key(&dm.keys[pos]);
+        w.v = load_val(&dm.vals[pos]);
+    }
+    return w;
+}
+
+// The first window of a key (its bucket).
+__device__ __forceinline__ ProbeWindow load_first_window(const DeviceMap &dm, uint32_t start)
+{
+    return load_window(dm, start, 0, kBucketSlots);
 }
 
 // Pool slot behind a hit found at window position f_hit (waits, bounded, for
 // a value that is published after its key).
-__device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t h, uint32_t base, int f_hit,
+__device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t start, uint32_t base, int f_hit,
                                                uint32_t v)
 {
     uint32_t slot = (uint32_t)__shfl((int)v, f_hit);
     if (slot == kInvalidSlot) {
-        const uint32_t at = (h + base + (uint32_t)f_hit) & dm.hash_mask;
+        const uint32_t at = (start + base + (uint32_t)f_hit) & dm.hash_mask;
         if (lane_id() == 0) {
             for (int spin = 0; slot == kInvalidSlot && spin < (1 << 20); ++spin)
                 slot = load_val(&dm.vals[at]);
@@ -126,51 +139,54 @@ __device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t h,
     return slot;
 }
 
-// Read-only lookup of `key` (wave-uniform) starting from a preloaded first
-// window: the pool slot, or kInvalidSlot if the key is absent.
-__device__ inline uint32_t find_block(const DeviceMap &dm, unsigned long long key, uint32_t h, ProbeWindow w)
+// Read-only lookup of `key` (wave-uniform) starting from its preloaded first
+// window: the pool slot, or kInvalidSlot if the key is absent.  Windows are
+// scanned in probe order; the first slot holding the key or empty decides.
+__device__ inline uint32_t find_block(const DeviceMap &dm, unsigned long long key, uint32_t start, ProbeWindow w)
 {
-    for (uint32_t base = 0; base <= dm.hash_mask; base += 64) {
+    uint32_t width = kBucketSlots;
+    for (uint32_t base = 0; base <= dm.hash_mask; base += width, width = 64) {
         if (base != 0)
-            w = load_window(dm, h, base);
+            w = load_window(dm, start, base, 64);
         const unsigned long long m_hit = __ballot(w.k == key);
         const unsigned long long m_free = __ballot(w.k == kEmptyKey);
         const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
         const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
         if (f_hit < f_free)
-            return (uint32_t)wave_bcast((int)slot_of_hit(dm, h, base, f_hit, w.v));
+            return (uint32_t)wave_bcast((int)slot_of_hit(dm, start, base, f_hit, w.v));
         if (f_free < 64)
             return kInvalidSlot;
     }
     return kInvalidSlot;
 }
 
-// Wave-cooperative find-or-insert of `key` (wave-uniform).  The 64 lanes look
-// at 64 consecutive slots per step; the first slot in probe order that holds
-// the key or is empty decides.  w is the first window, loaded ahead of time.
-// Returns the pool slot, or kInvalidSlot after recording an overflow.
-__device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key, uint32_t h, ProbeWindow w)
+// Wave-cooperative find-or-insert of `key` (wave-uniform).  Lanes look at the
+// slots of one window at a time, in probe order; the first slot that holds
+// the key or is empty decides.  w is the key's first window, loaded ahead of
+// time.  Returns the pool slot, or kInvalidSlot after recording an overflow.
+__device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key, uint32_t start, ProbeWindow w)
 {
     const int lane = lane_id();
     const uint32_t mask = dm.hash_mask;
     uint32_t fresh = kInvalidSlot;   // pool slot reserved for an insert (wave-uniform)
-    uint32_t base = 0;
+    uint32_t base = 0, width = kBucketSlots;
     bool loaded = true;
     while (base <= mask) {
         if (!loaded)
-            w = load_window(dm, h, base);
+            w = load_window(dm, start, base, width);
         loaded = false;
         const unsigned long long m_hit = __ballot(w.k == key);
         const unsigned long long m_free = __ballot(w.k == kEmptyKey);
         const int f_hit = m_hit ? __builtin_ctzll(m_hit) : 64;
         const int f_free = m_free ? __builtin_ctzll(m_free) : 64;
         if (f_hit < f_free)
-            return (uint32_t)wave_bcast((int)slot_of_hit(dm, h, base, f_hit, w.v));
+            return (uint32_t)wave_bcast((int)slot_of_hit(dm, start, base, f_hit, w.v));
         if (f_free == 64) {
-            base += 64;
+            base += width;
+            width = 64;
             continue;
         }
-        const uint32_t at = (h + base + (uint32_t)f_free) & mask;
+        const uint32_t at = (start + base + (uint32_t)f_free) & mask;
         int won = 0;
         if (lane == 0) {
             if (fresh == kInvalidSlot) {

@@ -52,8 +52,8 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
         ++n_cands;
         // first hash probe window, consumed only if the block is touched
         const unsigned long long key = pack_key(bx, by, bz);
-        const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
-        const ProbeWindow w0 = load_window(dm, h, 0);
+        const uint32_t h = probe_start(key, dm.hash_mask);
+        const ProbeWindow w0 = load_first_window(dm, h);
 
         // voxel centre p = ((float)g + 0.5) * vs
         const float px = ((float)(8 * bx + lx) + 0.5f) * fa.mc.vs;

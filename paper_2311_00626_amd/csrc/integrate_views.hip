@@ -50,8 +50,8 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     auto block = [&](int bx, int by, int bz, uint32_t vmask) {
         ++n_cands;
         const unsigned long long key = pack_key(bx, by, bz);
-        const uint32_t h = (uint32_t)hash_key(key) & dm.hash_mask;
-        const ProbeWindow w0 = load_window(dm, h, 0);
+        const uint32_t h = probe_start(key, dm.hash_mask);
+        const ProbeWindow w0 = load_first_window(dm, h);
 
         const float px = ((float)(8 * bx + lx) + 0.5f) * va.mc.vs;
         const float py = ((float)(8 * by + ly) + 0.5f) * va.mc.vs;

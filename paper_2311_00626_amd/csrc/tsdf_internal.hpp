@@ -199,6 +199,18 @@ __host__ __device__ inline unsigned long long hash_key(unsigned long long k)
     return k;
 }
 
+// Linear probing from the first slot of the key's 16-slot bucket: the first
+// probe window is then exactly one 128-byte line of keys and one 64-byte line
+// of values.  Every insert and lookup scans slots in the same order from here.
+constexpr uint32_t kBucketSlots = 16;
+__host__ __device__ inline uint32_t probe_start(unsigned long long key, uint32_t mask)
+{
+    return (uint32_t)hash_key(key) & mask & ~(kBucketSlots - 1u);
+}
+// What a probe-window lane that reads no slot holds: bit 63 set, so it is
+// neither kEmptyKey nor any packed key (3 x 21 bits).
+constexpr unsigned long long kNoKey = ~0ull - 1ull;
+
 // Kernel launchers (integrate.hip, query.hip).
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
                                   hipStream_t stream);
@@ -242,7 +254,14 @@ hipError_t launch_fill_u8(unsigned char *p, long long n, hipStream_t stream);
 hipError_t launch_footprint_tiles(const ViewsArgs &va, hipStream_t stream);
 hipError_t launch_footprint_tiles_dev(const ViewsArgs *va_dev, hipStream_t stream);
 hipError_t launch_gather_touched(const DeviceMap &dm, int sub, long long n, int32_t *xyz, hipStream_t stream);
-hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n,
-                     hipStream_t stream);
+// temp == nullptr: *temp_bytes receives the work space n keys need
+hipError_t sort_keys(const unsigned long long *in, unsigned long long *out, long long n, void *temp,
+                     size_t *temp_bytes, hipStream_t stream);
+// *count = number of keys before the first kEmptyKey of n ascending keys
+hipError_t launch_count_valid(const unsigned long long *keys, long long n, unsigned long long *count,
+                              hipStream_t stream);
+// Inserts the keys of pool slots [0, n) into an empty table of mask + 1 slots.
+hipError_t launch_rehash(const unsigned long long *slot_keys, uint32_t n, unsigned long long *keys, uint32_t *vals,
+                         uint32_t mask, hipStream_t stream);
 
 }  // namespace tsdf

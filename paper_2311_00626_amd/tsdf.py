@@ -34,7 +34,12 @@ class TsdfError(RuntimeError):
 class tsdf_stats(C.Structure):
     _fields_ = [("blocks", C.c_longlong), ("voxel_updates", C.c_longlong),
                 ("voxel_writes", C.c_longlong), ("touched_blocks", C.c_longlong),
-                ("launches", C.c_longlong), ("candidate_blocks", C.c_longlong)]
+                ("launches", C.c_longlong), ("candidate_blocks", C.c_longlong),
+                ("block_capacity", C.c_longlong), ("hash_capacity", C.c_longlong),
+                ("error_bits", C.c_longlong)]
+
+# tsdf_stats.error_bits
+ERR_POOL_FULL, ERR_HASH_FULL, ERR_TOUCHED_OVERFLOW, ERR_INSERT_RACE, ERR_WALK_OUTSIDE = 1, 2, 4, 8, 16
 
 
 class tsdf_depth_view(C.Structure):
@@ -89,6 +94,7 @@ def _load() -> C.CDLL:
     lib.create_map.argtypes = [C.c_float, C.c_float, C.POINTER(vp)]
     lib.create_map_ex.argtypes = [C.POINTER(tsdf_params), C.POINTER(vp)]
     lib.destroy_map.argtypes = [vp]
+    lib.reserve.argtypes = [vp, ll]
     lib.integrate_depth.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
@@ -111,7 +117,7 @@ def _load() -> C.CDLL:
     lib.tsdf_sm_trainer_destroy.argtypes = [vp]
     lib.tsdf_sm_loss_grad.argtypes = [vp, vp, i, vp, vp, vp, C.c_float, C.c_float, ll, vp, vp, vp, vp, vp]
     lib.tsdf_sm_adam.argtypes = [vp, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float, i, vp]
-    for name in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "integrate_depth_views",
+    for name in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth", "integrate_depth_views",
                  "integrate_range",
                  "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
@@ -124,7 +130,7 @@ def _load() -> C.CDLL:
 
 lib = _load()
 
-EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "integrate_depth",
+EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth",
             "integrate_depth_views", "integrate_range",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
             "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config",
@@ -265,6 +271,12 @@ class TsdfMap:
             self.close()
         except Exception:
             pass
+
+    def reserve(self, block_capacity: int) -> None:
+        """Grows the block pool (and the hash) to block_capacity blocks; every
+        block keeps its voxels.  Also clears a sticky overflow (see tsdf.h)."""
+        _check(lib.reserve(self._h, int(block_capacity)), "reserve")
+        self.block_capacity = max(self.block_capacity, int(block_capacity))
 
     # -- integration --------------------------------------------------------
     def integrate_depth(self, depth: torch.Tensor, K: Sequence[float], T_world_cam,

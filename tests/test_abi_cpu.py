@@ -23,8 +23,9 @@ def t():
 
 def test_header_declares_expected_entry_points():
     names = set(declared_functions())
-    for n in ("create_map", "create_map_ex", "destroy_map", "integrate_depth", "query_blocks",
-              "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_strerror"):
+    for n in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth", "integrate_range",
+              "integrate_depth_views", "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
+              "tsdf_strerror"):
         assert n in names
 
 
@@ -37,7 +38,7 @@ def test_every_declared_symbol_is_exported(t):
 def test_struct_layouts(t):
     assert C.sizeof(t.tsdf_depth_view) == 112
     assert C.sizeof(t.tsdf_lidar_model) == 32
-    assert C.sizeof(t.tsdf_stats) == 48
+    assert C.sizeof(t.tsdf_stats) == 72
     assert C.sizeof(t.tsdf_launch_config) == 20
 
 
@@ -88,6 +89,7 @@ def test_null_map_rejected(t):
     assert t.lib.integrate_depth_views(None, views, 1, None) == t.EINVAL
     assert t.lib.map_status(None) == t.EINVAL
     assert t.lib.destroy_map(None) == t.OK
+    assert t.lib.reserve(None, 1024) == t.EINVAL
     step = C.c_void_p()
     assert t.lib.tsdf_step_create(None, 0, C.byref(step)) == t.EINVAL and not step.value
     assert t.lib.tsdf_step_run(None, views, 1, None) == t.EINVAL
@@ -135,3 +137,23 @@ def test_view_record_layout_matches_struct():
         assert (v.width, v.height, v.model) == (int(rec["width"][k]), int(rec["height"][k]), int(rec["model"][k]))
         assert v.max_range_m == rec["max_range_m"][k] and v.interp_max_diff_m == rec["interp_max_diff_m"][k]
         assert list(v.K) == list(rec["K"][k]) and list(v.T_world_cam) == list(rec["T_world_cam"][k])
+
+
+def test_hash_capacity_rules(t):
+    """hash_capacity: 0 (automatic) or a power of two no smaller than the
+    pool, down to tiny tables whose 32 slots the 64-lane probe window covers
+    twice; rejected values fail before any device call, accepted ones get
+    past validation (on a machine without a GPU the device call then fails)."""
+    h = C.c_void_p()
+    for bc, hc, ok in ((32, 32, True), (32, 64, True), (1, 1, True), (1000, 1024, True), (1024, 1024, True),
+                       (33, 32, False), (32, 48, False), (32, 16, False), ((1 << 30) + 1, 0, False),
+                       (1 << 20, 1 << 32, False)):
+        q = t.default_params(0.05, 4.0)
+        q.block_capacity, q.hash_capacity = bc, hc
+        st = t.lib.create_map_ex(C.byref(q), C.byref(h))
+        if ok:
+            assert st != t.EINVAL, (bc, hc)
+            if st == t.OK:
+                t.lib.destroy_map(h)
+        else:
+            assert st == t.EINVAL and not h.value, (bc, hc)

@@ -1,13 +1,18 @@
 """Parity at the measured workloads' full sizes, in the launch configurations
-the benchmark times: the 300-frame cluttered room (640x480, 4 cm) one frame
-per launch and 16 per launch, the 300-frame box room at 1 cm, and 500 rig
-steps (4 cameras + LiDAR) replayed from graphs.  The oracle cannot fuse these
-whole in a test, so sampled blocks are checked against its dense evaluator
-(every voxel of a box fused frame by frame, no hash or candidates), which
-computes any voxel on its own: allocated sampled blocks hold bit-identical
-(D, W), sampled blocks the GPU did not allocate receive no update, and every
-allocated block holds an updated voxel (the allocation rule, checked over the
-whole map)."""
+the benchmark times.
+
+The headline 300-frame cluttered room (640x480, 4 cm) and the 300-frame box
+room at 1 cm are fused whole by the sparse oracle (the 1 cm room on all host
+cores through its multi-threaded entry point, bitwise the single-threaded
+map): every allocated block, every voxel and the touched set after every
+launch are compared, one frame per launch and (4 cm) 16 per launch.  500 rig
+steps (4 cameras + a LiDAR reaching 25 m, whose scan box holds ~10^8 voxels
+per range image) replayed from graphs would take the oracle many minutes, so
+there sampled blocks are checked against its dense evaluator (every voxel of
+a box fused frame by frame, no hash or candidates), which computes any voxel
+on its own: allocated sampled blocks hold bit-identical (D, W), sampled
+blocks the GPU did not allocate receive no update, and every allocated block
+holds an updated voxel (the allocation rule, checked over the whole map)."""
 import numpy as np
 import pytest
 import torch
@@ -61,10 +66,25 @@ def check_map(gm, rng, dense_of_block, n_alloc=10, n_absent=6):
             "updated_voxels_in_sample": updated}
 
 
+@pytest.fixture(scope="module")
 def cluttered():
     w = synth.cluttered_room_sequence(300)
     frames = w.frames(device="cuda", count=300)
     return w, frames, [torch.as_tensor(f, device="cuda") for f in frames]
+
+
+@pytest.fixture(scope="module")
+def cluttered_oracle(cluttered):
+    """The binary32 oracle over all 300 frames: its sorted final state and
+    the touched set of every frame."""
+    import oracle
+    w, frames, _ = cluttered
+    om = oracle.OracleMap.from_params(w.params)
+    touched = []
+    for d, T in zip(frames, w.poses):
+        om.integrate(d, w.camera.K, T)
+        touched.append({tuple(x) for x in om.touched()})
+    return om.sorted_state(), touched
 
 
 def dense_frames(params, frames, K, poses):
@@ -75,39 +95,71 @@ def dense_frames(params, frames, K, poses):
     return of_block
 
 
-def test_cluttered_room_300_frames_one_per_launch():
-    w, frames, dev = cluttered()
-    say("case: cluttered room 640x480 / 4 cm, all 300 frames one per launch (default launch shape), sampled blocks")
+def test_cluttered_room_300_frames_one_per_launch(cluttered, cluttered_oracle):
+    w, frames, dev = cluttered
+    (ob, od, ow), touched = cluttered_oracle
+    say("case: cluttered room 640x480 / 4 cm, all 300 frames one per launch (default launch shape), "
+        "whole map and every touched set against the sparse oracle")
     gm = gpu_map(w.params, block_capacity=1 << 16)
-    for d, T in zip(dev, w.poses):
+    for k, (d, T) in enumerate(zip(dev, w.poses)):
         gm.integrate_depth(d, w.camera.K, T)
+        gt = gm.query_touched().cpu().numpy()
+        assert len(gt) == len(touched[k]) and {tuple(x) for x in gt} == touched[k], f"touched set differs at frame {k}"
     torch.cuda.synchronize()
-    say(check_map(gm, np.random.default_rng(20), dense_frames(w.params, frames, w.camera.K, w.poses)))
+    say(compare_whole(gm, ob, od, ow))
 
 
-def test_cluttered_room_300_frames_16_per_launch():
-    w, frames, dev = cluttered()
+def test_cluttered_room_300_frames_16_per_launch(cluttered, cluttered_oracle):
+    w, frames, dev = cluttered
+    (ob, od, ow), touched = cluttered_oracle
     B = 16
     first = len(dev) % B or B
-    say("case: cluttered room 640x480 / 4 cm, 300 frames 16 per launch (compacted launches), sampled blocks")
+    say("case: cluttered room 640x480 / 4 cm, 300 frames 16 per launch (compacted launches), "
+        "whole map and every launch's touched set against the sparse oracle")
     gm = gpu_map(w.params, block_capacity=1 << 16)
     K = w.camera.K
-    gm.integrate_depth_views(dev[:first], [K] * first, w.poses[:first])
-    for a in range(first, len(dev), B):
-        gm.integrate_depth_views(dev[a:a + B], [K] * B, w.poses[a:a + B])
+    for a, b in [(0, first)] + [(a, a + B) for a in range(first, len(dev), B)]:
+        gm.integrate_depth_views(dev[a:b], [K] * (b - a), w.poses[a:b])
+        want = set().union(*touched[a:b])
+        gt = gm.query_touched().cpu().numpy()
+        assert len(gt) == len(want) and {tuple(x) for x in gt} == want, f"touched set differs at launch {a}"
     torch.cuda.synchronize()
-    say(check_map(gm, np.random.default_rng(21), dense_frames(w.params, frames, K, w.poses)))
+    say(compare_whole(gm, ob, od, ow))
+
+
+def compare_whole(gm, ob, od, ow):
+    """Every allocated block and every voxel of the GPU map against the
+    oracle's sorted state: block sets and weights identical, distances
+    bit-identical."""
+    gb, gd, gw = gm.sorted_state()
+    assert gm.status() == 0
+    assert gb.shape == ob.shape and np.array_equal(gb, ob), f"{len(gb)} GPU blocks vs {len(ob)} oracle blocks"
+    assert np.array_equal(gw.astype(np.float64), ow), "weights differ"
+    assert np.array_equal(gd.astype(np.float64), od), "distances differ"
+    return {"blocks": len(gb), "updated_voxels": int((gw > 0).sum()), "bit_identical": True}
 
 
 def test_box_room_1cm_300_frames():
+    import os
+    import oracle
     w = synth.box_room_sequence(0.01, n_frames=300)
     frames = w.frames(device="cuda")
-    say("case: box room 640x480 / 1 cm, 300 frames (footprint culling and compacted launches), sampled blocks")
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    say(f"case: box room 640x480 / 1 cm, 300 frames (footprint culling and compacted launches), whole map "
+        f"and every touched set against the sparse oracle ({threads} threads)")
     gm = gpu_map(w.params, block_capacity=1 << 17)
-    for f, T in zip(frames, w.poses):
+    om = oracle.OracleMap.from_params(w.params)
+    for k, (f, T) in enumerate(zip(frames, w.poses)):
         gm.integrate_depth(torch.as_tensor(f, device="cuda"), w.camera.K, T)
+        om.integrate_threads(f, w.camera.K, T, threads)
+        gt = gm.query_touched().cpu().numpy()
+        ot = om.touched()
+        assert len(gt) == len(ot), f"touched count differs at frame {k}"
+        assert np.array_equal(np.unique(gt, axis=0), np.unique(ot, axis=0)), f"touched set differs at frame {k}"
     torch.cuda.synchronize()
-    say(check_map(gm, np.random.default_rng(22), dense_frames(w.params, frames, w.camera.K, w.poses)))
+    ob, od, ow = om.sorted_state()
+    del om
+    say(compare_whole(gm, ob, od, ow))
 
 
 def test_rig_500_steps_graph():

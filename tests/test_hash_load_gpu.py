@@ -1,0 +1,213 @@
+"""The block hash under load (§IV-A), and growing a map with reserve().
+
+Every other test builds the hash at twice the pool and fills it to a few per
+cent, where a key is nearly always decided in its first 64-slot probe window.
+Here the hash is exactly as large as the pool and filled to ~90 %, so probes
+run through several windows and past the end of the table (linear probing
+wraps), and tables smaller than one window (32 slots: the 64 lanes cover
+every slot twice) are exercised.  Filling past capacity must leave the sticky
+TSDF_EFULL with the hash-full bit set; reserve() must grow a map so that it
+ends bit-identical to the oracle and to a map created large, and must bring a
+map that overflowed back into service."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2311_00626_amd import synth
+from tests.gpu_util import assert_parity, gpu_map, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_00626_amd.tsdf  # noqa: F401
+
+
+@pytest.fixture(scope="module")
+def cluttered():
+    w = synth.cluttered_room_sequence(300)
+    frames = w.frames(device="cuda", count=200)
+    return w, frames
+
+
+def oracle_prefix(params, frames, K, poses, limit):
+    """Oracle block counts after each frame, up to the first frame past `limit`."""
+    import oracle
+    om = oracle.OracleMap.from_params(params)
+    counts = []
+    for d, T in zip(frames, poses):
+        om.integrate(d, K, T)
+        counts.append(om.num_blocks())
+        if counts[-1] > limit:
+            break
+    return counts
+
+
+def run_checked(params, frames, K, poses, **kw):
+    """GPU and oracle over the frames, touched sets compared after every frame."""
+    import oracle
+    gm = gpu_map(params, **kw)
+    om = oracle.OracleMap.from_params(params)
+    for k, (d, T) in enumerate(zip(frames, poses)):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), K, T)
+        om.integrate(d, K, T)
+        gt = gm.query_touched().cpu().numpy()
+        assert {tuple(x) for x in gt} == {tuple(x) for x in om.touched()}, f"touched set differs at frame {k}"
+        assert len(gt) == len(om.touched())
+    torch.cuda.synchronize()
+    return gm, om
+
+
+def test_full_table_parity_2048(cluttered):
+    """hash capacity == block capacity == 2048, ~90 % full."""
+    w, frames = cluttered
+    cap = 2048
+    counts = oracle_prefix(w.params, frames, w.camera.K, w.poses, int(0.92 * cap))
+    n = len(counts) - 1 if counts[-1] > int(0.92 * cap) else len(counts)
+    assert counts[n - 1] >= int(0.85 * cap), counts[-3:]
+    say(f"case: cluttered room 640x480 / 4 cm, {n} frames, hash = pool = {cap}, "
+        f"{counts[n - 1]} blocks ({counts[n - 1] / cap:.0%} full)")
+    gm, om = run_checked(w.params, frames[:n], w.camera.K, w.poses[:n], block_capacity=cap, hash_capacity=cap)
+    st = gm.full_stats()
+    assert st["hash_capacity"] == cap and st["block_capacity"] == cap and st["error_bits"] == 0
+    assert st["blocks"] == counts[n - 1] and gm.status() == 0
+    say(assert_parity(gm, om, exact_dist=True))
+
+
+@pytest.mark.parametrize("hash_cap", [32, 64])
+def test_tiny_table_parity(hash_cap):
+    """29 blocks in a 32-slot table (each slot covered by two lanes of the
+    probe window) and in a 64-slot one (one window is the whole table)."""
+    p = synth.MapParams(0.125, 4.0, "constant", max_range=5.0)
+    ws = [synth.box_room_single(s) for s in (1, 2)]
+    frames = [w.frames()[0] for w in ws]
+    say(f"case: box room 160x120 at 12.5 cm, cameras of seeds 1-2, hash {hash_cap} slots, pool 32 blocks")
+    import oracle
+    gm = gpu_map(p, block_capacity=32, hash_capacity=hash_cap)
+    om = oracle.OracleMap.from_params(p)
+    for w, d in zip(ws, frames):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), w.camera.K, w.poses[0])
+        om.integrate(d, w.camera.K, w.poses[0])
+        assert {tuple(x) for x in gm.query_touched().cpu().numpy()} == {tuple(x) for x in om.touched()}
+    assert om.num_blocks() == 29
+    assert gm.status() == 0 and gm.full_stats()["error_bits"] == 0
+    say(assert_parity(gm, om, exact_dist=True))
+
+
+def test_overflow_is_sticky_with_hash_full_bit(cluttered):
+    """hash == pool == 256 while the first frame alone allocates ~1000
+    blocks: the table fills, later new blocks find no free slot."""
+    from paper_2311_00626_amd.tsdf import EFULL, ERR_HASH_FULL, ESTATE, TsdfError
+    w, frames = cluttered
+    say("case: cluttered room, hash = pool = 256, two frames (overflow)")
+    gm = gpu_map(w.params, block_capacity=256, hash_capacity=256)
+    for d, T in zip(frames[:2], w.poses[:2]):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), w.camera.K, T)
+    assert gm.status() == EFULL
+    st = gm.full_stats()
+    say({"error_bits": st["error_bits"], "blocks": st["blocks"]})
+    assert st["error_bits"] & ERR_HASH_FULL
+    assert st["blocks"] == 256
+    with pytest.raises(TsdfError) as ex:
+        gm.integrate_depth(torch.as_tensor(frames[2], device="cuda"), w.camera.K, w.poses[2])
+    assert ex.value.status == ESTATE
+    # every block the full map holds is one the oracle allocates
+    import oracle
+    om = oracle.OracleMap.from_params(w.params)
+    for d, T in zip(frames[:2], w.poses[:2]):
+        om.integrate(d, w.camera.K, T)
+    assert {tuple(b) for b in gm.query_blocks().cpu().numpy()} <= {tuple(b) for b in om.blocks()}
+
+    # recovery: reserve clears the error; the map takes frames again and only
+    # ever holds blocks the oracle holds
+    early = {tuple(b) for b in om.blocks()}
+    gm.reserve(4096)
+    assert gm.status() == 0
+    st = gm.full_stats()
+    assert st["error_bits"] == 0 and st["block_capacity"] == 4096 and st["hash_capacity"] == 8192
+    for d, T in zip(frames[2:6], w.poses[2:6]):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), w.camera.K, T)
+        om.integrate(d, w.camera.K, T)
+    assert gm.status() == 0
+    g = {tuple(b) for b in gm.query_blocks().cpu().numpy()}
+    o = {tuple(b) for b in om.blocks()}
+    assert g <= o and len(g) > 256
+    # blocks the oracle first allocates after the overflowing frames missed no
+    # update on the GPU either: they are exact
+    gb, gd, gw = gm.sorted_state()
+    ob, od, ow = om.sorted_state()
+    oi = {tuple(b): k for k, b in enumerate(ob)}
+    late = [k for k, b in enumerate(gb) if tuple(b) not in early]
+    assert len(late) > 0
+    for k in late:
+        j = oi[tuple(gb[k])]
+        assert np.array_equal(gw[k].astype(np.float64), ow[j]) and np.array_equal(gd[k].astype(np.float64), od[j])
+    assert {tuple(b) for b in ob if tuple(b) not in early} == {tuple(gb[k]) for k in late}
+
+
+def test_reserve_keeps_map_bit_identical(cluttered):
+    """N frames into a pool they just fit, reserve (the hash grows too),
+    more frames: the map equals the oracle's and a map created large, and
+    the touched sets match after every frame, the first after reserve too."""
+    w, frames = cluttered
+    n1, n2 = 8, 40
+    counts = oracle_prefix(w.params, frames[:n2], w.camera.K, w.poses[:n2], 1 << 30)
+    cap = counts[n1 - 1] + 4           # full after n1 frames, too small for n2
+    assert counts[-1] > cap
+    say(f"case: cluttered room, {n1} frames into a {cap}-block pool, reserve(4800), {n2 - n1} more frames")
+    import oracle
+    gm = gpu_map(w.params, block_capacity=cap)
+    big = gpu_map(w.params, block_capacity=1 << 14)
+    om = oracle.OracleMap.from_params(w.params)
+    for k, (d, T) in enumerate(zip(frames[:n2], w.poses[:n2])):
+        if k == n1:
+            before = gm.full_stats()
+            touched_before = {tuple(x) for x in gm.query_touched().cpu().numpy()}
+            gm.reserve(4800)
+            after = gm.full_stats()
+            assert after["block_capacity"] == 4800 and after["hash_capacity"] == 16384
+            assert before["hash_capacity"] == 1 << (2 * cap - 1).bit_length()
+            assert after["blocks"] == before["blocks"] == counts[n1 - 1]
+            assert {tuple(x) for x in gm.query_touched().cpu().numpy()} == touched_before
+            gm.reserve(100)            # not larger: nothing changes
+            assert gm.full_stats()["block_capacity"] == 4800
+        dt = torch.as_tensor(d, device="cuda")
+        gm.integrate_depth(dt, w.camera.K, T)
+        big.integrate_depth(dt, w.camera.K, T)
+        om.integrate(d, w.camera.K, T)
+        assert {tuple(x) for x in gm.query_touched().cpu().numpy()} == {tuple(x) for x in om.touched()}
+    torch.cuda.synchronize()
+    assert gm.full_stats()["blocks"] == counts[-1] > cap
+    say(assert_parity(gm, om, exact_dist=True))
+    b1, d1, w1 = gm.sorted_state()
+    b2, d2, w2 = big.sorted_state()
+    assert np.array_equal(b1, b2) and np.array_equal(d1, d2) and np.array_equal(w1, w2)
+
+
+def test_reserve_with_graph_step(cluttered):
+    """A graph step captured before reserve holds the old buffers; after
+    reserve its next run captures again and the map stays exact."""
+    w, frames = cluttered
+    B = 4
+    counts = oracle_prefix(w.params, frames[:24], w.camera.K, w.poses[:24], 1 << 30)
+    cap = counts[11] + 2               # room for the first 12 frames only
+    assert counts[-1] > cap
+    say(f"case: cluttered room, graph steps of 4 frames into a {cap}-block pool, reserve between steps")
+    import oracle
+    gm = gpu_map(w.params, block_capacity=cap)
+    step = gm.step()
+    om = oracle.OracleMap.from_params(w.params)
+    dev = [torch.as_tensor(f, device="cuda") for f in frames[:24]]
+    for a in range(0, 24, B):
+        if a == 12:
+            gm.reserve(8192)
+        step.run(dev[a:a + B], [w.camera.K] * B, w.poses[a:a + B])
+        for d, T in zip(frames[a:a + B], w.poses[a:a + B]):
+            om.integrate(d, w.camera.K, T)
+    torch.cuda.synchronize()
+    step.close()
+    assert gm.status() == 0
+    say(assert_parity(gm, om, exact_dist=True))

@@ -129,13 +129,45 @@ def test_loss_and_gradient_match_oracle(width, height, idx):
                                   torch.as_tensor(target.astype(np.float32), device="cuda"), grad)
     g = grad.cpu().numpy().astype(np.float64)
     rel = np.linalg.norm(g - grad_o) / np.linalg.norm(grad_o)
-    say({"loss_gpu": loss_g, "loss_oracle": loss_o, "used": [used_g, used_o], "grad_rel_err": rel})
-    assert abs(used_g - used_o) <= max(2, used_o // 500)
-    assert abs(loss_g - loss_o) <= 2e-3 * loss_o
-    assert rel < 2e-2
-    # every parameter block receives gradient
-    for a, b in ((0, 864), (864, 896), (896, 1920), (1920, 1952), (1952, 2016), (2016, 2018)):
-        assert np.abs(g[a:b]).max() > 0
+    blocks = check_gradient_blocks(g, grad_o)
+    say({"loss_gpu": loss_g, "loss_oracle": loss_o, "used": [used_g, used_o], "grad_rel_err": rel,
+         "blocks": blocks})
+    # the voxels reached and the loss: the GPU projects and fuses in binary32,
+    # the oracle in binary64, so a voxel on a pixel or band boundary may go
+    # the other way (none did in the recorded runs)
+    assert abs(used_g - used_o) <= 2
+    assert abs(loss_g - loss_o) <= 1e-5 * loss_o
+
+
+# Parameter blocks of the perceptron (offsets into the 2018 parameters).
+GRAD_BLOCKS = {"W1": (0, 864), "b1": (864, 896), "W2": (896, 1920), "b2": (1920, 1952), "W3": (1952, 2016),
+               "b3": (2016, 2018)}
+# Tolerances of the binary32 gradient kernels against the binary64 oracle.
+# Every parameter gradient is a sum over 10^3 - 10^4 pixels of products of
+# bfloat16 values accumulated in binary32 (order set by atomics and matrix
+# cores): rounding contributes a relative error of order sqrt(n) 2^-24,
+# ~1e-5 in the worst block, and the recorded runs stay near 2e-6.  The bounds
+# below sit above that and far below what a wrong term moves: a sign error, a
+# transposed operand or a dropped term (a ReLU mask, a bias, the clamp's
+# truncation path) changes its block by a sizeable fraction of its norm.
+GRAD_BLOCK_RTOL = 1e-4         # |g_b - o_b| / |o_b| per block
+GRAD_ELEM_RTOL = 1e-3          # per element, relative to the element
+GRAD_ELEM_ATOL = 1e-4          # per element, relative to the block's largest magnitude
+
+
+def check_gradient_blocks(g, o):
+    """Per parameter block: relative L2 error and an element-wise bound."""
+    out = {}
+    for name, (a, b) in GRAD_BLOCKS.items():
+        gb, ob = g[a:b], o[a:b]
+        scale = np.abs(ob).max()
+        assert scale > 0, f"{name} receives no gradient"
+        rel = float(np.linalg.norm(gb - ob) / np.linalg.norm(ob))
+        worst = float((np.abs(gb - ob) / (GRAD_ELEM_RTOL * np.abs(ob) + GRAD_ELEM_ATOL * scale)).max())
+        out[name] = {"rel": rel, "elem_bound_used": worst}
+        assert rel < GRAD_BLOCK_RTOL, f"{name}: relative error {rel:.3g}"
+        assert worst <= 1.0, f"{name}: an element is off by {worst:.3g}x its bound"
+    return out
 
 
 def test_training_beats_linear_dropoff_on_held_out_rooms():
