@@ -223,7 +223,11 @@ TSDF_API int tsdf_step_destroy(tsdf_step *step);
  * as int32 triples to out_xyz_dev (room for `capacity` blocks; min(count,
  * capacity) are written) and the total count to *out_count (host).
  * Synchronises hip_stream.  (§IV-A: the set of allocated blocks.)  The sort's
- * work buffers belong to the map and are allocated on the first call. */
+ * work buffers belong to the map and are allocated on the first call.  A map
+ * in a sticky error state can still be read (TSDF_OK; map_status reports the
+ * state): it holds every block it could allocate.  Errors: TSDF_EINVAL (NULL
+ * map or count, capacity < 0, NULL buffer with capacity > 0), TSDF_ENOMEM
+ * (the work buffers), TSDF_EDEVICE. */
 TSDF_API int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
                  void *hip_stream);
 
@@ -243,7 +247,7 @@ TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_
 /* Blocks with at least one voxel updated by the most recent integrate_depth
  * or integrate_depth_views call (the "updated blocks" that downstream layers consume, §IV-C), in
  * unspecified order, as int32 triples; same capacity / count contract as
- * query_blocks.  Synchronises hip_stream. */
+ * query_blocks (a map in a sticky error state included).  Synchronises hip_stream. */
 TSDF_API int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count,
                   void *hip_stream);
 

@@ -1232,7 +1232,7 @@ int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lon
     const long long n = std::min<long long>(cs.c[kNumBlocks], m->dm.block_cap);
     *out_count = 0;
     if (n == 0)
-        return m->sticky;
+        return TSDF_OK;
     // work buffers sized for the whole pool, kept for later calls
     hipError_t e = hipSuccess;
     if (!m->q_sorted)
@@ -1272,7 +1272,7 @@ int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lon
     if (e != hipSuccess)
         return hip_status(e);
     *out_count = (long long)valid;
-    return m->sticky;
+    return TSDF_OK;   // a map in a sticky error state is still readable
 }
 
 int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks, float *out_dist_dev,
@@ -1320,7 +1320,7 @@ int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lo
         if (e != hipSuccess)
             return hip_status(e);
     }
-    return m->sticky;
+    return TSDF_OK;
 }
 
 int map_stats(tsdf_map *m, tsdf_stats *out, void *hip_stream)

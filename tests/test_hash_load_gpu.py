@@ -62,11 +62,15 @@ def run_checked(params, frames, K, poses, **kw):
 
 
 def test_full_table_parity_2048(cluttered):
-    """hash capacity == block capacity == 2048, ~90 % full."""
+    """hash capacity == block capacity == 2048, 85-97 % full."""
     w, frames = cluttered
     cap = 2048
-    counts = oracle_prefix(w.params, frames, w.camera.K, w.poses, int(0.92 * cap))
-    n = len(counts) - 1 if counts[-1] > int(0.92 * cap) else len(counts)
+    # the map grows by a few hundred blocks a frame on this sequence (84 % of
+    # 2048 after one frame, 95 % after the next): stop at the last frame that
+    # still fits in 97 %
+    limit = int(0.97 * cap)
+    counts = oracle_prefix(w.params, frames, w.camera.K, w.poses, limit)
+    n = len(counts) - 1 if counts[-1] > limit else len(counts)
     assert counts[n - 1] >= int(0.85 * cap), counts[-3:]
     say(f"case: cluttered room 640x480 / 4 cm, {n} frames, hash = pool = {cap}, "
         f"{counts[n - 1]} blocks ({counts[n - 1] / cap:.0%} full)")
