@@ -58,6 +58,7 @@ extern "C" {
 #define TSDF_EFULL (-3)    /* block pool, hash table or touched list overflowed (sticky) */
 #define TSDF_EDEVICE (-4)  /* a HIP runtime call failed */
 #define TSDF_ESTATE (-5)   /* the map is in a sticky error state */
+#define TSDF_ESCRATCH (-6) /* integrate_depth_noalloc: the call needs more than its fixed scratch */
 
 #define TSDF_WEIGHT_CONSTANT 0        /* f_w(d_p) = 1 */
 #define TSDF_WEIGHT_LINEAR_DROPOFF 1  /* 1 for d_p >= -voxel_size, then linear to 0 at -epsilon */
@@ -147,6 +148,32 @@ TSDF_API int reserve(tsdf_map *m, long long block_capacity);
  * Errors: TSDF_EINVAL, TSDF_ESTATE, TSDF_EDEVICE. */
 TSDF_API int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height,
                     const float K[4], const float T_world_cam[16], void *hip_stream);
+
+/* integrate_depth for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, semantics and result as integrate_depth (the map afterwards
+ * is bit-identical), and the map is still created by create_map_ex; but the
+ * scratch integrate_depth allocates in the map on first use (the frame's
+ * depth footprint pyramid and the candidate-block list of a compacted launch)
+ * comes from one fixed device array of the library instead, about 9.3 MiB
+ * per GPU (a pyramid of one image up to 4096 pixels a side, then 2^20
+ * candidate entries), held on each GPU the function is used on until the
+ * process ends.  The call makes no device allocation and no free.  Its first
+ * call on a GPU looks the array's address up (hipGetSymbolAddress) with the
+ * map's device current.
+ * Limits: a frame whose candidate list could exceed 2^20 blocks (its block
+ * lattice, the world box of the frustum out to max range + epsilon, holds
+ * more than 2^20 blocks and the launch is compacted) is rejected with
+ * TSDF_ESCRATCH before any work is enqueued.  Maps with learned weighting or
+ * ray-walk allocation need per-map buffers and are rejected with
+ * TSDF_EINVAL.  Kernel timing (tsdf_profile) does not record these calls.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams, maps or threads, not ordered on one stream) race on it
+ * and give wrong maps; order them.  Nothing in the array needs clearing
+ * between calls (each call rewrites what it reads).
+ * Errors: those of integrate_depth, and TSDF_ESCRATCH. */
+TSDF_API int integrate_depth_noalloc(tsdf_map *m, const float *depth_dev, int width, int height,
+                                     const float K[4], const float T_world_cam[16], void *hip_stream);
 
 /* A rotating LiDAR's range image (§III: Omega is the beam angles; Eq. (3)).
  * Row-major float32[height][width] of Euclidean ranges in metres; sensor frame

@@ -409,10 +409,10 @@ hipError_t ensure_tiles(tsdf_map *m)
 
 // Points the view at pyramid slot `slot` (nothing for images beyond the
 // pyramid's largest side).
-void attach_tiles(const tsdf_map *m, CameraView &cv, int slot)
+void attach_tiles(float *tiles, CameraView &cv, int slot)
 {
     cv.tiles = nullptr;
-    if (!m->tiles || cv.width > kTileMaxSide || cv.height > kTileMaxSide)
+    if (!tiles || cv.width > kTileMaxSide || cv.height > kTileMaxSide)
         return;
     int off = 0;
     for (int l = 0; l < kTileLevels; ++l) {
@@ -422,18 +422,30 @@ void attach_tiles(const tsdf_map *m, CameraView &cv, int slot)
         cv.tile_off[l] = off;
         off += cv.tile_cols[l] * cv.tile_rows[l];
     }
-    cv.tiles = m->tiles + (size_t)slot * (size_t)kTileFloatsPerView;
+    cv.tiles = tiles + (size_t)slot * (size_t)kTileFloatsPerView;
 }
 
 // Builds the pyramid of a single-view launch when the policy asks for it.
-hipError_t prepare_footprint(tsdf_map *m, FrameArgs &fa, hipStream_t s)
+// Scratch buffers a call uses instead of the map's own (the no-allocation
+// entry point): a footprint pyramid slot and a candidate list.
+struct CallScratch {
+    float *tiles;
+    uint2 *cand;
+    long long cand_cap;
+};
+
+hipError_t prepare_footprint(tsdf_map *m, FrameArgs &fa, hipStream_t s, const CallScratch *sc)
 {
     if (!use_footprint(m, fa.lat))
         return hipSuccess;
-    hipError_t e = ensure_tiles(m);
-    if (e != hipSuccess)
-        return e;
-    attach_tiles(m, fa.cam, 0);
+    if (sc) {
+        attach_tiles(sc->tiles, fa.cam, 0);
+    } else {
+        hipError_t e = ensure_tiles(m);
+        if (e != hipSuccess)
+            return e;
+        attach_tiles(m->tiles, fa.cam, 0);
+    }
     ViewsArgs va;
     std::memset(&va, 0, sizeof(va));
     va.cam[0] = fa.cam;
@@ -449,7 +461,7 @@ hipError_t prepare_footprint(tsdf_map *m, ViewsArgs &va, hipStream_t s, bool lau
     if (e != hipSuccess)
         return e;
     for (int v = 0; v < va.n_views; ++v)
-        attach_tiles(m, va.cam[v], v);
+        attach_tiles(m->tiles, va.cam[v], v);
     return launch ? launch_footprint_tiles(va, s) : hipSuccess;
 }
 
@@ -521,11 +533,17 @@ bool use_compaction(const tsdf_map *m, const Lattice &lat, int n_views)
 }
 
 // Points the lattice at a candidate list large enough for every block of it.
-hipError_t prepare_compaction(tsdf_map *m, Lattice &lat, int n_views)
+hipError_t prepare_compaction(tsdf_map *m, Lattice &lat, int n_views, const CallScratch *sc = nullptr)
 {
     lat.cand = nullptr;
     if (!use_compaction(m, lat, n_views))
         return hipSuccess;
+    if (sc) {
+        if (lat.n_lat > sc->cand_cap)
+            return hipErrorOutOfMemory;   // the caller checked the size first
+        lat.cand = sc->cand;
+        return hipSuccess;
+    }
     if (!m->cand || m->cand_cap < lat.n_lat) {
         if (m->cand) {
             hipError_t e = hipDeviceSynchronize();   // earlier launches may still read the old list
@@ -731,12 +749,20 @@ int destroy_map(tsdf_map *m)
     return TSDF_OK;
 }
 
-int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
-                    const float T_world_cam[16], void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// integrate_depth with the map's own scratch buffers (sc == nullptr, which
+// allocates them on first use) or with the fixed scratch `sc`.
+int integrate_depth_call(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
+                         const float T_world_cam[16], void *hip_stream, const CallScratch *sc)
 {
     if (!m || !view_args_valid(depth_dev, width, height, K, T_world_cam))
         return TSDF_EINVAL;
     if (m->p.weighting == TSDF_WEIGHT_LEARNED && !m->sm_params)
+        return TSDF_EINVAL;
+    if (sc && (m->p.weighting == TSDF_WEIGHT_LEARNED || m->p.allocation == TSDF_ALLOC_RAY_WALK))
         return TSDF_EINVAL;
     if (m->sticky)
         return TSDF_ESTATE;
@@ -749,19 +775,23 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     if (st != TSDF_OK)
         return st;
     map_consts(m, box_extent(lo, hi), (double)fa.cam.zfar, fa.mc);
+    if (sc && use_compaction(m, fa.lat, 1) && fa.lat.n_lat > sc->cand_cap)
+        return TSDF_ESCRATCH;
     fa.parity = (int)(m->frames & 1);
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
-    const bool timed = e == hipSuccess && timing_begin(m, s);   // every kernel of the call, pre-passes included
+    // every kernel of the call, pre-passes included (not with the fixed
+    // scratch: the first timed call creates events)
+    const bool timed = e == hipSuccess && !sc && timing_begin(m, s);
     const bool walk = m->p.allocation == TSDF_ALLOC_RAY_WALK;
     if (e == hipSuccess && !walk)
-        e = prepare_footprint(m, fa, s);
+        e = prepare_footprint(m, fa, s, sc);
     if (e == hipSuccess)
         e = prepare_learned(m, &fa.cam, 1, s);
     if (e == hipSuccess)
         e = prepare_walk(m, fa, T_world_cam, s);
     if (e == hipSuccess)
-        e = prepare_compaction(m, fa.lat, 1);
+        e = prepare_compaction(m, fa.lat, 1, sc);
     if (e != hipSuccess)
         return hip_status(e);
     int groups = schedule(m, fa.lat);
@@ -783,6 +813,34 @@ int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, 
     timing_end(m, s, timed);
     ++m->frames;
     return TSDF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int integrate_depth(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
+                    const float T_world_cam[16], void *hip_stream)
+{
+    return integrate_depth_call(m, depth_dev, width, height, K, T_world_cam, hip_stream, nullptr);
+}
+
+int integrate_depth_noalloc(tsdf_map *m, const float *depth_dev, int width, int height, const float K[4],
+                            const float T_world_cam[16], void *hip_stream)
+{
+    if (!m || !view_args_valid(depth_dev, width, height, K, T_world_cam))
+        return TSDF_EINVAL;
+    hipError_t e = use_device(m);
+    void *ptr = nullptr;
+    if (e == hipSuccess)
+        e = noalloc_scratch(&ptr);
+    if (e != hipSuccess)
+        return hip_status(e);
+    CallScratch sc;
+    sc.tiles = reinterpret_cast<float *>(ptr);
+    sc.cand = reinterpret_cast<uint2 *>(reinterpret_cast<unsigned char *>(ptr) + kNoAllocTileBytes);
+    sc.cand_cap = kNoAllocMaxCandidates;
+    return integrate_depth_call(m, depth_dev, width, height, K, T_world_cam, hip_stream, &sc);
 }
 
 int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model *lidar,
@@ -813,7 +871,7 @@ int integrate_range(tsdf_map *m, const float *range_dev, const tsdf_lidar_model 
     hipError_t e = use_device(m);
     const bool timed = e == hipSuccess && timing_begin(m, s);   // every kernel of the call, pre-passes included
     if (e == hipSuccess)
-        e = prepare_footprint(m, fa, s);
+        e = prepare_footprint(m, fa, s, nullptr);
     if (e == hipSuccess)
         e = prepare_learned(m, &fa.cam, 1, s);
     if (e == hipSuccess)
@@ -1378,6 +1436,7 @@ const char *tsdf_strerror(int status)
     case TSDF_EFULL: return "map capacity exceeded (block pool, hash table or touched list)";
     case TSDF_EDEVICE: return "HIP runtime error";
     case TSDF_ESTATE: return "map is in a sticky error state";
+    case TSDF_ESCRATCH: return "call needs more than the fixed scratch of the no-allocation entry point";
     default: return "unknown status";
     }
 }

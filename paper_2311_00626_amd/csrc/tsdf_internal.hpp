@@ -264,4 +264,13 @@ hipError_t launch_count_valid(const unsigned long long *keys, long long n, unsig
 hipError_t launch_rehash(const unsigned long long *slot_keys, uint32_t n, unsigned long long *keys, uint32_t *vals,
                          uint32_t mask, hipStream_t stream);
 
+// Fixed scratch of the no-allocation entry point (noalloc.hip): one view's
+// footprint pyramid, then a candidate list of kNoAllocMaxCandidates entries.
+constexpr size_t kNoAllocTileBytes = sizeof(float) * (size_t)kTileFloatsPerView;   // a multiple of 256
+constexpr long long kNoAllocMaxCandidates = 1ll << 20;
+constexpr size_t kNoAllocScratchBytes = kNoAllocTileBytes + 8u * (size_t)kNoAllocMaxCandidates;
+static_assert(kNoAllocTileBytes % 256 == 0, "candidate list alignment");
+// Device address of the scratch on the current device (looked up once per device).
+hipError_t noalloc_scratch(void **out);
+
 }  // namespace tsdf

@@ -17,7 +17,7 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libtsdf.so")
 
-OK, EINVAL, ENOMEM, EFULL, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EFULL, EDEVICE, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 WEIGHTINGS = {"constant": 0, "linear_dropoff": 1, "learned": 2}
 SM_NPARAM = 2018
 SM_MAX_FRAMES = 16
@@ -96,6 +96,7 @@ def _load() -> C.CDLL:
     lib.destroy_map.argtypes = [vp]
     lib.reserve.argtypes = [vp, ll]
     lib.integrate_depth.argtypes = [vp, vp, i, i, vp, vp, vp]
+    lib.integrate_depth_noalloc.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
     lib.query_touched.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
@@ -117,7 +118,8 @@ def _load() -> C.CDLL:
     lib.tsdf_sm_trainer_destroy.argtypes = [vp]
     lib.tsdf_sm_loss_grad.argtypes = [vp, vp, i, vp, vp, vp, C.c_float, C.c_float, ll, vp, vp, vp, vp, vp]
     lib.tsdf_sm_adam.argtypes = [vp, vp, vp, vp, vp, i, C.c_float, C.c_float, C.c_float, C.c_float, i, vp]
-    for name in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth", "integrate_depth_views",
+    for name in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth",
+                 "integrate_depth_noalloc", "integrate_depth_views",
                  "integrate_range",
                  "query_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
@@ -131,6 +133,7 @@ def _load() -> C.CDLL:
 lib = _load()
 
 EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth",
+            "integrate_depth_noalloc",
             "integrate_depth_views", "integrate_range",
             "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
             "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config",
@@ -290,6 +293,20 @@ class TsdfMap:
         st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
                                  _stream_ptr(stream, depth.get_device()))
         _check(st, "integrate_depth")
+
+    def integrate_depth_noalloc(self, depth: torch.Tensor, K: Sequence[float], T_world_cam,
+                                stream: Optional[torch.cuda.Stream] = None) -> None:
+        """integrate_depth with the library's fixed device scratch: the call
+        allocates no device memory (see tsdf.h for its limits)."""
+        if not (depth.is_cuda and depth.dtype == torch.float32 and depth.dim() == 2
+                and depth.is_contiguous()):
+            raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
+        Kh = _host_f32(K, 4)
+        Th = _host_f32(T_world_cam, 16)
+        H, W = depth.shape
+        st = lib.integrate_depth_noalloc(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
+                                         _stream_ptr(stream, depth.get_device()))
+        _check(st, "integrate_depth_noalloc")
 
     def integrate_range(self, rng: torch.Tensor, lidar, T_world_sensor,
                         stream: Optional[torch.cuda.Stream] = None) -> None:

@@ -51,7 +51,7 @@ def test_params_struct_layout(t):
 
 
 def test_strerror(t):
-    for s in (0, -1, -2, -3, -4, -5, -99):
+    for s in (0, -1, -2, -3, -4, -5, -6, -99):
         assert isinstance(t.strerror(s), str) and t.strerror(s)
     assert t.strerror(-3).startswith("map capacity")
 
