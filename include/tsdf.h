@@ -323,6 +323,16 @@ TSDF_API const char *tsdf_strerror(int status);
  *               (no voxel of it can be updated).  TSDF_FOOTPRINT_AUTO uses it
  *               for launches whose block lattice has at least 16384 blocks;
  *               views larger than 4096 pixels a side are never culled this way.
+ *   staging     LDS staging of block depth footprints (integrate_depth with a
+ *               pinhole view and constant or linear-dropoff weighting): a
+ *               wave copies the pixel rectangle under its block's projected
+ *               corners (widened by one pixel) into LDS with row loads when
+ *               it holds at most 1024 pixels, and its voxels read their
+ *               pixels there instead of gathering them from the image (§IV-B:
+ *               each voxel samples its projection's nearest pixel; the values
+ *               read are the same).  TSDF_STAGE_AUTO reads the image
+ *               directly (faster on every workload measured); staging runs
+ *               only with TSDF_STAGE_ALWAYS.
  * NULL restores the automatic choice.  Errors: TSDF_EINVAL. */
 #define TSDF_FOOTPRINT_AUTO 0
 #define TSDF_FOOTPRINT_NEVER 1
@@ -330,12 +340,16 @@ TSDF_API const char *tsdf_strerror(int status);
 #define TSDF_COMPACT_AUTO 0
 #define TSDF_COMPACT_NEVER 1
 #define TSDF_COMPACT_ALWAYS 2
+#define TSDF_STAGE_AUTO 0
+#define TSDF_STAGE_NEVER 1
+#define TSDF_STAGE_ALWAYS 2
 typedef struct {
     int max_groups, partitions, chunk, footprint;
     int compaction;   /* TSDF_COMPACT_*: a cull pre-pass compacts the surviving blocks into a list
                          that the integration kernel deals out evenly to its waves (automatic once
                          lattice blocks x views reach 16384; one band only, not with ray-walk
                          allocation) */
+    int staging;      /* TSDF_STAGE_* */
 } tsdf_launch_config;
 TSDF_API int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *config);
 

@@ -532,6 +532,16 @@ bool use_compaction(const tsdf_map *m, const Lattice &lat, int n_views)
     return lat.n_lat * n_views >= kCompactAutoWork;
 }
 
+// LDS staging of block footprints for a single pinhole view, on request
+// only: measured against direct gathers it lost on every workload tried
+// (640x480 frames at 1, 2 and 4 cm: the copy adds a load -> LDS write -> LDS
+// read step to a latency-bound chain and reads more pixels than the voxels
+// sample), so the automatic choice is direct reads.
+bool use_staging(const tsdf_map *m, const CameraView &)
+{
+    return m->p.weighting != TSDF_WEIGHT_LEARNED && m->launch.staging == TSDF_STAGE_ALWAYS;
+}
+
 // Points the lattice at a candidate list large enough for every block of it.
 hipError_t prepare_compaction(tsdf_map *m, Lattice &lat, int n_views, const CallScratch *sc = nullptr)
 {
@@ -778,6 +788,7 @@ int integrate_depth_call(tsdf_map *m, const float *depth_dev, int width, int hei
     if (sc && use_compaction(m, fa.lat, 1) && fa.lat.n_lat > sc->cand_cap)
         return TSDF_ESCRATCH;
     fa.parity = (int)(m->frames & 1);
+    fa.stage = use_staging(m, fa.cam) ? 1 : 0;
     hipStream_t s = (hipStream_t)hip_stream;
     hipError_t e = use_device(m);
     // every kernel of the call, pre-passes included (not with the fixed
@@ -1445,7 +1456,7 @@ int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *lc)
 {
     if (!m)
         return TSDF_EINVAL;
-    tsdf_launch_config c = {0, 0, 0, 0, 0};
+    tsdf_launch_config c = {0, 0, 0, 0, 0, 0};
     if (lc)
         c = *lc;
     if (c.max_groups < 0 || c.max_groups > 65536 || c.chunk < 0 || c.chunk > kMaxChunk ||
@@ -1453,7 +1464,8 @@ int tsdf_set_launch_config(tsdf_map *m, const tsdf_launch_config *lc)
          c.footprint != TSDF_FOOTPRINT_ALWAYS) ||
         (c.compaction != TSDF_COMPACT_AUTO && c.compaction != TSDF_COMPACT_NEVER &&
          c.compaction != TSDF_COMPACT_ALWAYS) ||
-        (c.partitions != 0 && c.partitions != 1 && c.partitions != kPartitions))
+        (c.partitions != 0 && c.partitions != 1 && c.partitions != kPartitions) ||
+        (c.staging != TSDF_STAGE_AUTO && c.staging != TSDF_STAGE_NEVER && c.staging != TSDF_STAGE_ALWAYS))
         return TSDF_EINVAL;
     m->launch = c;
     return TSDF_OK;

@@ -666,6 +666,170 @@ __device__ __forceinline__ uint32_t measure_pinhole(const CameraView &cv, const 
     return hit;
 }
 
+// LDS staging of a block's depth footprint.  The voxel centres of a block in
+// front of the camera project inside the rectangle of its 8 projected corners
+// (the projection of a box is the hull of its corners' projections); widened
+// by one pixel and clipped to the image, that rectangle is copied into the
+// wave's LDS region with row-contiguous loads when it holds at most
+// kStagePixels pixels, and each voxel then reads its nearest pixel there.  A
+// voxel whose pixel lies outside the rectangle (only through rounding at its
+// edge) reads the image directly, so every voxel sees exactly the value a
+// direct read gives.
+constexpr int kStagePixels = 1024;   // 4 KiB of LDS per wave
+
+struct StageRect {
+    int u0, v0, w, h;   // w * h == 0: not staged
+};
+
+// Footprint rectangle of block (bx, by, bz) (wave-uniform): lane c computes
+// corner c & 7 and the extremes are reduced over each group of 8 lanes.
+__device__ __forceinline__ StageRect stage_rect(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
+{
+    const int c = lane_id() & 7;
+    const float e = 8.0f * mc.vs;
+    const float px = (float)(8 * bx) * mc.vs + ((c & 1) ? e : 0.0f);
+    const float py = (float)(8 * by) * mc.vs + ((c & 2) ? e : 0.0f);
+    const float pz = (float)(8 * bz) * mc.vs + ((c & 4) ? e : 0.0f);
+    const float x = cv.R[0] * px + cv.R[1] * py + cv.R[2] * pz + cv.t[0];
+    const float y = cv.R[3] * px + cv.R[4] * py + cv.R[5] * pz + cv.t[1];
+    float z = cv.R[6] * px + cv.R[7] * py + cv.R[8] * pz + cv.t[2];
+    float u = cv.fx * (x / z) + cv.cx;
+    float v = cv.fy * (y / z) + cv.cy;
+    float umax = u, vmax = v;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        z = fminf(z, __shfl_xor(z, m));
+        u = fminf(u, __shfl_xor(u, m));
+        v = fminf(v, __shfl_xor(v, m));
+        umax = fmaxf(umax, __shfl_xor(umax, m));
+        vmax = fmaxf(vmax, __shfl_xor(vmax, m));
+    }
+    StageRect r{0, 0, 0, 0};
+    auto uniform = [](float f) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, f)));
+    };
+    if (!(uniform(z) > 1e-3f))
+        return r;
+    const float lo_u = fmaxf(floorf(uniform(u)) - 1.0f, 0.0f);
+    const float lo_v = fmaxf(floorf(uniform(v)) - 1.0f, 0.0f);
+    const float hi_u = fminf(floorf(uniform(umax)) + 1.0f, cv.width_f - 1.0f);
+    const float hi_v = fminf(floorf(uniform(vmax)) + 1.0f, cv.height_f - 1.0f);
+    // NaN or an empty rectangle fails these tests
+    if (!(hi_u >= lo_u && hi_v >= lo_v))
+        return r;
+    const float area = (hi_u - lo_u + 1.0f) * (hi_v - lo_v + 1.0f);
+    if (!(area <= (float)kStagePixels))
+        return r;
+    r.u0 = (int)lo_u;
+    r.v0 = (int)lo_v;
+    r.w = (int)(hi_u - lo_u) + 1;
+    r.h = (int)(hi_v - lo_v) + 1;
+    return r;
+}
+
+// Copies the rectangle into `region` (row-major, r.w floats a row): a pass
+// of the wave loads 64 / w rows at once when a row fits the wave (lane ->
+// (row, column) by one division per block), one row-chunk at a time
+// otherwise.  All of a pass's loads are issued before its LDS writes.
+__device__ __forceinline__ void stage_copy(const CameraView &cv, const StageRect &r, float *region)
+{
+    const int lane = lane_id();
+    const __amdgpu_buffer_rsrc_t depth = make_rsrc(cv.depth, 4u * (uint32_t)cv.width * (uint32_t)cv.height);
+    if (r.w <= 64) {
+        const int rows = 64 / r.w;                 // rows per pass
+        const int q = lane / r.w, col = lane - q * r.w;
+        const bool active = q < rows;
+        for (int base = 0; base < r.h; base += 4 * rows) {
+            float val[4];
+            int at[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int row = base + t * rows + q;
+                const bool ok = active && row < r.h;
+                at[t] = ok ? row * r.w + col : -1;
+                const uint32_t off = ok ? 4u * ((uint32_t)(r.v0 + row) * (uint32_t)cv.width + (uint32_t)(r.u0 + col))
+                                        : kOutOfRange;
+                val[t] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(depth, off, 0, 0));
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (at[t] >= 0)
+                    region[at[t]] = val[t];
+        }
+    } else {
+        for (int row = 0; row < r.h; ++row)
+            for (int col = lane; col < r.w; col += 64)
+                region[row * r.w + col] = __builtin_bit_cast(
+                    float, __builtin_amdgcn_raw_buffer_load_b32(
+                               depth, 4u * ((uint32_t)(r.v0 + row) * (uint32_t)cv.width + (uint32_t)(r.u0 + col)), 0,
+                               0));
+    }
+    // the wave's own writes are read back by other lanes of the same wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// measure_pinhole (constant or linear-dropoff weighting) with the depth
+// footprint staged in `region` when the block's rectangle is small enough.
+template <int WEIGHTING>
+__device__ __forceinline__ uint32_t measure_pinhole_staged(const CameraView &cv, const MapConsts &mc, int bx, int by,
+                                                           float px, float py, int bz, float xs[8], float ws[8],
+                                                           float *region)
+{
+    const StageRect r = stage_rect(cv, mc, bx, by, bz);
+    if (r.w * r.h == 0)
+        return measure_pinhole<WEIGHTING>(cv, mc, px, py, bz, xs, ws);
+    // the previous block's reads of the region are complete before it is rewritten
+    __builtin_amdgcn_wave_barrier();
+    stage_copy(cv, r, region);
+    const uint32_t width = (uint32_t)cv.width;
+    const __amdgpu_buffer_rsrc_t depth = make_rsrc(cv.depth, 4u * width * (uint32_t)cv.height);
+    const float ax = cv.R[0] * px + cv.R[1] * py;
+    const float ay = cv.R[3] * px + cv.R[4] * py;
+    const float az = cv.R[6] * px + cv.R[7] * py;
+    float zc[8], d[8];
+    uint32_t pix_off[8];
+    uint32_t outside = 0;   // bit s: voxel s projects into the image but outside the rectangle
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const float pz = ((float)(8 * bz + s) + 0.5f) * mc.vs;
+        const float xc = (ax + cv.R[2] * pz) + cv.t[0];
+        const float yc = (ay + cv.R[5] * pz) + cv.t[1];
+        zc[s] = (az + cv.R[8] * pz) + cv.t[2];
+        const float rz = 1.0f / zc[s];
+        const float u = cv.fx * (xc * rz) + cv.cx;
+        const float v = cv.fy * (yc * rz) + cv.cy;
+        const bool ok = zc[s] > 0.0f && u >= 0.0f && u < cv.width_f && v >= 0.0f && v < cv.height_f;
+        const uint32_t i = (uint32_t)(ok ? u : 0.0f);
+        const uint32_t j = (uint32_t)(ok ? v : 0.0f);
+        const uint32_t li = i - (uint32_t)r.u0, lj = j - (uint32_t)r.v0;
+        const bool in_rect = li < (uint32_t)r.w && lj < (uint32_t)r.h;
+        pix_off[s] = ok && !in_rect ? 4u * (j * width + i) : kOutOfRange;
+        outside |= (ok && !in_rect ? 1u : 0u) << s;
+        d[s] = ok && in_rect ? region[lj * (uint32_t)r.w + li] : 0.0f;
+    }
+    if (__ballot(outside != 0) != 0ull) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+            if ((outside >> s) & 1u)
+                d[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(depth, pix_off[s], 0, 0));
+    }
+    uint32_t hit = 0;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const float dp = d[s] - zc[s];
+        float wm = 1.0f;
+        if (WEIGHTING == 1 && dp < -mc.delta)
+            wm = (mc.eps + dp) * mc.span_inv;
+        const bool upd = d[s] > 0.0f && d[s] <= cv.d_max && dp >= -mc.eps && wm > 0.0f;
+        xs[s] = dp < mc.eps ? dp : mc.eps;
+        ws[s] = wm;
+        hit |= (upd ? 1u : 0u) << s;
+    }
+    return hit;
+}
+
 // Eq. (3) and the TSDF measurement (§IV-B) of the lane's 8 voxels against a
 // spherical range image: azimuth theta = atan2(y, x), polar angle phi =
 // atan2(sqrt(x^2 + y^2), z) (the angle acos(z / r)), pixel coordinates

@@ -32,10 +32,14 @@ namespace {
 using namespace dev;
 
 // LIST: the candidates come from the cull kernel's list (compacted launch)
-// instead of this kernel's own walk of the lattice.
-template <int WEIGHTING, int STORAGE, int SPHERICAL, bool LIST>
+// instead of this kernel's own walk of the lattice.  STAGE: a pinhole view's
+// depth footprint is staged in LDS per block (measure_pinhole_staged).
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool LIST, bool STAGE>
 __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const FrameArgs &fa)
 {
+    static_assert(!STAGE || (SPHERICAL == 0 && WEIGHTING != kWeightLearned), "staging: pinhole, fixed weighting");
+    __shared__ float s_stage[STAGE ? kWavesPerGroup * kStagePixels : 1];
+    float *const region = s_stage + (STAGE ? (threadIdx.x >> 6) * kStagePixels : 0);
     const int lane = lane_id();
     const int lx = lane & 7;
     const int ly = lane >> 3;
@@ -59,7 +63,11 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
         const float px = ((float)(8 * bx + lx) + 0.5f) * fa.mc.vs;
         const float py = ((float)(8 * by + ly) + 0.5f) * fa.mc.vs;
         float xs[8], ws[8];
-        const uint32_t hit = measure_view<WEIGHTING, SPHERICAL>(fa.cam, fa.mc, px, py, bz, xs, ws);
+        uint32_t hit;
+        if constexpr (STAGE)
+            hit = measure_pinhole_staged<WEIGHTING>(fa.cam, fa.mc, bx, by, px, py, bz, xs, ws, region);
+        else
+            hit = measure_view<WEIGHTING, SPHERICAL>(fa.cam, fa.mc, px, py, bz, xs, ws);
         // ray-walk allocation keeps every visited block, updated or not
         if (!fa.cam.dda_marks && __ballot(hit != 0) == 0ull)
             return;
@@ -107,17 +115,17 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
 // The binary16 form, with its conversions, runs slower under that cap, and
 // already under a four-wave one (its code changes at 102 VGPRs), so it keeps
 // the compiler's own choice (two waves: the minimum a 512-thread group needs).
-template <int WEIGHTING, int STORAGE, int SPHERICAL>
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool STAGE = false>
 __global__ __launch_bounds__(64 * kWavesPerGroup, STORAGE == 0 ? 5 : 2) void integrate_depth_kernel(DeviceMap dm,
                                                                                                    FrameArgs fa)
 {
-    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, false>(dm, fa);
+    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, false, STAGE>(dm, fa);
 }
 
-template <int WEIGHTING, int STORAGE, int SPHERICAL>
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool STAGE = false>
 __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kernel(DeviceMap dm, FrameArgs fa)
 {
-    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, true>(dm, fa);
+    integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, true, STAGE>(dm, fa);
 }
 
 __global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
@@ -135,9 +143,32 @@ hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream
     return hipGetLastError();
 }
 
+template <int WEIGHTING>
+static void launch_depth_staged(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
+{
+    if (fa.lat.cand) {
+        if (dm.storage == 1)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 1, 0, true>), grid, block, 0,
+                               stream, dm, fa);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 0, 0, true>), grid, block, 0,
+                               stream, dm, fa);
+    } else if (dm.storage == 1) {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 1, 0, true>), grid, block, 0, stream,
+                           dm, fa);
+    } else {
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 0, 0, true>), grid, block, 0, stream,
+                           dm, fa);
+    }
+}
+
 template <int WEIGHTING, int SPHERICAL>
 static void launch_depth_storage(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
 {
+    if (SPHERICAL == 0 && WEIGHTING != kWeightLearned && fa.stage) {
+        launch_depth_staged<WEIGHTING == kWeightLearned ? kWeightConstant : WEIGHTING>(dm, fa, grid, block, stream);
+        return;
+    }
     if (fa.lat.cand) {
         if (dm.storage == 1)
             hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0,

@@ -161,6 +161,7 @@ struct FrameArgs {
     MapConsts mc;
     Lattice lat;
     int parity;             // launch counter & 1: selects this launch's touched counters
+    int stage;              // nonzero: stage block depth footprints in LDS (pinhole, fixed weighting)
 };
 
 // Arguments of a multi-view launch: views are fused per voxel in array order.

@@ -68,11 +68,12 @@ def lidar_struct(lidar) -> tsdf_lidar_model:
 MAX_VIEWS = 16
 FOOTPRINT = {"auto": 0, "never": 1, "always": 2}
 COMPACTION = {"auto": 0, "never": 1, "always": 2}
+STAGING = {"auto": 0, "never": 1, "always": 2}
 
 
 class tsdf_launch_config(C.Structure):
     _fields_ = [("max_groups", C.c_int), ("partitions", C.c_int), ("chunk", C.c_int), ("footprint", C.c_int),
-                ("compaction", C.c_int)]
+                ("compaction", C.c_int), ("staging", C.c_int)]
 
 
 class tsdf_params(C.Structure):
@@ -396,10 +397,12 @@ class TsdfMap:
         return b.cpu().numpy(), d.cpu().numpy(), w.cpu().numpy()
 
     def set_launch_config(self, max_groups: int = 0, partitions: int = 0, chunk: int = 0,
-                          footprint: str = "auto", compaction: str = "auto") -> None:
+                          footprint: str = "auto", compaction: str = "auto", staging: str = "auto") -> None:
         """Launch shape of the integration kernels (0 = automatic); footprint
-        culling and compacted launches "auto", "never" or "always"."""
-        c = tsdf_launch_config(max_groups, partitions, chunk, FOOTPRINT[footprint], COMPACTION[compaction])
+        culling, compacted launches and LDS footprint staging "auto", "never"
+        or "always"."""
+        c = tsdf_launch_config(max_groups, partitions, chunk, FOOTPRINT[footprint], COMPACTION[compaction],
+                               STAGING[staging])
         _check(lib.tsdf_set_launch_config(self._h, C.byref(c)), "tsdf_set_launch_config")
 
     # -- kernel timing -------------------------------------------------------

@@ -110,7 +110,7 @@ int main(void)
     EXPECT(tsdf_step_create(NULL, 0, NULL), TSDF_EINVAL);
     EXPECT(tsdf_step_run(NULL, views, 1, NULL), TSDF_EINVAL);
     EXPECT(tsdf_step_destroy(NULL), TSDF_OK);
-    tsdf_launch_config lc = {0, 0, 0, 0, 0};
+    tsdf_launch_config lc = {0, 0, 0, 0, 0, 0};
     EXPECT(tsdf_set_launch_config(NULL, &lc), TSDF_EINVAL);
     EXPECT(tsdf_profile(NULL, 1), TSDF_EINVAL);
     double ms = 0;

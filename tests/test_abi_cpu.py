@@ -39,7 +39,7 @@ def test_struct_layouts(t):
     assert C.sizeof(t.tsdf_depth_view) == 112
     assert C.sizeof(t.tsdf_lidar_model) == 32
     assert C.sizeof(t.tsdf_stats) == 72
-    assert C.sizeof(t.tsdf_launch_config) == 20
+    assert C.sizeof(t.tsdf_launch_config) == 24
 
 
 def test_params_struct_layout(t):
