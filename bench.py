@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STAGING = "auto"   # LDS footprint staging of the one-frame-per-launch legs (--staging)
+PARTITIONS = 0     # image bands of the one-frame-per-launch legs (--partitions; 0 = automatic)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "integrate_depth_cluttered_room_pmc.json")
 KERNEL_SOURCES = ["paper_2311_00626_amd/csrc/integrate.hip", "paper_2311_00626_amd/csrc/device_common.hpp",
                   "paper_2311_00626_amd/csrc/tsdf_internal.hpp"]
@@ -55,9 +57,9 @@ def algorithmic_bytes(voxel_rw: int, touched: int, new_blocks: int, pixels: int,
     return 2 * voxel_bytes * voxel_rw + 4 * pixels * frames + 16 * touched + 20 * new_blocks
 
 
-def measured_traffic(launches_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel source; else None."""
+def _pmc_summary():
+    """The committed rocprofv3 PMC summary, if it was taken on the current
+    kernel source; else None."""
     try:
         with open(PMC_SUMMARY) as f:
             s = json.load(f)
@@ -65,7 +67,24 @@ def measured_traffic(launches_bytes: float):
         return None
     if s.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return s.get("hbm_bytes_per_launch")
+    return s
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the PMC summary."""
+    s = _pmc_summary()
+    return None if s is None else s.get("hbm_bytes_per_launch")
+
+
+def measured_traffic_record():
+    """The frames the PMC figure averages over, and the algorithmic bytes of
+    those same frames, so that their ratio is read off one frame set."""
+    s = _pmc_summary()
+    if s is None:
+        return None
+    keys = ("frames", "algorithmic_bytes_per_launch", "traffic_over_algorithmic", "fetch_scale", "write_scale",
+            "calibration")
+    return {k: s[k] for k in keys if k in s}
 
 
 def host_cpu() -> dict:
@@ -142,6 +161,33 @@ def cpu_baseline(w, frames_host, budget_s: float) -> dict:
                                                 f"binary64 oracle, {f64['seconds']:.1f} s"}}
 
 
+def calibration_kernels(mib: int, dev) -> list:
+    """Kernels of known traffic for scaling the FETCH_SIZE / WRITE_SIZE
+    counters, launched in this order after the buffers are filled: a plain
+    copy of `mib` MiB (contiguous 16-byte accesses), and two gathers of one
+    4-byte word per 128-byte and per 64-byte line (the access pattern of the
+    integration kernel's depth and hash reads) over buffers far larger than
+    the L2 caches, each line touched once.  Returns (kind, bytes read,
+    bytes written) per kernel, in launch order."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.zeros_like(src)
+    g128 = torch.ones(n // 4, dtype=torch.float32, device=dev)        # n bytes, n / 128 lines
+    g64 = torch.ones(n // 8, dtype=torch.float32, device=dev)         # n / 2 bytes, n / 128 lines
+    o128 = torch.zeros(n // 128, dtype=torch.float32, device=dev)
+    o64 = torch.zeros(n // 128, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    o128.copy_(g128.view(-1, 32)[:, 0])
+    o64.copy_(g64.view(-1, 16)[:, 0])
+    torch.cuda.synchronize()
+    plan = [("copy", n, n), ("gather_4B_per_128B_line", n // 128 * 128, n // 32),
+            ("gather_4B_per_64B_line", n // 128 * 64, n // 32)]
+    log("calibration kernels (kind, algorithmic bytes read, written), in launch order: " + json.dumps(plan))
+    return plan
+
+
 def counters(m):
     st = m.full_stats()
     return st["blocks"], st["voxel_updates"], st["voxel_writes"], st["touched_blocks"]
@@ -159,7 +205,7 @@ def region_events():
 
 
 def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int,
-                setup=None, **map_kw) -> dict:
+                setup=None, per_frame: bool = False, **map_kw) -> dict:
     """One integrate_depth launch per frame over `steps` frames (cycling the
     sequence) after `warmup` untimed ones.  One HIP event pair on the launch
     stream brackets the timed region; the mean launch duration is its time over
@@ -171,7 +217,9 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     n_frames = frames.shape[0]
     H, W = frames.shape[1], frames.shape[2]
     K = w.camera.K
+    log(f"leg: {w.name} {storage} {map_kw or ''} one frame per launch, {steps} timed after {warmup}")
     m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity, **map_kw)
+    m.set_launch_config(partitions=PARTITIONS, staging=STAGING)
     if setup is not None:
         setup(m)
     for k in range(warmup):
@@ -191,11 +239,55 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     kernel_ms, launches = ev[0].elapsed_time(ev[1]), steps
     b1, u1, _, t1_ = counters(m)
     assert m.status() == 0, "map overflowed"
-    alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, steps, 4 if storage == "fp16" else 8) / steps
+    vb = 4 if storage == "fp16" else 8
+    alg = algorithmic_bytes(u1 - u0, t1_ - t0_, b1 - b0, H * W, steps, vb) / steps
     kern = kernel_ms / 1e3 / max(launches, 1)
-    return {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
-            "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9,
-            "blocks": b1, "candidates": candidates(m) - c0}
+    out = {"elapsed": t_end - t_start, "updates": u1 - u0, "touched": t1_ - t0_, "new_blocks": b1 - b0,
+           "alg_per_launch": alg, "kernel_s": kern, "launches": launches, "achieved": alg / kern / 1e9,
+           "blocks": b1, "candidates": candidates(m) - c0,
+           "block_granular_per_launch": block_granular_bytes(t1_ - t0_, vb) / steps,
+           "frames_timed": f"{warmup}-{warmup + steps - 1}" if steps <= n_frames - warmup
+                           else f"{warmup}.. ({steps} frames, the sequence cycled)"}
+    del m
+    if per_frame:
+        out["per_frame"] = per_frame_times(w, frames, poses, storage, steps, warmup, block_capacity, setup, **map_kw)
+    return out
+
+
+def block_granular_bytes(touched: int, voxel_bytes: int) -> int:
+    """Whole touched blocks read and written once (512 voxels each way)."""
+    return 2 * 512 * voxel_bytes * touched
+
+
+def per_frame_times(w, frames, poses, storage: str, steps: int, warmup: int, block_capacity: int,
+                    setup=None, **map_kw) -> dict:
+    """Median and 90th percentile of one integrate_depth call's GPU time over
+    the timed frames, from a second pass over the same frames into a fresh
+    map with the library's per-call events (they cost a few microseconds a
+    call, so the timed region above uses one event pair instead)."""
+    import torch
+    from paper_2311_00626_amd.tsdf import TsdfMap
+    n_frames = frames.shape[0]
+    K = w.camera.K
+    m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity, **map_kw)
+    m.set_launch_config(partitions=PARTITIONS, staging=STAGING)
+    if setup is not None:
+        setup(m)
+    for k in range(warmup):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+    torch.cuda.synchronize()
+    m.profile(True)
+    ms = []
+    for k in range(warmup, warmup + steps):
+        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        t, n = m.profile_read()
+        assert n == 1
+        ms.append(t)
+    m.profile(False)
+    a = np.asarray(ms)
+    return {"median_ms": float(np.median(a)), "p90_ms": float(np.percentile(a, 90)),
+            "min_ms": float(a.min()), "max_ms": float(a.max()), "frames": len(ms),
+            "note": "GPU time of one call (all of its kernels), library events per call"}
 
 
 def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
@@ -210,7 +302,7 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
     poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
     out = {"workload": w.name, "voxel_size_m": voxel_size}
     for storage in ("fp32", "fp16"):
-        r = timed_plain(w, frames, poses, storage, min(steps, 290), warmup, 1 << 17)
+        r = timed_plain(w, frames, poses, storage, min(steps, 290), warmup, 1 << 17, per_frame=True)
         out[storage] = {"value": r["updates"] / r["elapsed"], "unit": "voxel updates/s",
                         "frames_per_s": min(steps, 290) / r["elapsed"],
                         "updates_per_frame": r["updates"] / min(steps, 290),
@@ -221,7 +313,10 @@ def precision_leg(voxel_size: float, steps: int, warmup: int) -> dict:
                                      "kernel": f"integrate_depth<{storage}> per frame (footprint and cull "
                                                "pre-passes included on lattices large enough to use them)",
                                      "kernel_ms_mean": r["kernel_s"] * 1e3,
-                                     "algorithmic_bytes_per_launch": r["alg_per_launch"]}}
+                                     "algorithmic_bytes_per_launch": r["alg_per_launch"],
+                                     "block_granular_bytes_per_launch": r["block_granular_per_launch"],
+                                     "frames_timed": r["frames_timed"]},
+                        "per_frame": r["per_frame"]}
     out["fp32_16_per_launch"] = timed_views(w, frames, poses, 16, 1 << 18)
     del frames
     torch.cuda.empty_cache()
@@ -238,6 +333,7 @@ def timed_views(w, frames, poses, B: int, block_capacity: int) -> dict:
     K = w.camera.K
     n = frames.shape[0]
     H, W = frames.shape[1], frames.shape[2]
+    log(f"leg: {w.name} {B} frames per launch")
     m = TsdfMap.from_params(w.params, block_capacity=block_capacity)
     first = n % B or B
     m.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
@@ -275,7 +371,7 @@ def walk_leg(w, frames, poses, steps: int, warmup: int) -> dict:
             "note": "kernel_ms_mean is GPU time per frame: the per-pixel walk and the integration kernel"}
 
 
-def learned_leg(w, frames, poses, steps: int, warmup: int) -> dict:
+def learned_leg(w, frames, poses, steps: int, warmup: int, full_gain: bool = True) -> dict:
     """Learned sensor-model weighting on the same frames (untrained model: the
     cost does not depend on the parameter values), and the training step time
     on one 640x480 room at 2 cm."""
@@ -301,6 +397,17 @@ def learned_leg(w, frames, poses, steps: int, warmup: int) -> dict:
     targets = sum(int(wd.target.numel()) for wd in room.windows) / len(room.windows)
     out["training"] = {"window_frames": 8, "target_voxels_per_window": targets, "steps": n,
                        "ms_per_step": dt / n * 1e3, "workload": "learning room 1000, 640x480, 2 cm"}
+    if full_gain:
+        log("leg: learned sensor model, full training configuration and held-out gain")
+        g = sm.gain_run()
+        out["gain_full_configuration"] = {
+            "workload": "20 training rooms (seeds 1000-1019) x 100 corrupted 640x480 frames, 2 cm, windows of 8, "
+                        "2400 Adam steps; held-out rooms 2000-2002 of 100 frames",
+            "data_s": g["data_s"], "train_s": g["train_s"], "train_ms_per_step": g["train_s"] / g["steps"] * 1e3,
+            "held_out_loss_before": g["held_out_loss_before"], "held_out_loss_after": g["held_out_loss_after"],
+            "surface_error": g["surface_error"],
+            "rms_gain_vs_linear_dropoff": {k: 1.0 - e["learned"]["rms_m"] / e["fallback"]["rms_m"]
+                                           for k, e in g["surface_error"].items()}}
     return out
 
 
@@ -398,7 +505,24 @@ def main():
                     help="steps of the multi-sensor rig leg (4 cameras + LiDAR, graph-replayed; 0 = skip it)")
     ap.add_argument("--legs", default="plain,fp16,batched,rig,precision,walk,learned",
                     help="comma-separated legs to run (plain is always run)")
+    ap.add_argument("--skip-learned-gain", action="store_true",
+                    help="learned leg: time inference and training only, without the full training run")
+    ap.add_argument("--precision-voxels", default="0.01,0.02",
+                    help="voxel sizes (m) of the box-room precision leg")
+    ap.add_argument("--calibrate-only", action="store_true",
+                    help="run only the PMC calibration kernels (--copy-calibration-mib, default 256) and exit")
+    ap.add_argument("--partitions", type=int, default=0, choices=(0, 1, 8),
+                    help="image bands (one per XCD) of the one-frame-per-launch legs; 0 = automatic")
+    ap.add_argument("--staging", default="auto", choices=("auto", "never", "always"),
+                    help="LDS footprint staging of the one-frame-per-launch legs")
     args = ap.parse_args()
+    global STAGING, PARTITIONS
+    STAGING = args.staging
+    PARTITIONS = args.partitions
+    if args.calibrate_only:
+        import torch
+        calibration_kernels(args.copy_calibration_mib or 256, torch.device("cuda:0"))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the path shards by space with no exchange; see the design notes).", file=sys.stderr)
@@ -420,7 +544,8 @@ def main():
     poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
 
     def plain_leg(storage: str):
-        return timed_plain(w, frames, poses, storage, args.steps, args.warmup, 1 << 16)
+        return timed_plain(w, frames, poses, storage, args.steps, args.warmup, 1 << 16,
+                           per_frame=storage == "fp32")
 
     # ---- plain path, binary32 storage: the headline value ------------------
     p32 = plain_leg("fp32")
@@ -479,18 +604,16 @@ def main():
         del mb
 
     rig = rig_leg(args.rig_steps, args.warmup) if args.rig_steps > 0 and "rig" in legs else None
-    precision = ([precision_leg(vs, args.steps, args.warmup) for vs in (0.01, 0.02)]
+    precision = ([precision_leg(float(vs), args.steps, args.warmup) for vs in args.precision_voxels.split(",")]
                  if "precision" in legs else None)
     walk = walk_leg(w, frames, poses, args.steps, args.warmup) if "walk" in legs else None
     if walk is not None:
         walk["blocks_allocated_exact_touch"] = p32["blocks"]
-    learned = learned_leg(w, frames, poses, args.steps, args.warmup) if "learned" in legs else None
+    learned = (learned_leg(w, frames, poses, args.steps, args.warmup, full_gain=not args.skip_learned_gain)
+               if "learned" in legs else None)
 
     if args.copy_calibration_mib > 0:
-        src = torch.empty(args.copy_calibration_mib << 20, dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+        calibration_kernels(args.copy_calibration_mib, dev)
 
     result = {
         "metric": "voxel updates/s (frames/s and achieved HBM GB/s alongside)",
@@ -516,10 +639,16 @@ def main():
         "new_blocks": new_blocks,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(alg_per_launch),
+                     "traffic": measured_traffic(),
                      "kernel": "integrate_depth_kernel", "kernel_ms_mean": mean_kernel_s * 1e3,
-                     "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches},
+                     "algorithmic_bytes_per_launch": alg_per_launch, "launches_timed": launches,
+                     "frames_timed": p32["frames_timed"],
+                     "block_granular_bytes_per_launch": p32["block_granular_per_launch"]},
+        "per_frame": p32["per_frame"],
     }
+    traffic = measured_traffic_record()
+    if traffic is not None:
+        result["roofline"]["traffic_profile"] = traffic
     if fp16 is not None:
         result["fp16"] = fp16
     if rig is not None:

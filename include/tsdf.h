@@ -411,7 +411,12 @@ TSDF_API int tsdf_sensor_maps(const float *depth_dev, int width, int height, con
  * before any weight cap).  tsdf_sm_loss_grad writes dL/dparams to grad_dev
  * (TSDF_SM_NPARAM floats, overwritten) and, when loss_host is not NULL, waits
  * for the stream and stores {L, N} there.  The band test d_p >= -eps carries no
- * gradient; rounding to bfloat16 is differentiated as the identity.  A
+ * gradient; rounding to bfloat16 is differentiated as the identity.  The
+ * loss and the gradient evaluate the perceptron on the matrix cores
+ * (bfloat16 operands, binary32 sums in the matrix core's order), one function
+ * for both, so the gradient is that of the loss computed; it differs from
+ * the inference of integration and tsdf_sensor_maps (sequential binary32
+ * sums) only in the rounding of the sums.  A
  * trainer holds the per-pixel work buffers of windows of up to max_frames
  * (<= TSDF_SM_MAX_FRAMES) images of one size; calls on one trainer must be
  * ordered on one stream. */

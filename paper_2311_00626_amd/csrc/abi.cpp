@@ -1637,7 +1637,7 @@ int tsdf_sm_loss_grad(tsdf_sm_trainer *t, const float *params_dev, int n_frames,
     for (int f = 0; f < n_frames && e == hipSuccess; ++f) {
         SmView v{depth_dev[f], t->width, t->height, K[0], K[1], K[2], K[3], max_range};
         float2 *maps = t->maps + (size_t)f * (size_t)wh;
-        e = launch_sm_maps(v, voxel_size, params_dev, maps, s);
+        e = launch_sm_maps_mfma(v, voxel_size, params_dev, maps, s);   // the function the backward recomputes
         SmFrame &fr = la.frames[f];
         pose_inverse(T_world_cam + 16 * f, fr.R, fr.t);
         fr.depth = depth_dev[f];

@@ -10,10 +10,17 @@
 // Outputs o: weight w = (o0 + sqrt(o0^2 + 4)) / 2 and truncation
 // eps = vs (1 + 7 s) with s = (1 + o1 / sqrt(1 + o1^2)) / 2.
 //
-// Inference (sm_maps_kernel) rounds inputs and hidden activations to
-// bfloat16 and accumulates every dot product in binary32, one fused
-// multiply-add per term in index order from the bias; with parameters that
-// are bfloat16 values this reproduces the CPU reference bit for bit.
+// Inference for integration (sm_maps_kernel) rounds inputs and hidden
+// activations to bfloat16 and accumulates every dot product in binary32, one
+// fused multiply-add per term in index order from the bias; with parameters
+// that are bfloat16 values this reproduces the CPU reference bit for bit.
+//
+// Training runs the same perceptron on the matrix cores
+// (v_mfma_f32_16x16x32_bf16: bfloat16 inputs, weights and activations,
+// binary32 accumulation in the matrix core's own order): the loss's maps
+// (sm_maps_mfma_kernel) and the backward's recomputation of the forward pass
+// are one function, so the gradient is exactly that of the loss evaluated.
+// It differs from the inference function only in the rounding of the sums.
 //
 // Training computes the gradient of
 //   L = (1/N) sum_v (D(v) - D*(v))^2,  D(v) = sum_f w_f x_f / sum_f w_f,
@@ -61,13 +68,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t sm_image(const SmView &v)
     return make_rsrc(v.depth, 4u * (uint32_t)v.width * (uint32_t)v.height);
 }
 
-// pi/2 unless all 4 neighbours are valid (a pixel on the image border has a
-// neighbour outside, which reads as invalid)
-__device__ float sm_incidence(const SmView &v, __amdgpu_buffer_rsrc_t img, int i, int j, float d)
+// pi/2 unless all 4 neighbours (left, right, up, down) are valid (a pixel on
+// the image border has a neighbour outside, which reads as invalid)
+__device__ float sm_incidence_of(const SmView &v, int i, int j, float d, float dl, float dr, float du, float dd)
 {
     const float half_pi = 1.57079637f;
-    const float dl = sm_load(img, sm_off(v, i - 1, j)), dr = sm_load(img, sm_off(v, i + 1, j));
-    const float du = sm_load(img, sm_off(v, i, j - 1)), dd = sm_load(img, sm_off(v, i, j + 1));
     if (!(sm_valid(dl, v.d_max) && sm_valid(dr, v.d_max) && sm_valid(du, v.d_max) && sm_valid(dd, v.d_max)))
         return half_pi;
     const float rxl = (((float)(i - 1) + 0.5f) - v.cx) / v.fx, rxc = (((float)i + 0.5f) - v.cx) / v.fx;
@@ -82,6 +87,13 @@ __device__ float sm_incidence(const SmView &v, __amdgpu_buffer_rsrc_t img, int i
     const float cx = ny * pz - nz * py, cy = nz * px - nx * pz, cz = nx * py - ny * px;
     const float cr = sqrtf((cx * cx + cy * cy) + cz * cz);
     return atan2_as(cr, fabsf(dot));
+}
+
+__device__ float sm_incidence(const SmView &v, __amdgpu_buffer_rsrc_t img, int i, int j, float d)
+{
+    const float dl = sm_load(img, sm_off(v, i - 1, j)), dr = sm_load(img, sm_off(v, i + 1, j));
+    const float du = sm_load(img, sm_off(v, i, j - 1)), dd = sm_load(img, sm_off(v, i, j + 1));
+    return sm_incidence_of(v, i, j, d, dl, dr, du, dd);
 }
 
 // The 27 inputs, already rounded to bfloat16.
@@ -117,8 +129,8 @@ __device__ __forceinline__ ConstParams as_constant(const float *p)
     return (ConstParams)p;
 }
 
-// Forward through the hidden layers with parameters P; h1, h2 are the
-// bfloat16 activations, o the binary32 outputs.
+// Forward through the hidden layers with parameters P (binary32 multiply-adds
+// in index order); h1, h2 are the bfloat16 activations, o the binary32 outputs.
 template <typename Params>
 __device__ __forceinline__ void sm_forward(Params P, const float x[kSmIn], float h1[kSmHidden],
                                            float h2[kSmHidden], float o[kSmOut])
@@ -149,6 +161,152 @@ __device__ __forceinline__ void sm_forward(Params P, const float x[kSmIn], float
     }
 }
 
+// ---- forward pass on the matrix cores ----------------------------------
+//
+// v_mfma_f32_16x16x32_bf16 computes D = A B + C for A 16 x 32 and B 32 x 16
+// (bfloat16) and C, D 16 x 16 (binary32).  Lane l (g = l / 16, m = l mod 16)
+// supplies A[m][8 g + j] and B[8 g + j][m] (j = 0..7) and holds D[4 g + i][m]
+// (i = 0..3).  The layers are evaluated transposed, units along M and pixels
+// along N: a 16-pixel sub-tile is one column block, H^T = W X^T + b.  A
+// layer's output then sits where the next layer's B operand needs it: lane
+// (g, m) holds units 4 g + i of each half of the previous layer for pixel m,
+// so the next layer's K slots 8 g + j of lane group g are taken to be the
+// units {4 g .. 4 g + 3, 16 + 4 g .. 16 + 4 g + 3}, and the weights are
+// loaded in that order (a dot product's terms may come in any order).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Hidden unit behind K slot 8 g + j of layers 2 and 3.
+__device__ __forceinline__ int sm_slot_unit(int g, int j)
+{
+    return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+}
+
+// The perceptron's parameters as this lane's operands (once per wave).  The
+// weights are bfloat16 values (the parameter format), so the conversions
+// are exact; biases enter the accumulators in binary32.
+struct SmOperands {
+    bf16x8 w1[2], w2[2], w3;   // A operands of layer 1 and 2 (two 16-unit halves) and layer 3
+    f32x4 b1[2], b2[2], b3;    // accumulator start values
+};
+
+template <typename Params>
+__device__ __forceinline__ SmOperands sm_operands(Params P)
+{
+    const int l = lane_id(), g = l >> 4, m = l & 15;
+    SmOperands W;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int unit = 16 * h + m;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * g + j;
+            W.w1[h][j] = (__bf16)(k < kSmIn ? P[kSmW1 + kSmIn * unit + (k < kSmIn ? k : 0)] : 0.0f);
+            W.w2[h][j] = (__bf16)P[kSmW2 + kSmHidden * unit + sm_slot_unit(g, j)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            W.b1[h][i] = P[kSmB1 + 16 * h + 4 * g + i];
+            W.b2[h][i] = P[kSmB2 + 16 * h + 4 * g + i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        W.w3[j] = (__bf16)(m < kSmOut ? P[kSmW3 + kSmHidden * (m < kSmOut ? m : 0) + sm_slot_unit(g, j)] : 0.0f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        W.b3[i] = g == 0 && i < kSmOut ? P[kSmB3 + (i < kSmOut ? i : 0)] : 0.0f;
+    return W;
+}
+
+__device__ __forceinline__ f32x4 relu_bf16(f32x4 a)
+{
+    f32x4 h;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        h[i] = round_bf16(a[i] > 0.0f ? a[i] : 0.0f);
+    return h;
+}
+
+__device__ __forceinline__ bf16x8 sm_pack(const f32x4 h[2])
+{
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b[i] = (__bf16)h[0][i];       // exact: already bfloat16 values
+        b[4 + i] = (__bf16)h[1][i];
+    }
+    return b;
+}
+
+// Forward pass of one 16-pixel sub-tile: x holds inputs 8 g .. 8 g + 7 of
+// pixel m (bfloat16, zero beyond the 27th).  h1[h][i], h2[h][i]: the bfloat16
+// activations of unit 16 h + 4 g + i for pixel m; o[0], o[1] (lane group 0):
+// the pixel's binary32 outputs.  Every call with the same operands gives the
+// same results, so inference and the training backward evaluate one function.
+__device__ __forceinline__ void sm_forward_tile(const SmOperands &W, bf16x8 x, f32x4 h1[2], f32x4 h2[2], f32x4 &o)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        h1[h] = relu_bf16(__builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w1[h], x, W.b1[h], 0, 0, 0));
+    const bf16x8 a1 = sm_pack(h1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        h2[h] = relu_bf16(__builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w2[h], a1, W.b2[h], 0, 0, 0));
+    const bf16x8 a2 = sm_pack(h2);
+    o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w3, a2, W.b3, 0, 0, 0);
+}
+
+// This lane's share of pixel (i, j)'s inputs (depth d valid): lane group
+// g < 3 the patch entries 8 g .. 8 g + 7, group 3 patch entry 24, the depth
+// and the incidence angle (its 4 neighbours are gathered in slots 1..4 of the
+// same 8 loads).  Rounded to bfloat16.
+__device__ __forceinline__ bf16x8 sm_input_part(const SmView &v, __amdgpu_buffer_rsrc_t img, int i, int j, float d,
+                                               int g)
+{
+    float q[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        int di, dj;
+        if (g < 3) {
+            const int k = 8 * g + t;
+            dj = k / 5 - 2;
+            di = k - 5 * (k / 5) - 2;
+        } else {
+            // slot 0: patch entry 24 (2, 2); 1..4: left, right, up, down; 5..7: nothing
+            di = t == 0 ? 2 : t == 1 ? -1 : t == 2 ? 1 : 0;
+            dj = t == 0 ? 2 : t == 3 ? -1 : t == 4 ? 1 : 0;
+        }
+        const bool load = g < 3 || t < 5;
+        q[t] = sm_load(img, load ? sm_off(v, i + di, j + dj) : kOutOfRange);
+    }
+    bf16x8 x;
+    if (g < 3) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float e = 0.0f;
+            if (sm_valid(q[t], v.d_max)) {
+                e = q[t] - d;
+                e = e < -0.5f ? -0.5f : (e > 0.5f ? 0.5f : e);
+            }
+            x[t] = (__bf16)e;
+        }
+    } else {
+        float e = 0.0f;
+        if (sm_valid(q[0], v.d_max)) {
+            e = q[0] - d;
+            e = e < -0.5f ? -0.5f : (e > 0.5f ? 0.5f : e);
+        }
+        x[0] = (__bf16)e;
+        x[1] = (__bf16)d;
+        x[2] = (__bf16)sm_incidence_of(v, i, j, d, q[1], q[2], q[3], q[4]);
+#pragma unroll
+        for (int t = 3; t < 8; ++t)
+            x[t] = (__bf16)0.0f;
+    }
+    return x;
+}
+
 __device__ __forceinline__ float2 sm_outputs(const float o[kSmOut], float vs)
 {
     const float w = 0.5f * (o[0] + sqrtf(o[0] * o[0] + 4.0f));
@@ -158,9 +316,10 @@ __device__ __forceinline__ float2 sm_outputs(const float o[kSmOut], float vs)
 
 constexpr int kMapThreads = 256;
 
-// The parameters are read straight from the (read-only) parameter buffer:
-// every lane of a wave reads the same one, so they arrive through scalar loads
-// and feed the multiply-adds as scalar operands, leaving the LDS port free.
+// Inference: one pixel per thread.  The parameters are read straight from the
+// (read-only) parameter buffer: every lane of a wave reads the same one, so
+// they arrive through scalar loads and feed the multiply-adds as scalar
+// operands, leaving the LDS port free.
 __global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs, const float *__restrict__ params,
                                                               float2 *__restrict__ out)
 {
@@ -177,6 +336,39 @@ __global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs
         sm_inputs(v, i, j, d, x);
         sm_forward(P, x, h1, h2, o);
         out[p] = sm_outputs(o, vs);
+    }
+}
+
+// Training maps on the matrix cores: one 16-pixel sub-tile per wave pass
+// (four lanes per pixel gather the inputs, the three layers are five MFMAs);
+// lane group 0 writes the pixels' (weight, truncation).  Invalid pixels get
+// (0, 0).
+__global__ __launch_bounds__(kMapThreads) void sm_maps_mfma_kernel(SmView v, float vs,
+                                                                   const float *__restrict__ params,
+                                                                   float2 *__restrict__ out)
+{
+    const SmOperands W = sm_operands(as_constant(params));
+    const int l = lane_id(), g = l >> 4, m = l & 15;
+    const long long n = (long long)v.width * v.height;
+    const long long n_tiles = (n + 15) / 16;
+    const __amdgpu_buffer_rsrc_t img = sm_image(v);
+    const long long waves = (long long)gridDim.x * (kMapThreads / 64);
+    for (long long tile = (long long)blockIdx.x * (kMapThreads / 64) + (threadIdx.x >> 6); tile < n_tiles;
+         tile += waves) {
+        const long long p = tile * 16 + m;
+        const bool in = p < n;
+        const float d = sm_load(img, in ? 4u * (uint32_t)p : kOutOfRange);
+        const bool valid = in && sm_valid(d, v.d_max);
+        const int j = (int)(p / v.width), i = (int)(p - (long long)j * v.width);
+        bf16x8 x = {};
+        if (valid)
+            x = sm_input_part(v, img, i, j, d, g);
+        f32x4 h1[2], h2[2], o;
+        sm_forward_tile(W, x, h1, h2, o);
+        if (g == 0 && in) {
+            const float ov[kSmOut] = {o[0], o[1]};
+            out[p] = valid ? sm_outputs(ov, vs) : make_float2(0.0f, 0.0f);
+        }
     }
 }
 
@@ -291,8 +483,10 @@ __device__ __forceinline__ int tile_at(int t, int m)
     return t * kSmHidden + ((m + t) & (kSmHidden - 1));
 }
 
-// Per pixel: recompute the forward pass, back-propagate dL/dw and dL/deps to
-// the hidden layers.  Per 64-pixel tile (staged in LDS) the weight gradients
+// Per 64-pixel tile: recompute the forward pass on the matrix cores (the
+// inference function, sm_forward_tile, on four 16-pixel sub-tiles whose
+// inputs come from the X tile), then per pixel back-propagate dL/dw and
+// dL/deps to the hidden layers.  Per tile (staged in LDS) the weight gradients
 // are sums of outer products over the pixels -- dense contractions -- and run
 // on the matrix cores: dW1 (32 x 27) += G1^T X and dW2 (32 x 32) += G2^T H1 as
 // 32 steps of v_mfma_f32_32x32x2_f32 each (two pixels per step).  Lane l
@@ -301,7 +495,7 @@ __device__ __forceinline__ int tile_at(int t, int m)
 // small W3 and bias sums stay on the vector units.
 __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 {
-    __shared__ float X[kTile][kSmIn + 1];
+    __shared__ float X[kTile][kSmIn + 1];   // column kSmIn is padding (zero)
     __shared__ float H1[kTile * kSmHidden], H2[kTile * kSmHidden];
     __shared__ float G1[kTile * kSmHidden], G2[kTile * kSmHidden];
     __shared__ float GO[kTile][kSmOut];
@@ -309,6 +503,8 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
     const int col = lane & 31, half = lane >> 5;
     // the weights are read-only here and the same for every lane: scalar loads, as in inference
     const ConstParams P = as_constant(a.params);
+    const SmOperands W = sm_operands(P);
+    const int g = lane >> 4, m16 = lane & 15;
     const double n_used = a.acc[1];
     const float scale = n_used > 0.0 ? (float)(1.0 / n_used) : 0.0f;
     v16f acc_w1 = {}, acc_w2 = {};
@@ -323,21 +519,18 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
     for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int f = (int)(tile / tiles_per_frame);
         const long long k = (tile - (long long)f * tiles_per_frame) * kTile + lane;
-        float x[kSmIn], h1[kSmHidden], h2[kSmHidden], o[kSmOut];
-        float go0 = 0.0f, go1 = 0.0f;
+        float x[kSmIn], h1[kSmHidden], h2[kSmHidden];
+        float go0 = 0.0f, go1 = 0.0f, gw = 0.0f, ge = 0.0f;
         bool active = false;
         if (k < per_frame) {
             const long long p = (long long)f * per_frame + k;
-            const float gw = a.gw[p], ge = a.ge[p];
+            gw = a.gw[p];
+            ge = a.ge[p];
             const SmView &v = a.views[f];
             const float d = v.depth[k];
             if ((gw != 0.0f || ge != 0.0f) && sm_valid(d, v.d_max)) {
                 const int j = (int)k / v.width, i = (int)k - j * v.width;
                 sm_inputs(v, i, j, d, x);
-                sm_forward(P, x, h1, h2, o);
-                go0 = scale * gw * 0.5f * (1.0f + o[0] / sqrtf(o[0] * o[0] + 4.0f));
-                const float q = 1.0f + o[1] * o[1];
-                go1 = scale * ge * a.vs * 7.0f * 0.5f / (q * sqrtf(q));
                 active = true;
             }
         }
@@ -345,6 +538,47 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 #pragma unroll
             for (int m = 0; m < kSmIn; ++m)
                 x[m] = 0.0f;
+        }
+        // forward pass on the matrix cores, the same function inference evaluates:
+        // four 16-pixel sub-tiles, inputs read back from the X tile
+#pragma unroll
+        for (int m = 0; m < kSmIn; ++m)
+            X[lane][m] = x[m];
+        X[lane][kSmIn] = 0.0f;
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < kTile / 16; ++st) {
+            const int t = 16 * st + m16;
+            bf16x8 xb;
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                xb[jj] = (__bf16)(8 * g + jj < kSmIn ? X[t][8 * g + jj < kSmIn ? 8 * g + jj : 0] : 0.0f);
+            f32x4 th1[2], th2[2], to;
+            sm_forward_tile(W, xb, th1, th2, to);
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    H1[tile_at(t, 16 * h + 4 * g + i)] = th1[h][i];
+                    H2[tile_at(t, 16 * h + 4 * g + i)] = th2[h][i];
+                }
+            if (g == 0) {
+                GO[t][0] = to[0];
+                GO[t][1] = to[1];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < kSmHidden; ++m) {
+                h1[m] = H1[tile_at(lane, m)];
+                h2[m] = H2[tile_at(lane, m)];
+            }
+            const float o0 = GO[lane][0], o1 = GO[lane][1];
+            go0 = scale * gw * 0.5f * (1.0f + o0 / sqrtf(o0 * o0 + 4.0f));
+            const float q = 1.0f + o1 * o1;
+            go1 = scale * ge * a.vs * 7.0f * 0.5f / (q * sqrtf(q));
+        } else {
 #pragma unroll
             for (int m = 0; m < kSmHidden; ++m)
                 h1[m] = h2[m] = 0.0f;
@@ -371,9 +605,6 @@ __global__ __launch_bounds__(64) void sm_backward_kernel(SmBackArgs a)
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m)
             g1[m] = h1[m] > 0.0f ? g1[m] : 0.0f;
-#pragma unroll
-        for (int m = 0; m < kSmIn; ++m)
-            X[lane][m] = x[m];
 #pragma unroll
         for (int m = 0; m < kSmHidden; ++m) {
             H1[tile_at(lane, m)] = h1[m];
@@ -462,6 +693,16 @@ hipError_t launch_sm_maps(const SmView &v, float vs, const float *params, float2
     const unsigned groups = (unsigned)std::max<long long>(1, std::min<long long>((n + kMapThreads - 1) / kMapThreads,
                                                                                   2048));
     hipLaunchKernelGGL(sm_maps_kernel, dim3(groups), dim3(kMapThreads), 0, stream, v, vs, params, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sm_maps_mfma(const SmView &v, float vs, const float *params, float2 *out, hipStream_t stream)
+{
+    const long long tiles = ((long long)v.width * v.height + 15) / 16;   // 16 pixels per wave pass
+    const long long waves_per_group = kMapThreads / 64;
+    const unsigned groups = (unsigned)std::max<long long>(
+        1, std::min<long long>((tiles + waves_per_group - 1) / waves_per_group, 2048));
+    hipLaunchKernelGGL(sm_maps_mfma_kernel, dim3(groups), dim3(kMapThreads), 0, stream, v, vs, params, out);
     return hipGetLastError();
 }
 

@@ -46,6 +46,8 @@ struct SmBackArgs {
 };
 
 hipError_t launch_sm_maps(const SmView &v, float vs, const float *params, float2 *out, hipStream_t stream);
+// The same maps from the matrix-core forward pass that training differentiates.
+hipError_t launch_sm_maps_mfma(const SmView &v, float vs, const float *params, float2 *out, hipStream_t stream);
 hipError_t launch_sm_fill(float *p, long long n, float value, hipStream_t stream);
 hipError_t launch_sm_loss(const SmLossArgs &a, hipStream_t stream);
 hipError_t launch_sm_backward(const SmBackArgs &a, hipStream_t stream);

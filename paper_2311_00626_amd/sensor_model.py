@@ -196,6 +196,29 @@ def surface_error(room: Room, vs: float, params: Optional[np.ndarray], max_range
     return out
 
 
+def gain_run(n_rooms: int = 20, n_held_out: int = 3, frames: int = 100, vs: float = 0.02, window: int = 8,
+             steps: int = 2400, lr: float = 3e-3, log_every: int = 0) -> dict:
+    """Trains on rooms 1000.. and compares the learned model with the
+    linear-dropoff fallback on held-out rooms 2000.. (640x480 frames); the
+    defaults are the full configuration.  Returns the losses, timings and
+    per-room surface errors."""
+    import time
+    cam = synth.CAM_640
+    t0 = time.perf_counter()
+    rooms = [prepare_room(1000 + k, frames, cam, vs, window=window) for k in range(n_rooms)]
+    held = [prepare_room(2000 + k, frames, cam, vs, window=window) for k in range(n_held_out)]
+    t_data = time.perf_counter() - t0
+    before = window_loss(init_params(0), held, vs)
+    t1 = time.perf_counter()
+    res = train(rooms, vs, steps=steps, lr=lr, seed=0, log_every=log_every or max(1, steps // 12))
+    t_train = time.perf_counter() - t1
+    return {"train_rooms": n_rooms, "frames_per_room": frames, "resolution": f"{cam.width}x{cam.height}",
+            "voxel_m": vs, "window": window, "steps": steps, "data_s": t_data, "train_s": t_train,
+            "held_out_loss_before": before, "held_out_loss_after": window_loss(res.params, held, vs),
+            "loss_log": res.losses,
+            "surface_error": {str(r.seed): surface_error(r, vs, res.params) for r in held}}
+
+
 def main(argv=None) -> dict:
     """Trains at a chosen scale and compares with the linear-dropoff fallback
     on held-out rooms.  Defaults: the full configuration -- 20 training rooms
@@ -215,20 +238,7 @@ def main(argv=None) -> dict:
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
-    cam, vs = synth.CAM_640, args.voxel
-    t0 = time.perf_counter()
-    rooms = [prepare_room(1000 + k, args.frames, cam, vs, window=args.window) for k in range(args.rooms)]
-    held = [prepare_room(2000 + k, args.frames, cam, vs, window=args.window) for k in range(args.held_out)]
-    t_data = time.perf_counter() - t0
-    before = window_loss(init_params(0), held, vs)
-    t1 = time.perf_counter()
-    res = train(rooms, vs, steps=args.steps, lr=args.lr, seed=0, log_every=max(1, args.steps // 12))
-    t_train = time.perf_counter() - t1
-    out = {"train_rooms": args.rooms, "frames_per_room": args.frames, "resolution": f"{cam.width}x{cam.height}",
-           "voxel_m": vs, "window": args.window, "steps": args.steps, "data_s": t_data, "train_s": t_train,
-           "held_out_loss_before": before, "held_out_loss_after": window_loss(res.params, held, vs),
-           "loss_log": res.losses,
-           "surface_error": {str(r.seed): surface_error(r, vs, res.params) for r in held}}
+    out = gain_run(args.rooms, args.held_out, args.frames, args.voxel, args.window, args.steps, args.lr)
     text = json.dumps(out)
     print(text, flush=True)
     if args.out:
