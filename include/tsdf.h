@@ -315,7 +315,10 @@ TSDF_API const char *tsdf_strerror(int status);
  *               each XCD reads about 1/8 of every depth image (lattice-walk
  *               launches; more than 1 turns compaction off);
  *   chunk       lattice blocks a wave culls per pass, 1 .. 64 (lattice-walk
- *               launches);
+ *               launches); 0 with one band: every thread of a workgroup culls
+ *               one lattice block per pass (a workgroup's blocks strided
+ *               across the lattice) and the workgroup's waves share its
+ *               surviving blocks through LDS;
  *   footprint   footprint culling: a pre-pass reduces every view to the
  *               largest valid measurement per 8/16/32/64-pixel tile, and a
  *               block is skipped when its nearest point lies beyond the

@@ -383,6 +383,8 @@ int schedule(const tsdf_map *m, Lattice &lat)
     const long long chunk = lc.chunk > 0 ? lc.chunk : (lat.n_lat > 4 * full_waves ? 8 : 1);
     lat.chunk = (int)std::max(1ll, std::min<long long>(chunk, kMaxChunk));
     lat.partitions = parts;
+    // automatic chunk, one band: the walk culls and compacts per workgroup
+    lat.group_scan = (lc.chunk == 0 && parts == 1) ? 1 : 0;
     return (int)groups;
 }
 

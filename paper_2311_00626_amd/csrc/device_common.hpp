@@ -543,10 +543,93 @@ __device__ __forceinline__ uint32_t spread_position(uint32_t g, uint32_t groups)
 // partition are handed to body(bx, by, bz, view_mask) one at a time
 // (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
 // lattice block is a candidate exactly when marked.
+// Lattice block lb of the launch: its block indices and the views whose
+// culling it survives (bit v), or, with ray-walk marks, 1 when the walk
+// marked it (the mark is cleared for the next frame: each entry is read by
+// exactly one thread).
+__device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const CameraView *cams, int n_views,
+                                                      const MapConsts &mc, uint32_t lb, int &bx, int &by, int &bz)
+{
+    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+    const uint32_t rest = lb / dim_x;
+    bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
+    by = lat.lat_min[1] + (int)(rest % dim_y);
+    bz = lat.lat_min[2] + (int)(rest / dim_y);
+    uint32_t vmask = 0;
+    if (cams[0].dda_marks) {
+        vmask = cams[0].dda_marks[lb] ? 1u : 0u;
+        if (vmask)
+            cams[0].dda_marks[lb] = 0;
+    } else {
+        for (int v = 0; v < n_views; ++v)
+            if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                vmask |= 1u << v;
+    }
+    return vmask;
+}
+
+// Walk of a launch's lattice compacted per workgroup (one band): each pass
+// gives every thread of the grid one lattice block, the blocks of a
+// workgroup strided across the whole lattice (block lb goes to the workgroup
+// at position lb mod groups, in the XCD-aware order of spread_position), so
+// that every workgroup draws about the same number of surviving blocks from
+// anywhere in the frame; a workgroup collects its survivors in LDS and its
+// waves take them in turn, so no wave handles more than its share.
+template <class Body>
+__device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const CameraView *cams, int n_views,
+                                                   const MapConsts &mc, Body &&body)
+{
+    constexpr uint32_t kThreads = 64u * (uint32_t)kWavesPerGroup;
+    __shared__ uint32_t s_lb[kThreads], s_vm[kThreads];
+    __shared__ uint32_t s_count[kWavesPerGroup];
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const uint32_t groups = gridDim.x;
+    const uint32_t pos = spread_position(blockIdx.x, groups);
+    const uint32_t n_lat = (uint32_t)lat.n_lat;
+    const unsigned long long per_pass = (unsigned long long)groups * kThreads;
+    // the loop runs the same number of times in every thread of the workgroup
+    for (unsigned long long base = 0; base < n_lat; base += per_pass) {
+        const unsigned long long item = base + (unsigned long long)threadIdx.x * groups + pos;
+        uint32_t vmask = 0;
+        int bx = 0, by = 0, bz = 0;
+        if (item < n_lat)
+            vmask = lattice_candidate(lat, cams, n_views, mc, (uint32_t)item, bx, by, bz);
+        const unsigned long long keep = __ballot(vmask != 0);
+        if (lane == 0)
+            s_count[wave] = (uint32_t)__popcll(keep);
+        __syncthreads();
+        uint32_t at = 0, total = 0;
+        for (int k = 0; k < kWavesPerGroup; ++k) {
+            at += k < wave ? s_count[k] : 0u;
+            total += s_count[k];
+        }
+        if (vmask != 0) {
+            const uint32_t i = at + (uint32_t)__popcll(keep & ((1ull << lane) - 1ull));
+            s_lb[i] = (uint32_t)item;
+            s_vm[i] = vmask;
+        }
+        __syncthreads();
+        for (uint32_t i = (uint32_t)wave; i < total; i += (uint32_t)kWavesPerGroup) {
+            const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_lb[i]);
+            const uint32_t svm = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_vm[i]);
+            const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
+            const uint32_t rest = lb / dim_x;
+            body(lat.lat_min[0] + (int)(lb - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
+                 lat.lat_min[2] + (int)(rest / dim_y), svm);
+        }
+        __syncthreads();   // s_lb, s_vm and s_count are rewritten by the next pass
+    }
+}
+
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body)
 {
+    if (lat.group_scan) {
+        scan_lattice_group(lat, cams, n_views, mc, body);
+        return;
+    }
     const int lane = lane_id();
     const uint32_t P = (uint32_t)lat.partitions;
     const int part = (int)(blockIdx.x % P);

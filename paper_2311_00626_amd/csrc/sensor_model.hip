@@ -257,56 +257,6 @@ __device__ __forceinline__ void sm_forward_tile(const SmOperands &W, bf16x8 x, f
     o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(W.w3, a2, W.b3, 0, 0, 0);
 }
 
-// This lane's share of pixel (i, j)'s inputs (depth d valid): lane group
-// g < 3 the patch entries 8 g .. 8 g + 7, group 3 patch entry 24, the depth
-// and the incidence angle (its 4 neighbours are gathered in slots 1..4 of the
-// same 8 loads).  Rounded to bfloat16.
-__device__ __forceinline__ bf16x8 sm_input_part(const SmView &v, __amdgpu_buffer_rsrc_t img, int i, int j, float d,
-                                               int g)
-{
-    float q[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        int di, dj;
-        if (g < 3) {
-            const int k = 8 * g + t;
-            dj = k / 5 - 2;
-            di = k - 5 * (k / 5) - 2;
-        } else {
-            // slot 0: patch entry 24 (2, 2); 1..4: left, right, up, down; 5..7: nothing
-            di = t == 0 ? 2 : t == 1 ? -1 : t == 2 ? 1 : 0;
-            dj = t == 0 ? 2 : t == 3 ? -1 : t == 4 ? 1 : 0;
-        }
-        const bool load = g < 3 || t < 5;
-        q[t] = sm_load(img, load ? sm_off(v, i + di, j + dj) : kOutOfRange);
-    }
-    bf16x8 x;
-    if (g < 3) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            float e = 0.0f;
-            if (sm_valid(q[t], v.d_max)) {
-                e = q[t] - d;
-                e = e < -0.5f ? -0.5f : (e > 0.5f ? 0.5f : e);
-            }
-            x[t] = (__bf16)e;
-        }
-    } else {
-        float e = 0.0f;
-        if (sm_valid(q[0], v.d_max)) {
-            e = q[0] - d;
-            e = e < -0.5f ? -0.5f : (e > 0.5f ? 0.5f : e);
-        }
-        x[0] = (__bf16)e;
-        x[1] = (__bf16)d;
-        x[2] = (__bf16)sm_incidence_of(v, i, j, d, q[1], q[2], q[3], q[4]);
-#pragma unroll
-        for (int t = 3; t < 8; ++t)
-            x[t] = (__bf16)0.0f;
-    }
-    return x;
-}
-
 __device__ __forceinline__ float2 sm_outputs(const float o[kSmOut], float vs)
 {
     const float w = 0.5f * (o[0] + sqrtf(o[0] * o[0] + 4.0f));
@@ -339,36 +289,68 @@ __global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs
     }
 }
 
-// Training maps on the matrix cores: one 16-pixel sub-tile per wave pass
-// (four lanes per pixel gather the inputs, the three layers are five MFMAs);
-// lane group 0 writes the pixels' (weight, truncation).  Invalid pixels get
-// (0, 0).
+// Training maps on the matrix cores.  A wave takes 64 pixels, one per lane,
+// gathers their inputs (sm_inputs, as the backward does), stages them in its
+// LDS tile, and runs the forward pass as four 16-pixel sub-tiles of five
+// MFMAs, building each sub-tile's operands from the tile exactly as the
+// backward's recomputation does (so the two agree bit for bit); lane group 0
+// writes the pixels' (weight, truncation).  Invalid pixels get (0, 0).
 __global__ __launch_bounds__(kMapThreads) void sm_maps_mfma_kernel(SmView v, float vs,
                                                                    const float *__restrict__ params,
                                                                    float2 *__restrict__ out)
 {
+    constexpr int kWaves = kMapThreads / 64;
+    __shared__ float X[kWaves][64][kSmIn + 1];   // column kSmIn: 1 for a valid pixel
     const SmOperands W = sm_operands(as_constant(params));
-    const int l = lane_id(), g = l >> 4, m = l & 15;
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6), g = lane >> 4, m = lane & 15;
+    float(*Xw)[kSmIn + 1] = X[wave];
     const long long n = (long long)v.width * v.height;
-    const long long n_tiles = (n + 15) / 16;
-    const __amdgpu_buffer_rsrc_t img = sm_image(v);
-    const long long waves = (long long)gridDim.x * (kMapThreads / 64);
-    for (long long tile = (long long)blockIdx.x * (kMapThreads / 64) + (threadIdx.x >> 6); tile < n_tiles;
-         tile += waves) {
-        const long long p = tile * 16 + m;
-        const bool in = p < n;
-        const float d = sm_load(img, in ? 4u * (uint32_t)p : kOutOfRange);
-        const bool valid = in && sm_valid(d, v.d_max);
-        const int j = (int)(p / v.width), i = (int)(p - (long long)j * v.width);
-        bf16x8 x = {};
-        if (valid)
-            x = sm_input_part(v, img, i, j, d, g);
-        f32x4 h1[2], h2[2], o;
-        sm_forward_tile(W, x, h1, h2, o);
-        if (g == 0 && in) {
-            const float ov[kSmOut] = {o[0], o[1]};
-            out[p] = valid ? sm_outputs(ov, vs) : make_float2(0.0f, 0.0f);
+    const long long n_tiles = (n + 63) / 64;
+    const long long waves = (long long)gridDim.x * kWaves;
+    for (long long tile = (long long)blockIdx.x * kWaves + wave; tile < n_tiles; tile += waves) {
+        const long long p = tile * 64 + lane;
+        float x[kSmIn];
+        bool valid = false;
+        if (p < n) {
+            const float d = v.depth[p];
+            if (sm_valid(d, v.d_max)) {
+                const int j = (int)(p / v.width), i = (int)(p - (long long)j * v.width);
+                sm_inputs(v, i, j, d, x);
+                valid = true;
+            }
         }
+        if (!valid) {
+#pragma unroll
+            for (int k = 0; k < kSmIn; ++k)
+                x[k] = 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kSmIn; ++k)
+            Xw[lane][k] = x[k];
+        Xw[lane][kSmIn] = valid ? 1.0f : 0.0f;
+        // the wave's own LDS writes are read back by other lanes of the wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int t = 16 * st + m;
+            bf16x8 xb;
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj)
+                xb[jj] = (__bf16)(8 * g + jj < kSmIn ? Xw[t][8 * g + jj < kSmIn ? 8 * g + jj : 0] : 0.0f);
+            f32x4 h1[2], h2[2], o;
+            sm_forward_tile(W, xb, h1, h2, o);
+            const long long q = tile * 64 + t;
+            if (g == 0 && q < n) {
+                const float ov[kSmOut] = {o[0], o[1]};
+                out[q] = Xw[t][kSmIn] != 0.0f ? sm_outputs(ov, vs) : make_float2(0.0f, 0.0f);
+            }
+        }
+        // the tile's reads are complete before the next pass rewrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -698,7 +680,7 @@ hipError_t launch_sm_maps(const SmView &v, float vs, const float *params, float2
 
 hipError_t launch_sm_maps_mfma(const SmView &v, float vs, const float *params, float2 *out, hipStream_t stream)
 {
-    const long long tiles = ((long long)v.width * v.height + 15) / 16;   // 16 pixels per wave pass
+    const long long tiles = ((long long)v.width * v.height + 63) / 64;   // 64 pixels per wave pass
     const long long waves_per_group = kMapThreads / 64;
     const unsigned groups = (unsigned)std::max<long long>(
         1, std::min<long long>((tiles + waves_per_group - 1) / waves_per_group, 2048));

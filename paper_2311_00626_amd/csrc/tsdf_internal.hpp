@@ -149,6 +149,7 @@ struct Lattice {
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
     int chunk;              // 1 .. kMaxChunk
     int partitions;         // 1 or kPartitions ownership bands
+    int group_scan;         // nonzero: the walk culls and compacts per workgroup (scan_lattice_group)
     // Compacted launches: a cull kernel writes the surviving blocks (lattice
     // index, view mask) here and the integration kernel deals them out to its
     // waves; nullptr: the integration kernel walks the lattice itself.
