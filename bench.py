@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 STAGING = "auto"   # LDS footprint staging of the one-frame-per-launch legs (--staging)
 PARTITIONS = 0     # image bands of the one-frame-per-launch legs (--partitions; 0 = automatic)
+CHUNK = 0          # lattice blocks a wave culls per pass (--chunk; 0 = automatic)
+COMPACTION = "auto"  # compacted launches of the one-frame-per-launch legs (--compaction)
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "integrate_depth_cluttered_room_pmc.json")
 KERNEL_SOURCES = ["paper_2311_00626_amd/csrc/integrate.hip", "paper_2311_00626_amd/csrc/device_common.hpp",
                   "paper_2311_00626_amd/csrc/tsdf_internal.hpp"]
@@ -215,15 +217,16 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     import torch
     from paper_2311_00626_amd.tsdf import TsdfMap
     n_frames = frames.shape[0]
+    fl = list(frames.unbind(0))   # one view per frame, made before timing
     H, W = frames.shape[1], frames.shape[2]
     K = w.camera.K
     log(f"leg: {w.name} {storage} {map_kw or ''} one frame per launch, {steps} timed after {warmup}")
     m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity, **map_kw)
-    m.set_launch_config(partitions=PARTITIONS, staging=STAGING)
+    m.set_launch_config(partitions=PARTITIONS, chunk=CHUNK, compaction=COMPACTION, staging=STAGING)
     if setup is not None:
         setup(m)
     for k in range(warmup):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        m.integrate_depth(fl[k % n_frames], K, poses[k % n_frames])
     torch.cuda.synchronize()
     b0, u0, _, t0_ = counters(m)
     c0 = candidates(m)
@@ -232,7 +235,7 @@ def timed_plain(w, frames, poses, storage: str, steps: int, warmup: int, block_c
     t_start = time.perf_counter()
     ev[0].record()
     for k in range(warmup, warmup + steps):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        m.integrate_depth(fl[k % n_frames], K, poses[k % n_frames])
     ev[1].record()
     torch.cuda.synchronize()
     t_end = time.perf_counter()
@@ -268,18 +271,19 @@ def per_frame_times(w, frames, poses, storage: str, steps: int, warmup: int, blo
     import torch
     from paper_2311_00626_amd.tsdf import TsdfMap
     n_frames = frames.shape[0]
+    fl = list(frames.unbind(0))   # one view per frame, made before timing
     K = w.camera.K
     m = TsdfMap.from_params(w.params, storage=storage, block_capacity=block_capacity, **map_kw)
-    m.set_launch_config(partitions=PARTITIONS, staging=STAGING)
+    m.set_launch_config(partitions=PARTITIONS, chunk=CHUNK, compaction=COMPACTION, staging=STAGING)
     if setup is not None:
         setup(m)
     for k in range(warmup):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        m.integrate_depth(fl[k % n_frames], K, poses[k % n_frames])
     torch.cuda.synchronize()
     m.profile(True)
     ms = []
     for k in range(warmup, warmup + steps):
-        m.integrate_depth(frames[k % n_frames], K, poses[k % n_frames])
+        m.integrate_depth(fl[k % n_frames], K, poses[k % n_frames])
         t, n = m.profile_read()
         assert n == 1
         ms.append(t)
@@ -332,11 +336,12 @@ def timed_views(w, frames, poses, B: int, block_capacity: int) -> dict:
     from paper_2311_00626_amd.tsdf import TsdfMap
     K = w.camera.K
     n = frames.shape[0]
+    fl = list(frames.unbind(0))   # one view per frame, made before timing
     H, W = frames.shape[1], frames.shape[2]
     log(f"leg: {w.name} {B} frames per launch")
     m = TsdfMap.from_params(w.params, block_capacity=block_capacity)
     first = n % B or B
-    m.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
+    m.integrate_depth_views(fl[:first], [K] * first, poses[:first])
     torch.cuda.synchronize()
     b0, u0, wr0, t0_ = counters(m)
     ev = region_events()
@@ -344,7 +349,7 @@ def timed_views(w, frames, poses, B: int, block_capacity: int) -> dict:
     t_start = time.perf_counter()
     ev[0].record()
     for a in range(first, n, B):
-        m.integrate_depth_views([frames[k] for k in range(a, a + B)], [K] * B, poses[a:a + B])
+        m.integrate_depth_views(fl[a:a + B], [K] * B, poses[a:a + B])
     ev[1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t_start
@@ -513,12 +518,18 @@ def main():
                     help="run only the PMC calibration kernels (--copy-calibration-mib, default 256) and exit")
     ap.add_argument("--partitions", type=int, default=0, choices=(0, 1, 8),
                     help="image bands (one per XCD) of the one-frame-per-launch legs; 0 = automatic")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="lattice blocks a wave culls per pass in lattice walks (0 = automatic)")
+    ap.add_argument("--compaction", default="auto", choices=("auto", "never", "always"),
+                    help="compacted launches of the one-frame-per-launch legs")
     ap.add_argument("--staging", default="auto", choices=("auto", "never", "always"),
                     help="LDS footprint staging of the one-frame-per-launch legs")
     args = ap.parse_args()
-    global STAGING, PARTITIONS
+    global STAGING, PARTITIONS, CHUNK, COMPACTION
     STAGING = args.staging
     PARTITIONS = args.partitions
+    CHUNK = args.chunk
+    COMPACTION = args.compaction
     if args.calibrate_only:
         import torch
         calibration_kernels(args.copy_calibration_mib or 256, torch.device("cuda:0"))
@@ -539,6 +550,7 @@ def main():
     log(f"rendered {len(frames_host)} frames in {time.perf_counter() - t0:.1f} s")
     frames = torch.stack([torch.as_tensor(f) for f in frames_host]).to(dev).contiguous()
     n_frames = frames.shape[0]
+    fl = list(frames.unbind(0))   # one view per frame, made before timing
     H, W = frames.shape[1], frames.shape[2]
     K = w.camera.K
     poses = [np.ascontiguousarray(p, dtype=np.float32) for p in w.poses]
@@ -574,7 +586,7 @@ def main():
         B = args.batch
         mb = TsdfMap.from_params(w.params, block_capacity=1 << 16)
         first = n_frames % B or B           # warm-up batch, so that the rest splits evenly
-        mb.integrate_depth_views([frames[k] for k in range(first)], [K] * first, poses[:first])
+        mb.integrate_depth_views(fl[:first], [K] * first, poses[:first])
         torch.cuda.synchronize()
         bb0, ub0, wb0, tb0 = counters(mb)
         ev = region_events()
@@ -582,7 +594,7 @@ def main():
         tb_start = time.perf_counter()
         ev[0].record()
         for a in range(first, n_frames, B):
-            mb.integrate_depth_views([frames[k] for k in range(a, a + B)], [K] * B, poses[a:a + B])
+            mb.integrate_depth_views(fl[a:a + B], [K] * B, poses[a:a + B])
         ev[1].record()
         torch.cuda.synchronize()
         tb_end = time.perf_counter()

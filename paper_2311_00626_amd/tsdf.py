@@ -252,6 +252,13 @@ class TsdfMap:
         self._h = h
         self.params = p
         self.block_capacity = block_capacity
+        # per-map host staging of K and the pose: the library copies both by
+        # value during a call, so one buffer each is reused call after call
+        # (filled in place, their addresses taken once)
+        self._K = (C.c_float * 4)()
+        self._K_addr = C.addressof(self._K)
+        self._T = np.empty(16, np.float32)
+        self._T_addr = self._T.ctypes.data
 
     @classmethod
     def from_params(cls, params, **kw) -> "TsdfMap":
@@ -288,10 +295,10 @@ class TsdfMap:
         if not (depth.is_cuda and depth.dtype == torch.float32 and depth.dim() == 2
                 and depth.is_contiguous()):
             raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
-        Kh = _host_f32(K, 4)
-        Th = _host_f32(T_world_cam, 16)
+        self._K[:] = K
+        self._T[:] = np.reshape(T_world_cam, 16)
         H, W = depth.shape
-        st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
+        st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, self._K_addr, self._T_addr,
                                  _stream_ptr(stream, depth.get_device()))
         _check(st, "integrate_depth")
 
@@ -302,10 +309,10 @@ class TsdfMap:
         if not (depth.is_cuda and depth.dtype == torch.float32 and depth.dim() == 2
                 and depth.is_contiguous()):
             raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
-        Kh = _host_f32(K, 4)
-        Th = _host_f32(T_world_cam, 16)
+        self._K[:] = K
+        self._T[:] = np.reshape(T_world_cam, 16)
         H, W = depth.shape
-        st = lib.integrate_depth_noalloc(self._h, depth.data_ptr(), W, H, Kh.ctypes.data, Th.ctypes.data,
+        st = lib.integrate_depth_noalloc(self._h, depth.data_ptr(), W, H, self._K_addr, self._T_addr,
                                          _stream_ptr(stream, depth.get_device()))
         _check(st, "integrate_depth_noalloc")
 
@@ -317,8 +324,8 @@ class TsdfMap:
         lm = lidar_struct(lidar)
         if (lm.height, lm.width) != tuple(rng.shape):
             raise ValueError("range image shape does not match the LiDAR model")
-        Th = _host_f32(T_world_sensor, 16)
-        _check(lib.integrate_range(self._h, rng.data_ptr(), C.byref(lm), Th.ctypes.data, _stream_ptr(stream)),
+        self._T[:] = np.reshape(T_world_sensor, 16)
+        _check(lib.integrate_range(self._h, rng.data_ptr(), C.byref(lm), self._T_addr, _stream_ptr(stream)),
                "integrate_range")
 
     def integrate_depth_views(self, depths: Sequence[torch.Tensor], Ks, Ts, max_ranges=None,
