@@ -674,7 +674,11 @@ def main():
     if batched is not None:
         result["batched"] = batched
     if not args.skip_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(w, frames_host, args.cpu_budget)
+        cb = cpu_baseline(w, frames_host, args.cpu_budget)
+        # the GPU's voxel updates/s over the oracle's (a baseline, not a measure of kernel quality)
+        cb["gpu_speedup"] = {"vs_all_cores": result["value"] / cb["value"],
+                             "vs_one_thread": result["value"] / cb["one_thread"]["value"]}
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 
