@@ -23,9 +23,9 @@ def t():
 
 def test_header_declares_expected_entry_points():
     names = set(declared_functions())
-    for n in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth", "integrate_range",
-              "integrate_depth_views", "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
-              "tsdf_strerror"):
+    for n in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth", "integrate_depth_noalloc",
+              "integrate_range", "integrate_depth_views", "query_blocks", "query_tsdf", "query_touched", "map_stats",
+              "map_status", "tsdf_strerror"):
         assert n in names
 
 
@@ -40,6 +40,25 @@ def test_struct_layouts(t):
     assert C.sizeof(t.tsdf_lidar_model) == 32
     assert C.sizeof(t.tsdf_stats) == 72
     assert C.sizeof(t.tsdf_launch_config) == 24
+
+
+def test_struct_layouts_match_the_c_compiler(t, tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal the C layout of
+    include/tsdf.h (a small C program prints sizeof / offsetof)."""
+    import subprocess
+    exe = tmp_path / "abi_sizes"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe),
+                    os.path.join(ROOT, "tests", "abi_sizes.c")], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    c_layout = dict(line.rsplit(" ", 1) for line in out.splitlines())
+    checked = 0
+    for key, value in c_layout.items():
+        struct, _, field = key.partition(".")
+        cls = getattr(t, struct)
+        got = C.sizeof(cls) if not field else getattr(cls, field).offset
+        assert got == int(value), (key, got, value)
+        checked += 1
+    assert checked >= 15
 
 
 def test_params_struct_layout(t):
