@@ -271,6 +271,25 @@ TSDF_API int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity,
 TSDF_API int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks,
                float *out_dist_dev, float *out_weight_dev, void *hip_stream);
 
+/* Writes n_blocks blocks into the map, each found or inserted in the block
+ * hash as integration inserts blocks (§IV-A: block index -> block of 8^3
+ * voxels): blocks_xyz_dev holds int32 triples, dist_dev and weight_dev 512
+ * floats per block in the order query_tsdf writes them (voxel lx + 8 ly +
+ * 64 lz), all caller-owned device memory read on hip_stream.  With
+ * query_blocks and query_tsdf it saves and restores a map: the restored map
+ * holds the same blocks and voxel values (binary16 storage rounds values that
+ * are not binary16 numbers to nearest), and later integration continues from
+ * them; the touched list and the running counters other than the block count
+ * are not part of it.  A block already in the map is overwritten; each block
+ * should appear once (duplicates race, one of their values wins).  Blocks
+ * outside the block-index range are skipped.  A full pool or hash sets the
+ * sticky TSDF_EFULL, reported by map_status and the next integration call
+ * (reserve ahead: map_stats gives blocks and block_capacity).  Only enqueues.
+ * Errors: TSDF_EINVAL (NULL map, n_blocks < 0, NULL buffers with n_blocks >
+ * 0), TSDF_ESTATE (sticky error), TSDF_EDEVICE. */
+TSDF_API int insert_blocks(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks, const float *dist_dev,
+                           const float *weight_dev, void *hip_stream);
+
 /* Blocks with at least one voxel updated by the most recent integrate_depth
  * or integrate_depth_views call (the "updated blocks" that downstream layers consume, §IV-C), in
  * unspecified order, as int32 triples; same capacity / count contract as

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libtsdf.so")
-SOURCES = ["integrate.hip", "integrate_views.hip", "footprint.hip", "sensor_model.hip", "dda.hip", "query.hip", "noalloc.hip", "abi.cpp"]
+SOURCES = ["integrate.hip", "integrate_views.hip", "footprint.hip", "sensor_model.hip", "dda.hip", "query.hip", "noalloc.hip", "insert.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1359,6 +1359,21 @@ int query_tsdf(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks, f
                                         (hipStream_t)hip_stream));
 }
 
+int insert_blocks(tsdf_map *m, const int32_t *blocks_xyz_dev, long long n_blocks, const float *dist_dev,
+                  const float *weight_dev, void *hip_stream)
+{
+    if (!m || n_blocks < 0 || (n_blocks > 0 && (!blocks_xyz_dev || !dist_dev || !weight_dev)))
+        return TSDF_EINVAL;
+    if (m->sticky)
+        return TSDF_ESTATE;
+    if (n_blocks == 0)
+        return TSDF_OK;
+    if (use_device(m) != hipSuccess)
+        return TSDF_EDEVICE;
+    return hip_status(launch_insert_blocks(m->dm, blocks_xyz_dev, n_blocks, dist_dev, weight_dev,
+                                           (hipStream_t)hip_stream));
+}
+
 int query_touched(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long long *out_count, void *hip_stream)
 {
     if (!m || !out_count || capacity < 0 || (capacity > 0 && !out_xyz_dev))

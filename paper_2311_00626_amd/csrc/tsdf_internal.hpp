@@ -228,6 +228,10 @@ hipError_t launch_decode_keys(const unsigned long long *keys, long long n, int32
 // Compacted launches (integrate.hip, integrate_views.hip): the cull kernels
 // fill lat.cand; the list kernels integrate its entries.
 hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream_t stream);
+// Finds or inserts n blocks (int32 triples) and writes their 512 (distance,
+// weight) pairs each (insert.hip).
+hipError_t launch_insert_blocks(const DeviceMap &dm, const int32_t *xyz, long long n, const float *dist,
+                                const float *weight, hipStream_t stream);
 hipError_t launch_cull_views(const DeviceMap &dm, const ViewsArgs &va, hipStream_t stream);
 // lane_views: the views share one camera model (see views_share_model)
 hipError_t launch_cull_views_dev(const DeviceMap &dm, const ViewsArgs *va_dev, int groups, bool lane_views,

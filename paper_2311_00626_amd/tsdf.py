@@ -100,6 +100,7 @@ def _load() -> C.CDLL:
     lib.integrate_depth_noalloc.argtypes = [vp, vp, i, i, vp, vp, vp]
     lib.query_blocks.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.query_tsdf.argtypes = [vp, vp, ll, vp, vp, vp]
+    lib.insert_blocks.argtypes = [vp, vp, ll, vp, vp, vp]
     lib.query_touched.argtypes = [vp, vp, ll, C.POINTER(ll), vp]
     lib.map_stats.argtypes = [vp, C.POINTER(tsdf_stats), vp]
     lib.integrate_depth_views.argtypes = [vp, C.POINTER(tsdf_depth_view), i, vp]
@@ -122,7 +123,7 @@ def _load() -> C.CDLL:
     for name in ("create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth",
                  "integrate_depth_noalloc", "integrate_depth_views",
                  "integrate_range",
-                 "query_blocks",
+                 "query_blocks", "insert_blocks",
                  "query_tsdf", "query_touched", "map_stats", "map_status", "tsdf_profile",
                  "tsdf_profile_read", "tsdf_set_launch_config", "tsdf_step_create", "tsdf_step_run",
                  "tsdf_step_destroy", "tsdf_set_sensor_model", "tsdf_sensor_maps", "tsdf_sm_trainer_create",
@@ -136,7 +137,7 @@ lib = _load()
 EXPORTED = ("tsdf_default_params", "create_map", "create_map_ex", "destroy_map", "reserve", "integrate_depth",
             "integrate_depth_noalloc",
             "integrate_depth_views", "integrate_range",
-            "query_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
+            "query_blocks", "insert_blocks", "query_tsdf", "query_touched", "map_stats", "map_status",
             "tsdf_strerror", "tsdf_profile", "tsdf_profile_read", "tsdf_set_launch_config",
             "tsdf_step_create", "tsdf_step_run", "tsdf_step_destroy", "tsdf_set_sensor_model", "tsdf_sensor_maps",
             "tsdf_sm_trainer_create", "tsdf_sm_trainer_destroy", "tsdf_sm_loss_grad", "tsdf_sm_adam")
@@ -367,6 +368,50 @@ class TsdfMap:
             _check(lib.query_tsdf(self._h, C.c_void_p(blocks.data_ptr()), n, C.c_void_p(d.data_ptr()),
                                   C.c_void_p(w.data_ptr()), C.c_void_p(_stream_ptr(stream))), "query_tsdf")
         return d, w
+
+    def insert_blocks(self, blocks: torch.Tensor, dist: torch.Tensor, weight: torch.Tensor, stream=None) -> None:
+        """Writes blocks (int32 (n, 3)) with their (n, 512) distances and
+        weights into the map (see insert_blocks in tsdf.h)."""
+        blocks = blocks.to(device="cuda", dtype=torch.int32).contiguous()
+        dist = dist.to(device="cuda", dtype=torch.float32).contiguous()
+        weight = weight.to(device="cuda", dtype=torch.float32).contiguous()
+        n = blocks.shape[0]
+        if blocks.shape != (n, 3) or dist.shape != (n, 512) or weight.shape != (n, 512):
+            raise ValueError("blocks (n, 3), dist and weight (n, 512)")
+        if n:
+            _check(lib.insert_blocks(self._h, C.c_void_p(blocks.data_ptr()), n, C.c_void_p(dist.data_ptr()),
+                                     C.c_void_p(weight.data_ptr()), C.c_void_p(_stream_ptr(stream))),
+                   "insert_blocks")
+            (stream or torch.cuda.current_stream()).synchronize()   # the buffers may go once this returns
+
+    def save(self, path: str) -> None:
+        """Writes the map's parameters, blocks and voxels to an .npz file
+        (plain arrays: numpy.load with its default allow_pickle=False reads it)."""
+        b, d, w = self.sorted_state()
+        p = self.params
+        np.savez(path, format_version=np.int32(1), voxel_size_m=np.float32(p.voxel_size_m),
+                 truncation_vox=np.float32(p.truncation_vox), max_weight=np.float32(p.max_weight),
+                 max_range_m=np.float32(p.max_range_m), weighting=np.int32(p.weighting), storage=np.int32(p.storage),
+                 allocation=np.int32(p.allocation), blocks=b, dist=d, weight=w)
+
+    @classmethod
+    def load(cls, path: str, block_capacity: Optional[int] = None) -> "TsdfMap":
+        """A map restored from save(): same parameters, blocks and voxel
+        values; block_capacity defaults to twice the saved blocks (at least
+        2^16)."""
+        z = np.load(path)
+        if int(z["format_version"]) != 1:
+            raise ValueError("unknown map file version")
+        names = {v: k for k, v in WEIGHTINGS.items()}
+        stor = {v: k for k, v in STORAGES.items()}
+        alloc = {v: k for k, v in ALLOCATIONS.items()}
+        n = int(z["blocks"].shape[0])
+        m = cls(float(z["voxel_size_m"]), float(z["truncation_vox"]), max_weight=float(z["max_weight"]),
+                max_range=float(z["max_range_m"]), weighting=names[int(z["weighting"])],
+                storage=stor[int(z["storage"])], allocation=alloc[int(z["allocation"])],
+                block_capacity=block_capacity or max(1 << 16, 2 * n))
+        m.insert_blocks(torch.as_tensor(z["blocks"]), torch.as_tensor(z["dist"]), torch.as_tensor(z["weight"]))
+        return m
 
     def query_touched(self, stream=None) -> torch.Tensor:
         """Blocks updated by the last integrate_depth call, int32 (n, 3), unordered."""

@@ -82,6 +82,9 @@ int main(void)
         EXPECT(integrate_depth(m, (const float *)16, 1 << 20, 1 << 20, K, I, NULL), TSDF_EINVAL);
         EXPECT(integrate_depth_noalloc(m, NULL, 640, 480, K, I, NULL), TSDF_EINVAL);
         EXPECT(integrate_depth_noalloc(m, (const float *)16, 640, 480, K, shear, NULL), TSDF_EINVAL);
+        EXPECT(insert_blocks(m, NULL, 1, (const float *)16, (const float *)16, NULL), TSDF_EINVAL);
+        EXPECT(insert_blocks(m, (const int32_t *)16, -1, (const float *)16, (const float *)16, NULL), TSDF_EINVAL);
+        EXPECT(insert_blocks(m, NULL, 0, NULL, NULL, NULL), TSDF_OK);
         EXPECT(destroy_map(m), TSDF_OK);
     } else if (cs != TSDF_EDEVICE && cs != TSDF_ENOMEM) {
         fprintf(stderr, "create_map_ex returned %d\n", cs);
@@ -93,6 +96,7 @@ int main(void)
     EXPECT(reserve(NULL, 1024), TSDF_EINVAL);
     EXPECT(integrate_depth(NULL, (const float *)16, 4, 4, K, I, NULL), TSDF_EINVAL);
     EXPECT(integrate_depth_noalloc(NULL, (const float *)16, 4, 4, K, I, NULL), TSDF_EINVAL);
+    EXPECT(insert_blocks(NULL, (const int32_t *)16, 1, (const float *)16, (const float *)16, NULL), TSDF_EINVAL);
     tsdf_lidar_model lm = {1024, 64, 0.0f, 6.2831855f, 1.2915f, 0.5585f, 0.2f, 25.0f};
     EXPECT(integrate_range(NULL, (const float *)16, &lm, I, NULL), TSDF_EINVAL);
     EXPECT(integrate_range(NULL, (const float *)16, NULL, I, NULL), TSDF_EINVAL);
