@@ -1330,7 +1330,9 @@ int query_blocks(tsdf_map *m, int32_t *out_xyz_dev, long long capacity, long lon
         size_t bytes = m->q_temp_bytes;
         e = sort_keys(m->dm.slot_keys, m->q_sorted, n, m->q_temp, &bytes, s);
     }
-    // slots reserved but never published keep kEmptyKey, which sorts last
+    // every slot below the count holds its key; the count of valid keys is
+    // taken on the device all the same (an unwritten slot keeps kEmptyKey,
+    // which sorts last)
     if (e == hipSuccess)
         e = launch_count_valid(m->q_sorted, n, m->q_count, s);
     if (e == hipSuccess && capacity > 0)

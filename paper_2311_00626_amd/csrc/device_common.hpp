@@ -121,7 +121,8 @@ __device__ __forceinline__ ProbeWindow load_first_window(const DeviceMap &dm, ui
 }
 
 // Pool slot behind a hit found at window position f_hit (waits, bounded, for
-// a value that is published after its key).
+// a value that is published after its key), or kInvalidSlot when the key was
+// inserted after the pool ran out (its inserter recorded the overflow).
 __device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t start, uint32_t base, int f_hit,
                                                uint32_t v)
 {
@@ -136,7 +137,7 @@ __device__ __forceinline__ uint32_t slot_of_hit(const DeviceMap &dm, uint32_t st
         }
         slot = (uint32_t)wave_bcast((int)slot);
     }
-    return slot;
+    return slot == kNoSlot ? kInvalidSlot : slot;
 }
 
 // Read-only lookup of `key` (wave-uniform) starting from its preloaded first
@@ -163,12 +164,14 @@ __device__ inline uint32_t find_block(const DeviceMap &dm, unsigned long long ke
 // Wave-cooperative find-or-insert of `key` (wave-uniform).  Lanes look at the
 // slots of one window at a time, in probe order; the first slot that holds
 // the key or is empty decides.  w is the key's first window, loaded ahead of
-// time.  Returns the pool slot, or kInvalidSlot after recording an overflow.
+// time.  An insert claims the empty slot for the key first and only then
+// reserves a pool slot, so waves racing on one key take exactly one pool
+// slot between them; the losers find the key and wait for its published
+// value.  Returns the pool slot, or kInvalidSlot after recording an overflow.
 __device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long long key, uint32_t start, ProbeWindow w)
 {
     const int lane = lane_id();
     const uint32_t mask = dm.hash_mask;
-    uint32_t fresh = kInvalidSlot;   // pool slot reserved for an insert (wave-uniform)
     uint32_t base = 0, width = kBucketSlots;
     bool loaded = true;
     while (base <= mask) {
@@ -187,30 +190,20 @@ __device__ inline uint32_t find_or_insert(const DeviceMap &dm, unsigned long lon
             continue;
         }
         const uint32_t at = (start + base + (uint32_t)f_free) & mask;
-        int won = 0;
-        if (lane == 0) {
-            if (fresh == kInvalidSlot) {
-                fresh = atomicAdd(&dm.counters[kNumBlocks], 1u);
-                if (fresh >= dm.block_cap) {
-                    atomicOr(&dm.counters[kErrorBits], kErrPoolFull);
-                    fresh = kInvalidSlot;
-                }
+        uint32_t got = kInvalidSlot;   // lane 0: the value it published for `at`
+        if (lane == 0 && atomicCAS(&dm.keys[at], kEmptyKey, key) == kEmptyKey) {
+            got = atomicAdd(&dm.counters[kNumBlocks], 1u);
+            if (got < dm.block_cap) {
+                dm.slot_keys[got] = key;
+            } else {
+                atomicOr(&dm.counters[kErrorBits], kErrPoolFull);
+                got = kNoSlot;   // waiters on this key stop waiting and skip it
             }
-            if (fresh != kInvalidSlot) {
-                const unsigned long long prev = atomicCAS(&dm.keys[at], kEmptyKey, key);
-                if (prev == kEmptyKey) {
-                    dm.slot_keys[fresh] = key;
-                    __hip_atomic_store(&dm.vals[at], fresh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    won = 1;
-                }
-            }
+            __hip_atomic_store(&dm.vals[at], got, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        fresh = (uint32_t)wave_bcast((int)fresh);
-        won = wave_bcast(won);
-        if (fresh == kInvalidSlot)
-            return kInvalidSlot;
-        if (won == 1)
-            return fresh;
+        got = (uint32_t)wave_bcast((int)got);
+        if (got != kInvalidSlot)
+            return got == kNoSlot ? kInvalidSlot : got;
         // the slot went to another key (or to this key from elsewhere): reload this window
     }
     if (lane == 0)

@@ -8,6 +8,7 @@ namespace tsdf {
 
 constexpr unsigned long long kEmptyKey = ~0ull;     // hash slot never used
 constexpr uint32_t kInvalidSlot = 0xFFFFFFFFu;      // hash value not yet published
+constexpr uint32_t kNoSlot = 0xFFFFFFFEu;           // key inserted when the pool was full: no block
 constexpr int kBlockVoxels = 512;                   // 8 x 8 x 8 voxels per block (§IV-A)
 constexpr int kKeyBits = 21;                        // bits per packed block coordinate
 constexpr int kKeyOffset = 1 << 20;                 // block coordinate bias
