@@ -152,6 +152,57 @@ def test_overflow_is_sticky_with_hash_full_bit(cluttered):
     assert {tuple(b) for b in ob if tuple(b) not in early} == {tuple(gb[k]) for k in late}
 
 
+def test_pool_overflow_with_room_in_hash_then_reserve(cluttered):
+    """Pool of 256 blocks, hash of 4096 slots: the pool runs out first.  A key
+    inserted after that stays in the hash with no block (its later lookups,
+    in the same frame and the next, skip it), the pool-full bit is set, and
+    queries see exactly the 256 pooled blocks (a key without a block reads as
+    absent).  reserve() rehashes only the pooled blocks, clears the error, and
+    blocks first allocated after the overflow are exact against the oracle."""
+    import oracle
+    from paper_2311_00626_amd.tsdf import EFULL, ERR_HASH_FULL, ERR_POOL_FULL
+    w, frames = cluttered
+    say("case: cluttered room, pool 256 < hash 4096, two frames (pool overflow), reserve, four more frames")
+    gm = gpu_map(w.params, block_capacity=256, hash_capacity=4096)
+    om = oracle.OracleMap.from_params(w.params)
+    for d, T in zip(frames[:2], w.poses[:2]):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), w.camera.K, T)
+        om.integrate(d, w.camera.K, T)
+    assert gm.status() == EFULL
+    st = gm.full_stats()
+    say({"error_bits": st["error_bits"], "blocks": st["blocks"]})
+    assert st["error_bits"] & ERR_POOL_FULL and not st["error_bits"] & ERR_HASH_FULL
+    assert st["blocks"] == 256
+    held = gm.query_blocks().cpu().numpy()
+    assert len(held) == 256
+    early = {tuple(b) for b in om.blocks()}
+    assert {tuple(b) for b in held} <= early
+    # blocks the oracle holds but the pool does not: absent (zeros), although
+    # some of their keys sit in the hash without a block
+    missing = np.array(sorted(early - {tuple(b) for b in held}), dtype=np.int32)
+    assert len(missing) > 0
+    d_m, w_m = gm.query_tsdf(torch.as_tensor(missing, device="cuda"))
+    assert torch.all(d_m == 0) and torch.all(w_m == 0)
+
+    gm.reserve(4096)
+    assert gm.status() == 0 and gm.full_stats()["error_bits"] == 0
+    assert len(gm.query_blocks()) == 256
+    for d, T in zip(frames[2:6], w.poses[2:6]):
+        gm.integrate_depth(torch.as_tensor(d, device="cuda"), w.camera.K, T)
+        om.integrate(d, w.camera.K, T)
+    assert gm.status() == 0
+    gb, gd, gw = gm.sorted_state()
+    ob, od, ow = om.sorted_state()
+    assert {tuple(b) for b in gb} <= {tuple(b) for b in ob}
+    oi = {tuple(b): k for k, b in enumerate(ob)}
+    late = [k for k, b in enumerate(gb) if tuple(b) not in early]
+    assert len(late) > 0
+    for k in late:
+        j = oi[tuple(gb[k])]
+        assert np.array_equal(gw[k].astype(np.float64), ow[j]) and np.array_equal(gd[k].astype(np.float64), od[j])
+    assert {tuple(b) for b in ob if tuple(b) not in early} == {tuple(gb[k]) for k in late}
+
+
 def test_reserve_keeps_map_bit_identical(cluttered):
     """N frames into a pool they just fit, reserve (the hash grows too),
     more frames: the map equals the oracle's and a map created large, and
