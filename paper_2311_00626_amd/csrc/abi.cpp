@@ -289,6 +289,46 @@ void map_consts(const tsdf_map *m, double max_extent, double max_zfar, MapConsts
     mc.margin_z = (float)(0.5 * (double)m->p.voxel_size_m + 1e-5 * (1.0 + max_extent + max_zfar));
 }
 
+// The culling tests of a single pinhole view (lane_block_in_pinhole and
+// lane_block_footprint_pinhole, with their margins) as linear functions of
+// the lattice-relative block index, in binary64 (PinholeCull).  A frustum
+// plane a x + b y + c z + d of the camera frame is largest over a block at
+// the corner the positive components of its edge terms pick: its value at
+// the block's lower corner plus the positive parts of those terms.
+void pinhole_cull(const CameraView &cv, const MapConsts &mc, const Lattice &lat, PinholeCull &pc)
+{
+    const double e = 8.0 * (double)mc.vs;
+    double cam[12];
+    for (int a = 0; a < 3; ++a) {
+        double c = (double)cv.t[a];
+        for (int k = 0; k < 3; ++k) {
+            cam[4 * a + k] = e * (double)cv.R[3 * a + k];
+            c += e * (double)cv.R[3 * a + k] * (double)lat.lat_min[k];
+        }
+        cam[4 * a + 3] = c;
+    }
+    const double fx = cv.fx, fy = cv.fy, cx = cv.cx, cy = cv.cy;
+    const double planes[6][5] = {{fx, 0.0, cx, 0.0, cv.margin_u},
+                                 {-fx, 0.0, (double)cv.width_f - cx, 0.0, cv.margin_u},
+                                 {0.0, fy, cy, 0.0, cv.margin_v},
+                                 {0.0, -fy, (double)cv.height_f - cy, 0.0, cv.margin_v},
+                                 {0.0, 0.0, 1.0, 0.0, mc.margin_z},
+                                 {0.0, 0.0, -1.0, (double)cv.zfar, mc.margin_z}};
+    for (int q = 0; q < 6; ++q) {
+        const double *P = planes[q];
+        double t = P[0] * cam[3] + P[1] * cam[7] + P[2] * cam[11] + P[3] + P[4];
+        for (int k = 0; k < 3; ++k) {
+            const double A = P[0] * cam[k] + P[1] * cam[4 + k] + P[2] * cam[8 + k];
+            pc.plane[4 * q + k] = (float)A;
+            t += std::max(0.0, A);
+        }
+        pc.plane[4 * q + 3] = (float)t;
+    }
+    for (int k = 0; k < 12; ++k)
+        pc.cam[k] = (float)cam[k];
+    pc.valid = 1;
+}
+
 // Block lattice of a world box, widened by one voxel.
 int lattice_of(const tsdf_map *m, const double lo[3], const double hi[3], Lattice &lat)
 {
@@ -305,6 +345,7 @@ int lattice_of(const tsdf_map *m, const double lo[3], const double hi[3], Lattic
     lat.n_lat = (long long)lat.lat_dim[0] * lat.lat_dim[1] * lat.lat_dim[2];
     if (lat.n_lat >= (1ll << 31))
         return TSDF_EINVAL;
+    set_lattice_divisors(lat);
     return TSDF_OK;
 }
 
@@ -590,6 +631,7 @@ hipError_t prepare_walk(tsdf_map *m, FrameArgs &fa, const float T[16], hipStream
     lat.n_lat = (long long)lat.lat_dim[0] * lat.lat_dim[1] * lat.lat_dim[2];
     if (lat.n_lat >= (1ll << 31))
         return hipErrorInvalidValue;
+    set_lattice_divisors(lat);
     if (!m->walk_marks || m->walk_cap < lat.n_lat) {
         if (m->walk_marks) {
             hipError_t e = hipDeviceSynchronize();   // earlier launches may still read the old marks
@@ -810,6 +852,8 @@ int integrate_depth_call(tsdf_map *m, const float *depth_dev, int width, int hei
     int groups = schedule(m, fa.lat);
     if (walk)
         fa.lat.partitions = 1;    // every lattice entry is read by exactly one thread
+    else
+        pinhole_cull(fa.cam, fa.mc, fa.lat, fa.pc);
     if (fa.lat.cand) {
         groups = (int)std::max<long long>(kPartitions, (m->launch.max_groups > 0 ? m->launch.max_groups : m->max_groups) /
                                                            kPartitions * kPartitions);

@@ -529,6 +529,76 @@ __device__ __forceinline__ uint32_t spread_position(uint32_t g, uint32_t groups)
     return (g % (uint32_t)kXcds) * (groups / (uint32_t)kXcds) + g / (uint32_t)kXcds;
 }
 
+// Block indices of lattice entry lb (x fastest), with the lattice's
+// multiply-shift divisors in place of two integer divisions.
+__device__ __forceinline__ uint32_t lattice_div(uint32_t n, uint32_t m, int s)
+{
+    return (uint32_t)(((unsigned long long)n * (unsigned long long)m) >> s);
+}
+__device__ __forceinline__ void lattice_block(const Lattice &lat, uint32_t lb, int &bx, int &by, int &bz)
+{
+    const uint32_t rest = lattice_div(lb, lat.div_m[0], lat.div_s[0]);
+    const uint32_t z = lattice_div(rest, lat.div_m[1], lat.div_s[1]);
+    bx = lat.lat_min[0] + (int)(lb - rest * (uint32_t)lat.lat_dim[0]);
+    by = lat.lat_min[1] + (int)(rest - z * (uint32_t)lat.lat_dim[1]);
+    bz = lat.lat_min[2] + (int)z;
+}
+
+// Culling of block b against a single pinhole view with the host's
+// precomputed planes (PinholeCull): the same tests as lane_block_in_pinhole
+// and lane_block_footprint_pinhole, evaluated in lattice-relative
+// coordinates with fused multiply-adds; the margins are those of the
+// CameraView tests, far above the binary32 error of either evaluation.
+__device__ __forceinline__ bool lane_block_pinhole_precomputed(const PinholeCull &pc, const CameraView &cv,
+                                                               const MapConsts &mc, const Lattice &lat, int bx,
+                                                               int by, int bz)
+{
+    const float lx = (float)(bx - lat.lat_min[0]), ly = (float)(by - lat.lat_min[1]), lz = (float)(bz - lat.lat_min[2]);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (fmaf(pc.plane[4 * q], lx, fmaf(pc.plane[4 * q + 1], ly, fmaf(pc.plane[4 * q + 2], lz, pc.plane[4 * q + 3]))) <
+            0.0f)
+            return false;
+    if (!cv.tiles)
+        return true;
+    float cx0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        cx0[a] = fmaf(pc.cam[4 * a], lx, fmaf(pc.cam[4 * a + 1], ly, fmaf(pc.cam[4 * a + 2], lz, pc.cam[4 * a + 3])));
+    float zmin = 3.0e38f, umin = 3.0e38f, umax = -3.0e38f, vmin = 3.0e38f, vmax = -3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float p[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = cx0[a];
+            if (c & 1)
+                p[a] += pc.cam[4 * a];
+            if (c & 2)
+                p[a] += pc.cam[4 * a + 1];
+            if (c & 4)
+                p[a] += pc.cam[4 * a + 2];
+        }
+        const float r = __builtin_amdgcn_rcpf(fmaxf(p[2], 1e-3f));
+        const float u = fmaf(cv.fx, p[0] * r, cv.cx);
+        const float v = fmaf(cv.fy, p[1] * r, cv.cy);
+        zmin = fminf(zmin, p[2]);
+        umin = fminf(umin, u);
+        umax = fmaxf(umax, u);
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+    }
+    if (!(zmin > 1e-3f))
+        return true;
+    const float lo_u = fmaxf(umin - 2.0f, 0.0f), hi_u = fminf(umax + 2.0f, cv.width_f - 1.0f);
+    const float lo_v = fmaxf(vmin - 2.0f, 0.0f), hi_v = fminf(vmax + 2.0f, cv.height_f - 1.0f);
+    if (hi_u < lo_u || hi_v < lo_v)
+        return false;
+    bool ok;
+    const float dm = footprint_max(cv, (int)lo_u, (int)hi_u, (int)lo_v, (int)hi_v, ok);
+    return !ok || zmin <= dm + mc.eps + mc.margin_z;
+}
+
 // Walks the launch's lattice for this wave.  With P = lat.partitions bands,
 // the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
 // P = 8) scans all chunks; each lane bands and culls one block of a chunk of
@@ -541,18 +611,17 @@ __device__ __forceinline__ uint32_t spread_position(uint32_t g, uint32_t groups)
 // marked it (the mark is cleared for the next frame: each entry is read by
 // exactly one thread).
 __device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const CameraView *cams, int n_views,
-                                                      const MapConsts &mc, uint32_t lb, int &bx, int &by, int &bz)
+                                                      const MapConsts &mc, uint32_t lb, int &bx, int &by, int &bz,
+                                                      const PinholeCull *pc)
 {
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-    const uint32_t rest = lb / dim_x;
-    bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-    by = lat.lat_min[1] + (int)(rest % dim_y);
-    bz = lat.lat_min[2] + (int)(rest / dim_y);
+    lattice_block(lat, lb, bx, by, bz);
     uint32_t vmask = 0;
     if (cams[0].dda_marks) {
         vmask = cams[0].dda_marks[lb] ? 1u : 0u;
         if (vmask)
             cams[0].dda_marks[lb] = 0;
+    } else if (pc) {
+        vmask = lane_block_pinhole_precomputed(*pc, cams[0], mc, lat, bx, by, bz) ? 1u : 0u;
     } else {
         for (int v = 0; v < n_views; ++v)
             if (lane_block_in_view(cams[v], mc, bx, by, bz))
@@ -570,7 +639,7 @@ __device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const 
 // waves take them in turn, so no wave handles more than its share.
 template <class Body>
 __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const CameraView *cams, int n_views,
-                                                   const MapConsts &mc, Body &&body)
+                                                   const MapConsts &mc, Body &&body, const PinholeCull *pc)
 {
     constexpr uint32_t kThreads = 64u * (uint32_t)kWavesPerGroup;
     __shared__ uint32_t s_lb[kThreads], s_vm[kThreads];
@@ -587,7 +656,7 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
         uint32_t vmask = 0;
         int bx = 0, by = 0, bz = 0;
         if (item < n_lat)
-            vmask = lattice_candidate(lat, cams, n_views, mc, (uint32_t)item, bx, by, bz);
+            vmask = lattice_candidate(lat, cams, n_views, mc, (uint32_t)item, bx, by, bz, pc);
         const unsigned long long keep = __ballot(vmask != 0);
         if (lane == 0)
             s_count[wave] = (uint32_t)__popcll(keep);
@@ -606,10 +675,9 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
         for (uint32_t i = (uint32_t)wave; i < total; i += (uint32_t)kWavesPerGroup) {
             const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_lb[i]);
             const uint32_t svm = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_vm[i]);
-            const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
-            const uint32_t rest = lb / dim_x;
-            body(lat.lat_min[0] + (int)(lb - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
-                 lat.lat_min[2] + (int)(rest / dim_y), svm);
+            int sbx, sby, sbz;
+            lattice_block(lat, lb, sbx, sby, sbz);
+            body(sbx, sby, sbz, svm);
         }
         __syncthreads();   // s_lb, s_vm and s_count are rewritten by the next pass
     }
@@ -617,10 +685,10 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
 
 template <class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
-                                             const MapConsts &mc, Body &&body)
+                                             const MapConsts &mc, Body &&body, const PinholeCull *pc = nullptr)
 {
     if (lat.group_scan) {
-        scan_lattice_group(lat, cams, n_views, mc, body);
+        scan_lattice_group(lat, cams, n_views, mc, body, pc);
         return;
     }
     const int lane = lane_id();
@@ -634,7 +702,6 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
     const uint32_t waves_pp = groups_pp * (uint32_t)kWavesPerGroup;
     const uint32_t wave_pp = (threadIdx.x >> 6) * groups_pp + spread_position(blockIdx.x / P, groups_pp);
     const uint32_t chunk = (uint32_t)lat.chunk;
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     const uint32_t n_lat = (uint32_t)lat.n_lat;
     const uint32_t n_chunks = (n_lat + chunk - 1) / chunk;
     for (uint32_t c = wave_pp; c < n_chunks; c += waves_pp) {
@@ -642,10 +709,7 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
         uint32_t vmask = 0;
         int bx = 0, by = 0, bz = 0;
         if ((uint32_t)lane < chunk && lb < n_lat) {
-            const uint32_t rest = lb / dim_x;
-            bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-            by = lat.lat_min[1] + (int)(rest % dim_y);
-            bz = lat.lat_min[2] + (int)(rest / dim_y);
+            lattice_block(lat, lb, bx, by, bz);
             if (cams[0].dda_marks) {
                 // ray-walk allocation: the walk decides; the mark is cleared
                 // for the next frame (each entry is read by one lane only)
@@ -653,10 +717,14 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
                 if (vmask)
                     cams[0].dda_marks[lb] = 0;
             }
-            else if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part)
-                for (int v = 0; v < n_views; ++v)
-                    if (lane_block_in_view(cams[v], mc, bx, by, bz))
-                        vmask |= 1u << v;
+            else if (P == 1 || block_band(cams, n_views, mc, bx, by, bz, lb) == part) {
+                if (pc)
+                    vmask = lane_block_pinhole_precomputed(*pc, cams[0], mc, lat, bx, by, bz) ? 1u : 0u;
+                else
+                    for (int v = 0; v < n_views; ++v)
+                        if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                            vmask |= 1u << v;
+            }
         }
         unsigned long long todo = __ballot(vmask != 0);
         while (todo) {
@@ -1152,7 +1220,8 @@ __host__ __device__ __forceinline__ int cull_lanes_per_block(int n_views)
 // is a chain of cold scalar loads on every CU.
 template <bool LANE_VIEWS>
 __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice &lat, const CameraView *cams,
-                                             int n_views, const MapConsts &mc, int parity)
+                                             int n_views, const MapConsts &mc, int parity,
+                                             const PinholeCull *pc = nullptr)
 {
     constexpr int kWaves = kCullThreads / 64;
     __shared__ uint32_t s_count[kWaves];
@@ -1176,7 +1245,6 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
     const unsigned long long group_mask = lanes == 64 ? ~0ull : ((1ull << lanes) - 1ull);
     const unsigned long long n_lat = (unsigned long long)lat.n_lat;
     const unsigned long long n_work = n_lat << shift;
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     const unsigned long long stride = (unsigned long long)gridDim.x * (unsigned long long)kCullThreads;
     // the loop runs the same number of times in every thread of the workgroup
     for (unsigned long long base = (unsigned long long)blockIdx.x * kCullThreads; base < n_work; base += stride) {
@@ -1184,12 +1252,13 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
         const uint32_t lb = (uint32_t)(item >> shift);
         uint32_t vmask = 0;
         if (item < n_work && view < n_views) {
-            const uint32_t rest = lb / dim_x;
-            const int bx = lat.lat_min[0] + (int)(lb - rest * dim_x);
-            const int by = lat.lat_min[1] + (int)(rest % dim_y);
-            const int bz = lat.lat_min[2] + (int)(rest / dim_y);
+            int bx, by, bz;
+            lattice_block(lat, lb, bx, by, bz);
             if constexpr (LANE_VIEWS) {
-                vmask = lane_block_in_view(s_cams[view], mc, bx, by, bz) ? 1u : 0u;
+                vmask = (pc ? lane_block_pinhole_precomputed(*pc, s_cams[view], mc, lat, bx, by, bz)
+                            : lane_block_in_view(s_cams[view], mc, bx, by, bz))
+                            ? 1u
+                            : 0u;
             } else {
                 for (int v = 0; v < n_views; ++v)
                     if (lane_block_in_view(s_cams[v], mc, bx, by, bz))
@@ -1229,16 +1298,15 @@ __device__ __forceinline__ void scan_list(const DeviceMap &dm, const Lattice &la
                                          __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)n);
     const uint32_t waves = gridDim.x * (uint32_t)kWavesPerGroup;
-    const uint32_t dim_x = (uint32_t)lat.lat_dim[0], dim_y = (uint32_t)lat.lat_dim[1];
     // consecutive entries go to different workgroups of one XCD, as in scan_lattice
     for (uint32_t i = (threadIdx.x >> 6) * gridDim.x + spread_position(blockIdx.x, gridDim.x); i < count;
          i += waves) {
         const uint2 e = lat.cand[i];
         const uint32_t lb = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.x);
         const uint32_t vmask = (uint32_t)__builtin_amdgcn_readfirstlane((int)e.y);
-        const uint32_t rest = lb / dim_x;
-        body(lat.lat_min[0] + (int)(lb - rest * dim_x), lat.lat_min[1] + (int)(rest % dim_y),
-             lat.lat_min[2] + (int)(rest / dim_y), vmask);
+        int bx, by, bz;
+        lattice_block(lat, lb, bx, by, bz);
+        body(bx, by, bz, vmask);
     }
 }
 

@@ -105,7 +105,7 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
     if constexpr (LIST)
         scan_list(dm, fa.lat, parity, block);
     else
-        scan_lattice(fa.lat, &fa.cam, 1, fa.mc, block);
+        scan_lattice(fa.lat, &fa.cam, 1, fa.mc, block);   // (the plane table's kernel arguments cost the walk more than it saves)
     // one write per update: a single view updates a voxel at most once
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates, n_cands);
 }
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kern
 
 __global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
 {
-    cull_to_list<true>(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity);
+    cull_to_list<true>(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity, fa.pc.valid ? &fa.pc : nullptr);
 }
 
 }  // namespace

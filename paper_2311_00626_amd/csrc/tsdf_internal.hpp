@@ -148,6 +148,14 @@ struct Lattice {
     int lat_min[3];         // inclusive lower corner (block indices)
     int lat_dim[3];
     long long n_lat;        // lat_dim[0] * lat_dim[1] * lat_dim[2], below 2^31
+    // Division of a lattice index n < 2^31 by lat_dim[a] (a = 0, 1) as a
+    // multiply and shift: n / d = (n * div_m[a]) >> div_s[a] with
+    // s = 31 + ceil(log2 d) and m = ceil(2^s / d) < 2^32.  Exact: writing
+    // m d = 2^s + e with 0 <= e < d, n m / 2^s = n / d + n e / (d 2^s), and
+    // n e < 2^31 d <= 2^s, so the added term is below 1 / d and the floor
+    // does not move (set_lattice_divisors).
+    uint32_t div_m[2];
+    int div_s[2];
     int chunk;              // 1 .. kMaxChunk
     int partitions;         // 1 or kPartitions ownership bands
     int group_scan;         // nonzero: the walk culls and compacts per workgroup (scan_lattice_group)
@@ -157,11 +165,39 @@ struct Lattice {
     uint2 *cand;
 };
 
+// Multiply-shift divisors of a lattice's x and y extents (Lattice::div_m).
+inline void set_lattice_divisors(Lattice &lat)
+{
+    for (int a = 0; a < 2; ++a) {
+        const unsigned long long d = (unsigned long long)lat.lat_dim[a];
+        int c = 0;
+        while ((1ull << c) < d)
+            ++c;
+        const int s = 31 + c;
+        lat.div_s[a] = s;
+        lat.div_m[a] = (uint32_t)(((1ull << s) + d - 1) / d);
+    }
+}
+
+// Culling of a single pinhole view in lattice-relative block coordinates
+// l = b - lat_min (set by the host once the launch's lattice is known).  The
+// camera-frame corner of block l is cam[4a] l_x + cam[4a+1] l_y + cam[4a+2]
+// l_z + cam[4a+3] on axis a (the first three columns are the camera-frame
+// block edges), and each frustum plane's largest value over the block, plus
+// its margin, is plane[4p] l_x + plane[4p+1] l_y + plane[4p+2] l_z +
+// plane[4p+3]: the block is culled where that is negative.
+struct PinholeCull {
+    float cam[12];
+    float plane[24];
+    int valid;              // 0: the launch culls through CameraView alone
+};
+
 // Arguments of a single-frame launch.
 struct FrameArgs {
     CameraView cam;
     MapConsts mc;
     Lattice lat;
+    PinholeCull pc;
     int parity;             // launch counter & 1: selects this launch's touched counters
     int stage;              // nonzero: stage block depth footprints in LDS (pinhole, fixed weighting)
 };
