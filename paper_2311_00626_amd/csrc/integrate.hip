@@ -75,9 +75,6 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
         const uint32_t slot = find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
             return;
-        uint32_t at = 0;
-        if constexpr (!LIST)
-            at = reserve_touched(dm, parity, sub);
 
         // lanes whose voxel is not updated use an out-of-range offset: no load, no store
         using IO = VoxelIO<STORAGE>;
@@ -89,6 +86,12 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
             off[s] = ((hit >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange;
             dw[s] = IO::load(blk, off[s]);
         }
+        // the touched entry is reserved behind the voxel loads: its result is
+        // taken into a scalar register as soon as it is awaited, and awaited
+        // ahead of the loads it would put a full round trip before them
+        uint32_t at = 0;
+        if constexpr (!LIST)
+            at = reserve_touched(dm, parity, sub);
 #pragma unroll
         for (int s = 0; s < 8; ++s)
             dw[s] = fuse(dw[s], xs[s], ws[s], fa.mc.w_max);

@@ -111,15 +111,16 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
         const uint32_t slot = found != kInvalidSlot ? found : find_or_insert(dm, key, h, w0);
         if (slot == kInvalidSlot)
             return;
-        uint32_t at = 0;
-        if constexpr (!LIST)
-            at = reserve_touched(dm, parity, sub);
         const __amdgpu_buffer_rsrc_t blk = block_rsrc<STORAGE>(dm, slot);
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
             n_writes += (uint32_t)__popcll(__ballot((any >> s) & 1u));
             IO::store(blk, ((any >> s) & 1u) ? IO::kBytes * (uint32_t)(64 * s + lane) : kOutOfRange, dw[s]);
         }
+        // reserved behind the stores: its result is awaited where it is taken
+        uint32_t at = 0;
+        if constexpr (!LIST)
+            at = reserve_touched(dm, parity, sub);
         if constexpr (LIST)
             push_touched(dm, parity, sub, slot, pending, n_pending);
         else

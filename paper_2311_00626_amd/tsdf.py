@@ -259,6 +259,7 @@ class TsdfMap:
         self._K = (C.c_float * 4)()
         self._K_addr = C.addressof(self._K)
         self._T = np.empty(16, np.float32)
+        self._T44 = self._T.reshape(4, 4)     # the same memory: a 4x4 pose is copied in one step
         self._T_addr = self._T.ctypes.data
 
     @classmethod
@@ -291,13 +292,20 @@ class TsdfMap:
         self.block_capacity = max(self.block_capacity, int(block_capacity))
 
     # -- integration --------------------------------------------------------
+    def _set_pose(self, T) -> None:
+        """Copies a 4x4 (or 16-element) row-major pose into the call's binary32 buffer."""
+        if getattr(T, "shape", None) == (4, 4):
+            self._T44[...] = T
+        else:
+            self._T[:] = np.reshape(T, 16)
+
     def integrate_depth(self, depth: torch.Tensor, K: Sequence[float], T_world_cam,
                         stream: Optional[torch.cuda.Stream] = None) -> None:
         if not (depth.is_cuda and depth.dtype == torch.float32 and depth.dim() == 2
                 and depth.is_contiguous()):
             raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
         self._K[:] = K
-        self._T[:] = np.reshape(T_world_cam, 16)
+        self._set_pose(T_world_cam)
         H, W = depth.shape
         st = lib.integrate_depth(self._h, depth.data_ptr(), W, H, self._K_addr, self._T_addr,
                                  _stream_ptr(stream, depth.get_device()))
@@ -311,7 +319,7 @@ class TsdfMap:
                 and depth.is_contiguous()):
             raise ValueError("depth must be a contiguous 2-D float32 CUDA tensor")
         self._K[:] = K
-        self._T[:] = np.reshape(T_world_cam, 16)
+        self._set_pose(T_world_cam)
         H, W = depth.shape
         st = lib.integrate_depth_noalloc(self._h, depth.data_ptr(), W, H, self._K_addr, self._T_addr,
                                          _stream_ptr(stream, depth.get_device()))
@@ -325,7 +333,7 @@ class TsdfMap:
         lm = lidar_struct(lidar)
         if (lm.height, lm.width) != tuple(rng.shape):
             raise ValueError("range image shape does not match the LiDAR model")
-        self._T[:] = np.reshape(T_world_sensor, 16)
+        self._set_pose(T_world_sensor)
         _check(lib.integrate_range(self._h, rng.data_ptr(), C.byref(lm), self._T_addr, _stream_ptr(stream)),
                "integrate_range")
 
