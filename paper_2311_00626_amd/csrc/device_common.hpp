@@ -473,10 +473,12 @@ __device__ __forceinline__ bool lane_block_footprint_spherical(const CameraView 
 }
 
 // Culling of block (bx, by, bz) against one view: false only when no voxel
-// of the block can be updated.
+// of the block can be updated.  PINHOLE: the view is known to be a pinhole
+// camera (single-view pinhole launches compile no spherical test).
+template <bool PINHOLE = false>
 __device__ __forceinline__ bool lane_block_in_view(const CameraView &cv, const MapConsts &mc, int bx, int by, int bz)
 {
-    if (cv.model == kModelSpherical) {
+    if (!PINHOLE && cv.model == kModelSpherical) {
         if (!lane_block_in_spherical(cv, mc, bx, by, bz))
             return false;
         return !cv.tiles || lane_block_footprint_spherical(cv, mc, bx, by, bz);
@@ -610,6 +612,7 @@ __device__ __forceinline__ bool lane_block_pinhole_precomputed(const PinholeCull
 // culling it survives (bit v), or, with ray-walk marks, 1 when the walk
 // marked it (the mark is cleared for the next frame: each entry is read by
 // exactly one thread).
+template <bool PINHOLE>
 __device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const CameraView *cams, int n_views,
                                                       const MapConsts &mc, uint32_t lb, int &bx, int &by, int &bz,
                                                       const PinholeCull *pc)
@@ -624,7 +627,7 @@ __device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const 
         vmask = lane_block_pinhole_precomputed(*pc, cams[0], mc, lat, bx, by, bz) ? 1u : 0u;
     } else {
         for (int v = 0; v < n_views; ++v)
-            if (lane_block_in_view(cams[v], mc, bx, by, bz))
+            if (lane_block_in_view<PINHOLE>(cams[v], mc, bx, by, bz))
                 vmask |= 1u << v;
     }
     return vmask;
@@ -637,7 +640,7 @@ __device__ __forceinline__ uint32_t lattice_candidate(const Lattice &lat, const 
 // that every workgroup draws about the same number of surviving blocks from
 // anywhere in the frame; a workgroup collects its survivors in LDS and its
 // waves take them in turn, so no wave handles more than its share.
-template <class Body>
+template <bool PINHOLE, class Body>
 __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const CameraView *cams, int n_views,
                                                    const MapConsts &mc, Body &&body, const PinholeCull *pc)
 {
@@ -656,7 +659,7 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
         uint32_t vmask = 0;
         int bx = 0, by = 0, bz = 0;
         if (item < n_lat)
-            vmask = lattice_candidate(lat, cams, n_views, mc, (uint32_t)item, bx, by, bz, pc);
+            vmask = lattice_candidate<PINHOLE>(lat, cams, n_views, mc, (uint32_t)item, bx, by, bz, pc);
         const unsigned long long keep = __ballot(vmask != 0);
         if (lane == 0)
             s_count[wave] = (uint32_t)__popcll(keep);
@@ -683,12 +686,12 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
     }
 }
 
-template <class Body>
+template <bool PINHOLE = false, class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body, const PinholeCull *pc = nullptr)
 {
     if (lat.group_scan) {
-        scan_lattice_group(lat, cams, n_views, mc, body, pc);
+        scan_lattice_group<PINHOLE>(lat, cams, n_views, mc, body, pc);
         return;
     }
     const int lane = lane_id();
@@ -722,7 +725,7 @@ __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraVie
                     vmask = lane_block_pinhole_precomputed(*pc, cams[0], mc, lat, bx, by, bz) ? 1u : 0u;
                 else
                     for (int v = 0; v < n_views; ++v)
-                        if (lane_block_in_view(cams[v], mc, bx, by, bz))
+                        if (lane_block_in_view<PINHOLE>(cams[v], mc, bx, by, bz))
                             vmask |= 1u << v;
             }
         }
@@ -1218,7 +1221,7 @@ __host__ __device__ __forceinline__ int cull_lanes_per_block(int n_views)
 // prefix over its waves' counts), and the views' parameters are copied into
 // LDS once per workgroup: read view after view from the argument block, each
 // is a chain of cold scalar loads on every CU.
-template <bool LANE_VIEWS>
+template <bool LANE_VIEWS, bool PINHOLE = false>
 __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice &lat, const CameraView *cams,
                                              int n_views, const MapConsts &mc, int parity,
                                              const PinholeCull *pc = nullptr)
@@ -1255,10 +1258,10 @@ __device__ __forceinline__ void cull_to_list(const DeviceMap &dm, const Lattice 
             int bx, by, bz;
             lattice_block(lat, lb, bx, by, bz);
             if constexpr (LANE_VIEWS) {
-                vmask = (pc ? lane_block_pinhole_precomputed(*pc, s_cams[view], mc, lat, bx, by, bz)
-                            : lane_block_in_view(s_cams[view], mc, bx, by, bz))
-                            ? 1u
-                            : 0u;
+                if constexpr (PINHOLE)   // a single pinhole view with its precomputed planes
+                    vmask = lane_block_pinhole_precomputed(*pc, s_cams[view], mc, lat, bx, by, bz) ? 1u : 0u;
+                else
+                    vmask = lane_block_in_view(s_cams[view], mc, bx, by, bz) ? 1u : 0u;
             } else {
                 for (int v = 0; v < n_views; ++v)
                     if (lane_block_in_view(s_cams[v], mc, bx, by, bz))

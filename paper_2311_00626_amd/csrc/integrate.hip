@@ -108,7 +108,7 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
     if constexpr (LIST)
         scan_list(dm, fa.lat, parity, block);
     else
-        scan_lattice(fa.lat, &fa.cam, 1, fa.mc, block);   // (the plane table's kernel arguments cost the walk more than it saves)
+        scan_lattice<SPHERICAL == 0>(fa.lat, &fa.cam, 1, fa.mc, block);   // (the plane table's kernel arguments cost the walk more than it saves)
     // one write per update: a single view updates a voxel at most once
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates, n_cands);
 }
@@ -131,9 +131,12 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void integrate_depth_list_kern
     integrate_depth_body<WEIGHTING, STORAGE, SPHERICAL, true, STAGE>(dm, fa);
 }
 
+// PINHOLE: a pinhole view with the host's precomputed planes (fa.pc); else
+// any single view through its CameraView.
+template <bool PINHOLE>
 __global__ __launch_bounds__(kCullThreads) void cull_frame_kernel(DeviceMap dm, FrameArgs fa)
 {
-    cull_to_list<true>(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity, fa.pc.valid ? &fa.pc : nullptr);
+    cull_to_list<true, PINHOLE>(dm, fa.lat, &fa.cam, 1, fa.mc, fa.parity, &fa.pc);
 }
 
 }  // namespace
@@ -142,7 +145,10 @@ hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream
 {
     const unsigned groups = (unsigned)std::max<long long>(
         1, std::min<long long>((fa.lat.n_lat + kCullThreads - 1) / kCullThreads, kCullGroups));  // one view: one lane per block
-    hipLaunchKernelGGL(cull_frame_kernel, dim3(groups), dim3(kCullThreads), 0, stream, dm, fa);
+    if (fa.pc.valid)
+        hipLaunchKernelGGL(cull_frame_kernel<true>, dim3(groups), dim3(kCullThreads), 0, stream, dm, fa);
+    else
+        hipLaunchKernelGGL(cull_frame_kernel<false>, dim3(groups), dim3(kCullThreads), 0, stream, dm, fa);
     return hipGetLastError();
 }
 
