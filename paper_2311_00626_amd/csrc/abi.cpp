@@ -606,8 +606,15 @@ hipError_t prepare_compaction(tsdf_map *m, Lattice &lat, int n_views, const Call
         (void)hipFree(m->cand);
         m->cand = nullptr;
         m->cand_cap = 0;
-        const long long cap = std::max<long long>(lat.n_lat, 1ll << 18);
+        // twice the lattice: a growing lattice reallocates (a device
+        // synchronisation and a free in the middle of the stream) rarely
+        long long cap = std::max<long long>(2 * lat.n_lat, 1ll << 18);
         hipError_t e = hipMalloc((void **)&m->cand, sizeof(uint2) * (size_t)cap);
+        if (e == hipErrorOutOfMemory) {   // no room for the headroom: the lattice itself
+            (void)hipGetLastError();
+            cap = lat.n_lat;
+            e = hipMalloc((void **)&m->cand, sizeof(uint2) * (size_t)cap);
+        }
         if (e != hipSuccess)
             return e;
         m->cand_cap = cap;
@@ -641,8 +648,13 @@ hipError_t prepare_walk(tsdf_map *m, FrameArgs &fa, const float T[16], hipStream
         (void)hipFree(m->walk_marks);
         m->walk_marks = nullptr;
         m->walk_cap = 0;
-        const long long cap = std::max<long long>(lat.n_lat, 1ll << 20);
+        long long cap = std::max<long long>(2 * lat.n_lat, 1ll << 20);   // as the candidate list
         hipError_t e = hipMalloc((void **)&m->walk_marks, (size_t)cap);
+        if (e == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            cap = lat.n_lat;
+            e = hipMalloc((void **)&m->walk_marks, (size_t)cap);
+        }
         if (e == hipSuccess)
             e = launch_fill_u8(m->walk_marks, cap, s);   // from here on the integration kernel keeps it zero
         if (e != hipSuccess)
