@@ -1184,10 +1184,13 @@ __device__ __forceinline__ void finish_group(const DeviceMap &dm, int parity, in
     write_touched(dm, sub, s_base + before, pending, n_pending);
 }
 
-// Start of a launch: the previous launch (stream-ordered, complete) counted
-// into the other parity; fold its touched count into the running total and
-// clear it for the next launch.
-__device__ __forceinline__ void begin_launch(const DeviceMap &dm, int parity)
+// Once per launch (workgroup 0, after its own work): the previous launch
+// (stream-ordered, complete) counted into the other parity; fold its touched
+// count into the running total and clear it for the next launch.  Nothing in
+// this launch touches the other parity's counters, so where in the launch
+// this runs does not matter; at the end its returning atomics delay no
+// workgroup's first pass.
+__device__ __forceinline__ void fold_previous_launch(const DeviceMap &dm, int parity)
 {
     if (blockIdx.x == 0 && threadIdx.x < kSubLists) {
         const uint32_t prev = atomicExch(&dm.counters[touched_counter(parity ^ 1, (int)threadIdx.x)], 0u);

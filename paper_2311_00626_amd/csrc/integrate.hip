@@ -45,7 +45,6 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
     const int ly = lane >> 3;
     const int parity = fa.parity;
     const int sub = (int)(blockIdx.x % kSubLists);
-    begin_launch(dm, parity);
 
     uint32_t pending = kInvalidSlot;   // wave-local touched list: lane i holds entry i
     int n_pending = 0;                 // wave-uniform
@@ -111,6 +110,7 @@ __device__ __forceinline__ void integrate_depth_body(const DeviceMap &dm, const 
         scan_lattice<SPHERICAL == 0>(fa.lat, &fa.cam, 1, fa.mc, block);   // (the plane table's kernel arguments cost the walk more than it saves)
     // one write per update: a single view updates a voxel at most once
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_updates, n_cands);
+    fold_previous_launch(dm, parity);
 }
 
 // With binary32 storage five waves per SIMD cap the walking kernel at 96

@@ -39,7 +39,6 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     const int ly = lane >> 3;
     const int parity = va.parity;
     const int sub = (int)(blockIdx.x % kSubLists);
-    begin_launch(dm, parity);
 
     uint32_t pending = kInvalidSlot;
     int n_pending = 0;
@@ -131,6 +130,7 @@ __device__ __forceinline__ void integrate_views_body(const DeviceMap &dm, const 
     else
         scan_lattice(va.lat, va.cam, va.n_views, va.mc, block);
     finish_group<kWavesPerGroup>(dm, parity, sub, pending, n_pending, n_updates, n_writes, n_cands);
+    fold_previous_launch(dm, parity);
 }
 
 // Arguments passed by value (eager launches).  Four waves per SIMD (two
