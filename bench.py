@@ -40,11 +40,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _code_of(text: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines: what
+    the compiler sees, up to layout.  String and character literals are kept
+    whole, so a '//' inside one is not taken for a comment."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def kernel_source_hash() -> str:
+    """Hash of the measured kernels' code (comments and blank lines left out,
+    so a comment edit keeps the committed counter profile valid)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(_code_of(f.read()).encode("utf-8"))
     return h.hexdigest()[:16]
 
 

@@ -601,13 +601,6 @@ __device__ __forceinline__ bool lane_block_pinhole_precomputed(const PinholeCull
     return !ok || zmin <= dm + mc.eps + mc.margin_z;
 }
 
-// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
-// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
-// P = 8) scans all chunks; each lane bands and culls one block of a chunk of
-// lat.chunk consecutive lattice blocks, and the surviving blocks of this
-// partition are handed to body(bx, by, bz, view_mask) one at a time
-// (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
-// lattice block is a candidate exactly when marked.
 // Lattice block lb of the launch: its block indices and the views whose
 // culling it survives (bit v), or, with ray-walk marks, 1 when the walk
 // marked it (the mark is cleared for the next frame: each entry is read by
@@ -686,6 +679,15 @@ __device__ __forceinline__ void scan_lattice_group(const Lattice &lat, const Cam
     }
 }
 
+// Walks the launch's lattice for this wave.  With P = lat.partitions bands,
+// the partition of the workgroup (blockIdx.x mod P, the XCD it runs on when
+// P = 8) scans all chunks; each lane bands and culls one block of a chunk of
+// lat.chunk consecutive lattice blocks, and the surviving blocks of this
+// partition are handed to body(bx, by, bz, view_mask) one at a time
+// (wave-uniform).  Waves never wait for each other.  With ray-walk marks, a
+// lattice block is a candidate exactly when marked.  lat.group_scan selects
+// the workgroup-compacted walk (scan_lattice_group).  pc: the host's plane
+// table for a single pinhole view, or null for the CameraView tests.
 template <bool PINHOLE = false, class Body>
 __device__ __forceinline__ void scan_lattice(const Lattice &lat, const CameraView *cams, int n_views,
                                              const MapConsts &mc, Body &&body, const PinholeCull *pc = nullptr)
