@@ -369,8 +369,8 @@ typedef struct {
     int max_groups, partitions, chunk, footprint;
     int compaction;   /* TSDF_COMPACT_*: a cull pre-pass compacts the surviving blocks into a list
                          that the integration kernel deals out evenly to its waves (automatic once
-                         lattice blocks x views reach 16384, or for integrate_depth once the
-                         lattice reaches 131072 blocks; one band only, not with ray-walk
+                         lattice blocks x views reach 16384, or for integrate_depth and
+                         integrate_range once the lattice reaches 131072 blocks; one band only, not with ray-walk
                          allocation) */
     int staging;      /* TSDF_STAGE_* */
 } tsdf_launch_config;
