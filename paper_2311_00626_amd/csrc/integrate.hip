@@ -152,67 +152,86 @@ hipError_t launch_cull_frame(const DeviceMap &dm, const FrameArgs &fa, hipStream
     return hipGetLastError();
 }
 
-template <int WEIGHTING>
-static void launch_depth_staged(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
+// Workgroups of 64 * kWavesPerGroup threads that one compute unit keeps
+// resident for kernel k (1 if the runtime cannot say).
+static int resident_per_cu(const void *k)
 {
-    if (fa.lat.cand) {
-        if (dm.storage == 1)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 1, 0, true>), grid, block, 0,
-                               stream, dm, fa);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 0, 0, true>), grid, block, 0,
-                               stream, dm, fa);
-    } else if (dm.storage == 1) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 1, 0, true>), grid, block, 0, stream,
-                           dm, fa);
-    } else {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 0, 0, true>), grid, block, 0, stream,
-                           dm, fa);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64 * kWavesPerGroup, 0) != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        n = 1;
     }
+    return n;
+}
+
+// The compacted launch: `groups` workgroups, or with fill_cus > 0 every
+// workgroup that fill_cus compute units keep resident (a multiple of
+// kPartitions for spread_position, at least kPartitions).
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool STAGE>
+static void launch_list(const DeviceMap &dm, const FrameArgs &fa, int groups, int fill_cus, hipStream_t stream)
+{
+    if (fill_cus > 0) {
+        static const int per_cu =
+            resident_per_cu(reinterpret_cast<const void *>(&integrate_depth_list_kernel<WEIGHTING, STORAGE, SPHERICAL, STAGE>));
+        groups = std::max(kPartitions, per_cu * fill_cus / kPartitions * kPartitions);
+    }
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, STORAGE, SPHERICAL, STAGE>),
+                       dim3((unsigned)groups), dim3(64 * kWavesPerGroup), 0, stream, dm, fa);
+}
+
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool STAGE>
+static void launch_walk(const DeviceMap &dm, const FrameArgs &fa, int groups, hipStream_t stream)
+{
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, STORAGE, SPHERICAL, STAGE>),
+                       dim3((unsigned)groups), dim3(64 * kWavesPerGroup), 0, stream, dm, fa);
+}
+
+template <int WEIGHTING, int STORAGE, int SPHERICAL, bool STAGE>
+static void launch_form(const DeviceMap &dm, const FrameArgs &fa, int groups, int fill_cus, hipStream_t stream)
+{
+    if (fa.lat.cand)
+        launch_list<WEIGHTING, STORAGE, SPHERICAL, STAGE>(dm, fa, groups, fill_cus, stream);
+    else
+        launch_walk<WEIGHTING, STORAGE, SPHERICAL, STAGE>(dm, fa, groups, stream);
 }
 
 template <int WEIGHTING, int SPHERICAL>
-static void launch_depth_storage(const DeviceMap &dm, const FrameArgs &fa, dim3 grid, dim3 block, hipStream_t stream)
+static void launch_depth_storage(const DeviceMap &dm, const FrameArgs &fa, int groups, int fill_cus,
+                                 hipStream_t stream)
 {
-    if (SPHERICAL == 0 && WEIGHTING != kWeightLearned && fa.stage) {
-        launch_depth_staged<WEIGHTING == kWeightLearned ? kWeightConstant : WEIGHTING>(dm, fa, grid, block, stream);
-        return;
+    if constexpr (SPHERICAL == 0 && WEIGHTING != kWeightLearned) {
+        if (fa.stage) {
+            if (dm.storage == 1)
+                launch_form<WEIGHTING, 1, 0, true>(dm, fa, groups, fill_cus, stream);
+            else
+                launch_form<WEIGHTING, 0, 0, true>(dm, fa, groups, fill_cus, stream);
+            return;
+        }
     }
-    if (fa.lat.cand) {
-        if (dm.storage == 1)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0,
-                               stream, dm, fa);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_list_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0,
-                               stream, dm, fa);
-    } else if (dm.storage == 1) {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 1, SPHERICAL>), grid, block, 0, stream,
-                           dm, fa);
-    } else {
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(integrate_depth_kernel<WEIGHTING, 0, SPHERICAL>), grid, block, 0, stream,
-                           dm, fa);
-    }
+    if (dm.storage == 1)
+        launch_form<WEIGHTING, 1, SPHERICAL, false>(dm, fa, groups, fill_cus, stream);
+    else
+        launch_form<WEIGHTING, 0, SPHERICAL, false>(dm, fa, groups, fill_cus, stream);
 }
 
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
-                                  hipStream_t stream)
+                                  hipStream_t stream, int fill_cus)
 {
-    const dim3 grid((unsigned)groups), block(64 * kWavesPerGroup);
     const bool spherical = fa.cam.model == kModelSpherical;
     if (weighting == kWeightLearned) {
         if (spherical || !fa.cam.sm_maps)
             return hipErrorInvalidValue;
-        launch_depth_storage<kWeightLearned, 0>(dm, fa, grid, block, stream);
+        launch_depth_storage<kWeightLearned, 0>(dm, fa, groups, fill_cus, stream);
     } else if (weighting == kWeightDropoff) {
         if (spherical)
-            launch_depth_storage<kWeightDropoff, 1>(dm, fa, grid, block, stream);
+            launch_depth_storage<kWeightDropoff, 1>(dm, fa, groups, fill_cus, stream);
         else
-            launch_depth_storage<kWeightDropoff, 0>(dm, fa, grid, block, stream);
+            launch_depth_storage<kWeightDropoff, 0>(dm, fa, groups, fill_cus, stream);
     } else {
         if (spherical)
-            launch_depth_storage<kWeightConstant, 1>(dm, fa, grid, block, stream);
+            launch_depth_storage<kWeightConstant, 1>(dm, fa, groups, fill_cus, stream);
         else
-            launch_depth_storage<kWeightConstant, 0>(dm, fa, grid, block, stream);
+            launch_depth_storage<kWeightConstant, 0>(dm, fa, groups, fill_cus, stream);
     }
     return hipGetLastError();
 }

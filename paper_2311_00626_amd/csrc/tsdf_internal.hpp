@@ -251,8 +251,11 @@ __host__ __device__ inline uint32_t probe_start(unsigned long long key, uint32_t
 constexpr unsigned long long kNoKey = ~0ull - 1ull;
 
 // Kernel launchers (integrate.hip, query.hip).
+// groups: workgroups of the launch; with fill_cus > 0 a compacted launch
+// (fa.lat.cand) instead takes as many as its list kernel keeps resident on
+// fill_cus compute units (a multiple of kPartitions, at least kPartitions).
 hipError_t launch_integrate_depth(const DeviceMap &dm, const FrameArgs &fa, int weighting, int groups,
-                                  hipStream_t stream);
+                                  hipStream_t stream, int fill_cus = 0);
 hipError_t launch_integrate_views(const DeviceMap &dm, const ViewsArgs &va, int weighting, int groups,
                                   hipStream_t stream);
 // list: the compacted form (the cull kernel ran before it), else the lattice walk
