@@ -29,18 +29,22 @@ def states_equal(a, b):
 def test_compaction_box_room(vs, n, storage):
     import oracle
     w = synth.box_room_sequence(vs, n_frames=n)
-    say(f"case: compacted launches, box room {int(vs * 100)} cm, {n} frames, {storage}, never/always/auto")
+    say(f"case: compacted launches, box room {int(vs * 100)} cm, {n} frames, {storage}, never/always/auto"
+        " and always on an explicit 512-workgroup grid")
     frames = w.frames(device="cuda")
     dev = [torch.as_tensor(f, device="cuda") for f in frames]
     maps = {}
-    for mode in ("never", "always", "auto"):
+    # "always" runs the list kernel on every resident workgroup; "always_512"
+    # on the explicit grid of the lattice walk
+    for mode, groups in (("never", 0), ("always", 0), ("auto", 0), ("always_512", 512)):
         m = gpu_map(w.params, block_capacity=1 << 17, storage=storage)
-        m.set_launch_config(compaction=mode)
+        m.set_launch_config(max_groups=groups, compaction=mode.split("_")[0])
         for d, T in zip(dev, w.poses):
             m.integrate_depth(d, w.camera.K, T)
         maps[mode] = m
     torch.cuda.synchronize()
     assert states_equal(maps["never"], maps["always"]) and states_equal(maps["never"], maps["auto"])
+    assert states_equal(maps["never"], maps["always_512"])
     s_never, s_always = maps["never"].full_stats(), maps["always"].full_stats()
     assert s_never["voxel_updates"] == s_always["voxel_updates"]
     assert s_never["touched_blocks"] == s_always["touched_blocks"]
