@@ -329,7 +329,9 @@ TSDF_API const char *tsdf_strerror(int status);
 /* Launch shape of the integration kernels (tuning only: results do not
  * depend on it).  Zero fields mean automatic.
  *   max_groups  cap on workgroups of 512 threads per launch (rounded down to a
- *               multiple of 8), 1 .. 65536;
+ *               multiple of 8), 1 .. 65536; automatic: 512, and for a compacted
+ *               integrate_depth launch every workgroup its list kernel keeps
+ *               resident on the device (768 on MI355X);
  *   partitions  1, or 8: blocks are owned by 8 image bands, one per XCD, so
  *               each XCD reads about 1/8 of every depth image (lattice-walk
  *               launches; more than 1 turns compaction off);
