@@ -130,27 +130,38 @@ __device__ __forceinline__ ConstParams as_constant(const float *p)
 }
 
 // Forward through the hidden layers with parameters P (binary32 multiply-adds
-// in index order); h1, h2 are the bfloat16 activations, o the binary32 outputs.
+// in index order from the bias; hidden activations rounded to bfloat16), to
+// the binary32 outputs o.  Layer 2 takes the first layer's units four at a
+// time as they are computed: each second-layer sum still adds its terms in
+// index order, so the result is that of evaluating the layers one after the
+// other, with 4 instead of 32 first-layer activations held in registers.
 template <typename Params>
-__device__ __forceinline__ void sm_forward(Params P, const float x[kSmIn], float h1[kSmHidden],
-                                           float h2[kSmHidden], float o[kSmOut])
+__device__ __forceinline__ void sm_forward(Params P, const float x[kSmIn], float o[kSmOut])
 {
-#pragma unroll 4
-    for (int k = 0; k < kSmHidden; ++k) {
-        float a = P[kSmB1 + k];
+    float h2[kSmHidden];
 #pragma unroll
-        for (int m = 0; m < kSmIn; ++m)
-            a = __builtin_fmaf(P[kSmW1 + kSmIn * k + m], x[m], a);
-        h1[k] = round_bf16(a > 0.0f ? a : 0.0f);
-    }
-#pragma unroll 4
-    for (int k = 0; k < kSmHidden; ++k) {
-        float a = P[kSmB2 + k];
+    for (int k = 0; k < kSmHidden; ++k)
+        h2[k] = P[kSmB2 + k];
+#pragma unroll 1
+    for (int m0 = 0; m0 < kSmHidden; m0 += 4) {
+        float h1[4];
 #pragma unroll
-        for (int m = 0; m < kSmHidden; ++m)
-            a = __builtin_fmaf(P[kSmW2 + kSmHidden * k + m], h1[m], a);
-        h2[k] = round_bf16(a > 0.0f ? a : 0.0f);
+        for (int q = 0; q < 4; ++q) {
+            float a = P[kSmB1 + m0 + q];
+#pragma unroll
+            for (int i = 0; i < kSmIn; ++i)
+                a = __builtin_fmaf(P[kSmW1 + kSmIn * (m0 + q) + i], x[i], a);
+            h1[q] = round_bf16(a > 0.0f ? a : 0.0f);
+        }
+#pragma unroll
+        for (int k = 0; k < kSmHidden; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                h2[k] = __builtin_fmaf(P[kSmW2 + kSmHidden * k + m0 + q], h1[q], h2[k]);
     }
+#pragma unroll
+    for (int k = 0; k < kSmHidden; ++k)
+        h2[k] = round_bf16(h2[k] > 0.0f ? h2[k] : 0.0f);
 #pragma unroll
     for (int c = 0; c < kSmOut; ++c) {
         float a = P[kSmB3 + c];
@@ -282,9 +293,9 @@ __global__ __launch_bounds__(kMapThreads) void sm_maps_kernel(SmView v, float vs
             out[p] = make_float2(0.0f, 0.0f);
             continue;
         }
-        float x[kSmIn], h1[kSmHidden], h2[kSmHidden], o[kSmOut];
+        float x[kSmIn], o[kSmOut];
         sm_inputs(v, i, j, d, x);
-        sm_forward(P, x, h1, h2, o);
+        sm_forward(P, x, o);
         out[p] = sm_outputs(o, vs);
     }
 }
